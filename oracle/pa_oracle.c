@@ -1,0 +1,444 @@
+/*
+ * pa_oracle.c -- plain CPU oracle for population-annealing Max-Cut.
+ *
+ * TEST INFRASTRUCTURE ONLY. Nothing in the product library links, loads or
+ * calls this file; only the tests, the smoke check and the CPU-baseline leg
+ * of the benchmark do. It shares no code with the device path.
+ *
+ * What it computes (paper: "New Best-Known Max-Cut Solution for the G63
+ * Instance in the G-Set Benchmark", arXiv 2510.21105):
+ *
+ *   Section 1, eq. (1): the Max-Cut objective
+ *       cut(x) = 1/2 * sum_{i<j} w_ij (1 - x_i x_j),  x in {-1,+1}^N.
+ *   Section 2: Max-Cut is the ground state of the Ising energy with
+ *       antiferromagnetic couplings J_ij = -w_ij, i.e. of
+ *       E(x) = sum_{i<j} w_ij x_i x_j,  so  cut = (W_tot - E) / 2,
+ *       W_tot = sum_{i<j} w_ij.
+ *   Abstract and section 3: the solver is population annealing Monte Carlo
+ *   with adaptive control of stochasticity and periodic non-local moves.
+ *   The paper names these parts but does not define them; the concrete
+ *   integer-exact definitions below are the readings this project adopts
+ *   (each listed in the design notes):
+ *
+ *   RNG   Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11). A draw for
+ *         (tag, sweep s, step k, node i, replica r) is word (r & 3) of
+ *         Philox(key = (lo32 seed, hi32 seed),
+ *                ctr = (i, s | tag << 16, k, (r >> 2) | inst << 16)).
+ *         Tags: 0 Metropolis, 1 initial spins, 2 resampling, 3 non-local.
+ *   Init  x_i^r = +1 if bit 0 of draw(1, 0, 0, i, r) is set, else -1.
+ *   Sweep for each replica, for t = 0..N-1, i = order[t]:
+ *         h_i = sum_j w_ij x_j, m = -x_i h_i (the flip changes E by 2m);
+ *         accept iff m <= 0, or draw(0, s, k, i, r) < T_k,l(m) where
+ *         T(beta, m) = floor(2^32 * exp(-(beta * 2m))) computed in FP64 and
+ *         beta = beta_k * gamma^l (gamma^l by l successive FP64 products).
+ *         On accept x_i <- -x_i, E += 2m and h_j += 2 w_ij x_i(new).
+ *         After every sweep: if min_r E_r < best_E the best becomes
+ *         (E, lowest such r, k, s) with a copy of its configuration.
+ *   NL    every nl_period steps (after the sweeps of steps k with
+ *         (k+1) % nl_period == 0): for p = 0..R/2-1 take replicas a = p,
+ *         b = p + R/2; D = {i : x_i^a != x_i^b} in node order; if D is not
+ *         empty pick D[floor(draw(3, 0, k, 0, p) * |D| / 2^32)] and flip, in
+ *         both replicas, the connected component of that node in the
+ *         subgraph induced by D (Houdayer's cluster move). Then the best
+ *         check runs again (recorded with sweep index S).
+ *   AS    if the best improved during step k: level l <- 0, stall <- 0;
+ *         else stall += 1, and if stall >= P_stall and
+ *         frozen_inv * (uphill accepts) < (uphill attempts) during step k
+ *         then l <- min(l + 1, l_max) and stall <- 0. The level applies to the
+ *         next step's sweeps. Uphill means m > 0.
+ *   Resample (steps k < K-1): dbeta = beta_{k+1} - beta_k (FP64);
+ *         E_min = min_r E_r; W_r = floor(2^32 * exp(-(dbeta * (E_r - E_min))));
+ *         S = sum W (uint64); C_r = W_0 + ... + W_r;
+ *         U = word0 | word1 << 32 of Philox(ctr = (0, 2 << 16, k, inst << 16));
+ *         u = floor(U * S / 2^64); f(c) = 0 if R*c <= u else
+ *         ceil((R*c - u) / S); replica r gets n_r = f(C_r) - f(C_{r-1})
+ *         copies in new slots f(C_{r-1}) .. f(C_r)-1 (systematic resampling,
+ *         population size fixed at R).
+ *
+ * Parity status: Philox is pinned by the published known-answer vectors;
+ * eq. (1), brute force, closed forms, the Boltzmann distribution, the
+ * free-energy estimator and the resampling/cluster invariants pin the rest.
+ * The adaptive-stochasticity rule has no definition in the paper and is
+ * "parity unpinned" beyond its range invariant.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#include <math.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORACLE_STAT_FIELDS 8
+/* stats record per step k (int64):
+ *   0 E_min   (after sweeps and NL, before resampling)
+ *   1 E_sum
+ *   2 uphill attempts (m > 0) during the step's sweeps
+ *   3 uphill accepts
+ *   4 AS level used by the step's sweeps
+ *   5 best_E after the step
+ *   6 number of replicas with at least one copy (0 on the last step)
+ *   7 weight sum S (0 on the last step)                                  */
+
+/* ------------------------------------------------------------------ RNG */
+
+void oracle_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+        uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+        uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        uint32_t n1 = (uint32_t)p1;
+        uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        uint32_t n3 = (uint32_t)p0;
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+uint32_t oracle_draw(uint64_t seed, uint32_t inst, uint32_t tag, uint32_t sweep,
+                     uint32_t step, uint32_t node, uint32_t replica)
+{
+    uint32_t key[2] = { (uint32_t)seed, (uint32_t)(seed >> 32) };
+    uint32_t ctr[4] = { node, sweep | (tag << 16), step, (replica >> 2) | (inst << 16) };
+    uint32_t out[4];
+    oracle_philox4x32_10(ctr, key, out);
+    return out[replica & 3];
+}
+
+uint64_t oracle_resample_uniform(uint64_t seed, uint32_t inst, uint32_t step)
+{
+    uint32_t key[2] = { (uint32_t)seed, (uint32_t)(seed >> 32) };
+    uint32_t ctr[4] = { 0u, 2u << 16, step, inst << 16 };
+    uint32_t out[4];
+    oracle_philox4x32_10(ctr, key, out);
+    return (uint64_t)out[0] | ((uint64_t)out[1] << 32);
+}
+
+/* --------------------------------------------------------------- tables */
+
+/* floor(2^32 * exp(-(beta * 2m))) */
+uint64_t oracle_threshold(double beta, int32_t m)
+{
+    double x = exp(-(beta * (double)(2 * m)));
+    return (uint64_t)floor(ldexp(x, 32));
+}
+
+/* floor(2^32 * exp(-(dbeta * n))) */
+uint64_t oracle_weight(double dbeta, int64_t n)
+{
+    double x = exp(-(dbeta * (double)n));
+    return (uint64_t)floor(ldexp(x, 32));
+}
+
+double oracle_level_beta(double beta, double gamma, int32_t level)
+{
+    double g = 1.0;
+    for (int32_t l = 0; l < level; ++l) g = g * gamma;
+    return beta * g;
+}
+
+/* ---------------------------------------------------------------- graph */
+
+int64_t oracle_energy(int32_t n, const int32_t *row_ptr, const int32_t *col,
+                      const int8_t *w, const int8_t *x)
+{
+    int64_t twice = 0;
+    for (int32_t i = 0; i < n; ++i)
+        for (int32_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e)
+            twice += (int64_t)w[e] * x[i] * x[col[e]];
+    return twice / 2;
+}
+
+static void fields(int32_t n, const int32_t *row_ptr, const int32_t *col,
+                   const int8_t *w, const int8_t *x, int32_t *h)
+{
+    for (int32_t i = 0; i < n; ++i) {
+        int32_t s = 0;
+        for (int32_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) s += w[e] * x[col[e]];
+        h[i] = s;
+    }
+}
+
+/* ----------------------------------------------------------- resampling */
+
+static uint64_t sys_f(uint64_t c, uint64_t R, uint64_t u, uint64_t S)
+{
+    uint64_t rc = R * c;
+    if (rc <= u) return 0;
+    return (rc - u + S - 1) / S;
+}
+
+/* Copy counts n[0..R-1] of systematic resampling with weights W and the
+ * 64-bit uniform U. Returns the weight sum S (0 if all weights are 0). */
+uint64_t oracle_resample_counts(int32_t R, const uint64_t *W, uint64_t U, int32_t *n_out)
+{
+    uint64_t S = 0;
+    for (int32_t r = 0; r < R; ++r) S += W[r];
+    if (S == 0) return 0;
+    uint64_t u = (uint64_t)(((unsigned __int128)U * S) >> 64);
+    uint64_t C = 0, prev = 0;
+    for (int32_t r = 0; r < R; ++r) {
+        C += W[r];
+        uint64_t f = sys_f(C, (uint64_t)R, u, S);
+        n_out[r] = (int32_t)(f - prev);
+        prev = f;
+    }
+    return S;
+}
+
+/* ------------------------------------------------------ non-local move */
+
+/* Houdayer cluster move on one pair. xa, xb are modified in place.
+ * in_cluster (n bytes, may be NULL) receives 1 for flipped nodes.
+ * Returns the cluster size (0 when the replicas agree everywhere). */
+int32_t oracle_icm_pair(int32_t n, const int32_t *row_ptr, const int32_t *col,
+                        int8_t *xa, int8_t *xb, uint32_t draw, uint8_t *in_cluster)
+{
+    if (n <= 0) return 0;
+    int32_t nd = 0;
+    for (int32_t i = 0; i < n; ++i) nd += (xa[i] != xb[i]);
+    if (in_cluster) memset(in_cluster, 0, (size_t)n);
+    if (nd == 0) return 0;
+    int64_t pick = (int64_t)(((uint64_t)draw * (uint64_t)nd) >> 32);
+    int32_t seed_node = -1;
+    for (int32_t i = 0, c = 0; i < n; ++i) {
+        if (xa[i] != xb[i]) {
+            if (c == pick) { seed_node = i; break; }
+            ++c;
+        }
+    }
+    uint8_t *seen = (uint8_t *)calloc((size_t)n, 1);
+    int32_t *queue = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    int32_t head = 0, tail = 0;
+    queue[tail++] = seed_node;
+    seen[seed_node] = 1;
+    while (head < tail) {
+        int32_t i = queue[head++];
+        for (int32_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
+            int32_t j = col[e];
+            if (!seen[j] && xa[j] != xb[j]) { seen[j] = 1; queue[tail++] = j; }
+        }
+    }
+    for (int32_t q = 0; q < tail; ++q) {
+        int32_t i = queue[q];
+        xa[i] = (int8_t)-xa[i];
+        xb[i] = (int8_t)-xb[i];
+        if (in_cluster) in_cluster[i] = 1;
+    }
+    free(seen);
+    free(queue);
+    return tail;
+}
+
+/* ------------------------------------------------------------ PA driver */
+
+static void best_check(int32_t R, int32_t n, const int32_t *E, const int8_t *x,
+                       int64_t *best, int8_t *best_x, int32_t k, int32_t s, int *improved)
+{
+    int32_t arg = -1;
+    int64_t emin = best[0];
+    for (int32_t r = 0; r < R; ++r)
+        if ((int64_t)E[r] < emin) { emin = E[r]; arg = r; }
+    if (arg >= 0) {
+        best[0] = emin; best[1] = k; best[2] = s; best[3] = arg;
+        memcpy(best_x, x + (size_t)arg * n, (size_t)n);
+        *improved = 1;
+    }
+}
+
+/*
+ * Full population-annealing run. Output pointers may be NULL.
+ *   x_init  R*n   initial population (replica-major)
+ *   x_out   R*n   final population
+ *   E_out   R     final energies
+ *   best    4     {best_E, step, sweep, replica}; step -1 = initial population
+ *   best_x  n     best configuration (+-1)
+ *   stats   K*8   per-step records (see ORACLE_STAT_FIELDS)
+ *   counts  K*R   copy counts n_r of each resampling (row K-1 unused)
+ * Returns 0, or a negative value on invalid arguments.
+ */
+int oracle_run(int32_t n, const int32_t *row_ptr, const int32_t *col, const int8_t *w,
+               int32_t K, const double *beta, int32_t S, const int32_t *order,
+               int32_t as_enable, int32_t as_stall_steps, int32_t as_max_level,
+               int32_t as_frozen_inv, double as_gamma, int32_t nl_period,
+               int32_t R, uint64_t seed, uint32_t inst, int32_t nthreads,
+               int8_t *x_init, int8_t *x_out, int32_t *E_out, int64_t *best,
+               int8_t *best_x, int64_t *stats, int32_t *counts)
+{
+    if (n <= 0 || K <= 0 || S <= 0 || S > 65535 || R <= 0 || R > 32768 || inst > 65535)
+        return -1;
+    if (nl_period > 0 && (R & 1)) return -1;
+    if (as_enable && (as_stall_steps < 1 || as_max_level < 0 || as_frozen_inv < 1)) return -1;
+    for (int32_t k = 0; k < K; ++k) {
+        if (!(beta[k] >= 0.0) || !isfinite(beta[k])) return -1;
+        if (k > 0 && beta[k] < beta[k - 1]) return -1;
+    }
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+    int32_t dmax = 0;
+    for (int32_t i = 0; i < n; ++i)
+        if (row_ptr[i + 1] - row_ptr[i] > dmax) dmax = row_ptr[i + 1] - row_ptr[i];
+    int32_t lmax = as_enable ? as_max_level : 0;
+
+    int8_t *x = (int8_t *)malloc((size_t)R * n);
+    int8_t *x2 = (int8_t *)malloc((size_t)R * n);
+    int32_t *h = (int32_t *)malloc(sizeof(int32_t) * (size_t)R * n);
+    int32_t *h2 = (int32_t *)malloc(sizeof(int32_t) * (size_t)R * n);
+    int32_t *E = (int32_t *)malloc(sizeof(int32_t) * (size_t)R);
+    int32_t *E2 = (int32_t *)malloc(sizeof(int32_t) * (size_t)R);
+    uint64_t *Wr = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)R);
+    int32_t *cnt = (int32_t *)malloc(sizeof(int32_t) * (size_t)R);
+    uint64_t *att = (uint64_t *)calloc((size_t)R, sizeof(uint64_t));
+    uint64_t *acc = (uint64_t *)calloc((size_t)R, sizeof(uint64_t));
+    uint64_t *thr = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)(dmax + 1));
+    int8_t *bx = best_x ? best_x : (int8_t *)malloc((size_t)n);
+    int64_t bbuf[4];
+    int64_t *bst = best ? best : bbuf;
+
+    /* initial population */
+    for (int32_t r = 0; r < R; ++r) {
+        int8_t *xr = x + (size_t)r * n;
+        for (int32_t i = 0; i < n; ++i)
+            xr[i] = (oracle_draw(seed, inst, 1, 0, 0, (uint32_t)i, (uint32_t)r) & 1u) ? 1 : -1;
+        fields(n, row_ptr, col, w, xr, h + (size_t)r * n);
+        E[r] = (int32_t)oracle_energy(n, row_ptr, col, w, xr);
+    }
+    if (x_init) memcpy(x_init, x, (size_t)R * n);
+    bst[0] = INT64_MAX; bst[1] = -1; bst[2] = -1; bst[3] = -1;
+    int dummy = 0;
+    best_check(R, n, E, x, bst, bx, -1, -1, &dummy);
+
+    int32_t level = 0, stall = 0;
+    for (int32_t k = 0; k < K; ++k) {
+        int improved = 0;
+        double b = oracle_level_beta(beta[k], as_gamma, level);
+        thr[0] = 0;
+        for (int32_t m = 1; m <= dmax; ++m) thr[m] = oracle_threshold(b, m);
+        (void)lmax;
+
+        for (int32_t r = 0; r < R; ++r) { att[r] = 0; acc[r] = 0; }
+        for (int32_t s = 0; s < S; ++s) {
+#pragma omp parallel for schedule(dynamic, 1)
+            for (int32_t r = 0; r < R; ++r) {
+                int8_t *xr = x + (size_t)r * n;
+                int32_t *hr = h + (size_t)r * n;
+                int32_t e = E[r];
+                uint64_t a_up = 0, c_up = 0;
+                for (int32_t t = 0; t < n; ++t) {
+                    int32_t i = order ? order[t] : t;
+                    int32_t m = -xr[i] * hr[i];
+                    int accept;
+                    if (m <= 0) {
+                        accept = 1;
+                    } else {
+                        ++a_up;
+                        accept = thr[m] != 0 &&
+                                 (uint64_t)oracle_draw(seed, inst, 0, (uint32_t)s, (uint32_t)k,
+                                                       (uint32_t)i, (uint32_t)r) < thr[m];
+                        c_up += (uint64_t)accept;
+                    }
+                    if (accept) {
+                        xr[i] = (int8_t)-xr[i];
+                        e += 2 * m;
+                        for (int32_t q = row_ptr[i]; q < row_ptr[i + 1]; ++q)
+                            hr[col[q]] += 2 * w[q] * xr[i];
+                    }
+                }
+                E[r] = e;
+                att[r] += a_up;
+                acc[r] += c_up;
+            }
+            best_check(R, n, E, x, bst, bx, k, s, &improved);
+        }
+        uint64_t att_up = 0, acc_up = 0;
+        for (int32_t r = 0; r < R; ++r) { att_up += att[r]; acc_up += acc[r]; }
+
+        if (nl_period > 0 && (k + 1) % nl_period == 0) {
+            int32_t half = R / 2;
+#pragma omp parallel for schedule(dynamic, 1)
+            for (int32_t p = 0; p < half; ++p) {
+                int8_t *xa = x + (size_t)p * n;
+                int8_t *xb = x + (size_t)(p + half) * n;
+                uint32_t d = oracle_draw(seed, inst, 3, 0, (uint32_t)k, 0, (uint32_t)p);
+                if (oracle_icm_pair(n, row_ptr, col, xa, xb, d, NULL) > 0) {
+                    E[p] = (int32_t)oracle_energy(n, row_ptr, col, w, xa);
+                    E[p + half] = (int32_t)oracle_energy(n, row_ptr, col, w, xb);
+                    fields(n, row_ptr, col, w, xa, h + (size_t)p * n);
+                    fields(n, row_ptr, col, w, xb, h + (size_t)(p + half) * n);
+                }
+            }
+            best_check(R, n, E, x, bst, bx, k, S, &improved);
+        }
+
+        int64_t emin = INT64_MAX, esum = 0;
+        for (int32_t r = 0; r < R; ++r) {
+            if (E[r] < emin) emin = E[r];
+            esum += E[r];
+        }
+        int32_t level_used = level;
+        if (as_enable) {
+            if (improved) {
+                level = 0;
+                stall = 0;
+            } else {
+                stall += 1;
+                if (stall >= as_stall_steps &&
+                    (unsigned __int128)(uint64_t)as_frozen_inv * acc_up < (unsigned __int128)att_up) {
+                    level = level + 1 < as_max_level ? level + 1 : as_max_level;
+                    stall = 0;
+                }
+            }
+        }
+
+        int64_t parents = 0;
+        uint64_t wsum = 0;
+        if (k < K - 1) {
+            double dbeta = beta[k + 1] - beta[k];
+            for (int32_t r = 0; r < R; ++r) Wr[r] = oracle_weight(dbeta, (int64_t)E[r] - emin);
+            uint64_t U = oracle_resample_uniform(seed, inst, (uint32_t)k);
+            wsum = oracle_resample_counts(R, Wr, U, cnt);
+            int32_t slot = 0;
+            for (int32_t r = 0; r < R; ++r) {
+                if (cnt[r] > 0) ++parents;
+                for (int32_t c = 0; c < cnt[r]; ++c, ++slot) {
+                    memcpy(x2 + (size_t)slot * n, x + (size_t)r * n, (size_t)n);
+                    memcpy(h2 + (size_t)slot * n, h + (size_t)r * n, sizeof(int32_t) * (size_t)n);
+                    E2[slot] = E[r];
+                }
+            }
+            if (counts) memcpy(counts + (size_t)k * R, cnt, sizeof(int32_t) * (size_t)R);
+            int8_t *tx = x; x = x2; x2 = tx;
+            int32_t *th = h; h = h2; h2 = th;
+            int32_t *te = E; E = E2; E2 = te;
+        }
+        if (stats) {
+            int64_t *st = stats + (size_t)k * ORACLE_STAT_FIELDS;
+            st[0] = emin; st[1] = esum; st[2] = (int64_t)att_up; st[3] = (int64_t)acc_up;
+            st[4] = level_used; st[5] = bst[0]; st[6] = parents; st[7] = (int64_t)wsum;
+        }
+    }
+    if (x_out) memcpy(x_out, x, (size_t)R * n);
+    if (E_out) memcpy(E_out, E, sizeof(int32_t) * (size_t)R);
+
+    free(x); free(x2); free(h); free(h2); free(E); free(E2); free(Wr); free(cnt);
+    free(att); free(acc); free(thr);
+    if (!best_x) free(bx);
+    return 0;
+}
+
+int oracle_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

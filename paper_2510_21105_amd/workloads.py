@@ -1,0 +1,206 @@
+"""Seeded synthetic inputs: graphs, annealing schedules and sweep orders.
+
+This module only *generates inputs*. It holds none of the annealing method's
+arithmetic (no Metropolis rule, no fields, no energies, no resampling), so both
+the device library and the CPU oracle can be fed from it without sharing any
+of the method's code.
+
+The G-set benchmark (random, toroidal and planar graphs, 800 to 20,000 nodes,
+binary signed or unsigned weights; paper section 1) is not available offline;
+these generators stand in for its random and toroidal families:
+
+* ``random_graph(n, m, seed)``: m distinct node pairs drawn uniformly, weight
+  +1 (the G63 shape is n=7,000, m=41,459; paper section 1).
+* ``torus(L, seed, signed)``: an L x L periodic grid, node ``r*L + c``, edges to
+  the right and downward neighbours, weights +1 or equiprobable +-1.
+
+The random stream is SplitMix64 (Steele, Lea, Flood, OOPSLA 2014), written
+out here so the inputs do not depend on a numpy version.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+_MASK64 = np.uint64(0xFFFFFFFFFFFFFFFF)
+
+
+def splitmix64(seed: int, count: int, start: int = 0) -> np.ndarray:
+    """Return ``count`` SplitMix64 outputs for states seed+(start+1..start+count)*golden."""
+    with np.errstate(over="ignore"):
+        idx = np.arange(start + 1, start + count + 1, dtype=np.uint64)
+        z = np.uint64(seed & 0xFFFFFFFFFFFFFFFF) + idx * np.uint64(0x9E3779B97F4A7C15)
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+        z = z ^ (z >> np.uint64(31))
+    return z
+
+
+def _uniform_index(words: np.ndarray, n: int) -> np.ndarray:
+    """Map 32-bit words to [0, n) by multiply-shift."""
+    return ((words.astype(np.uint64) * np.uint64(n)) >> np.uint64(32)).astype(np.int64)
+
+
+class Graph:
+    """Symmetric CSR graph with int8 weights in {-1, +1}.
+
+    ``row_ptr`` (n+1, int32), ``col`` (nnz, int32), ``w`` (nnz, int8). Every
+    undirected edge {i, j} appears twice, once in row i and once in row j,
+    with equal weight; rows are sorted by column.
+    """
+
+    def __init__(self, n: int, row_ptr: np.ndarray, col: np.ndarray, w: np.ndarray, name: str = ""):
+        self.n = int(n)
+        self.row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int32)
+        self.col = np.ascontiguousarray(col, dtype=np.int32)
+        self.w = np.ascontiguousarray(w, dtype=np.int8)
+        self.name = name
+
+    @property
+    def nnz(self) -> int:
+        return int(self.col.shape[0])
+
+    @property
+    def n_edges(self) -> int:
+        return self.nnz // 2
+
+    def edges(self):
+        """Return (i, j, w) arrays of the undirected edges with i < j."""
+        rows = np.repeat(np.arange(self.n, dtype=np.int64), np.diff(self.row_ptr))
+        keep = rows < self.col
+        return rows[keep], self.col[keep].astype(np.int64), self.w[keep].astype(np.int64)
+
+    def degrees(self) -> np.ndarray:
+        return np.diff(self.row_ptr).astype(np.int64)
+
+
+def from_edges(n: int, i, j, w=None, name: str = "") -> Graph:
+    """Build the symmetric CSR of undirected edges (i[k], j[k], w[k])."""
+    i = np.asarray(i, dtype=np.int64)
+    j = np.asarray(j, dtype=np.int64)
+    w = np.ones_like(i) if w is None else np.asarray(w, dtype=np.int64)
+    src = np.concatenate([i, j])
+    dst = np.concatenate([j, i])
+    ww = np.concatenate([w, w])
+    order = np.lexsort((dst, src))
+    src, dst, ww = src[order], dst[order], ww[order]
+    row_ptr = np.zeros(n + 1, dtype=np.int64)
+    np.add.at(row_ptr, src + 1, 1)
+    row_ptr = np.cumsum(row_ptr)
+    return Graph(n, row_ptr, dst, ww, name)
+
+
+def random_graph(n: int, m: int, seed: int, name: str = "") -> Graph:
+    """m distinct unordered pairs of [0, n), uniform, weight +1.
+
+    Pairs are drawn as (hi32(z)*n >> 32, lo32(z)*n >> 32) from the SplitMix64
+    stream of ``seed``; self pairs are skipped and the first m distinct pairs
+    (in stream order) are kept.
+    """
+    if m > n * (n - 1) // 2:
+        raise ValueError("too many edges")
+    keys = np.empty(0, dtype=np.int64)
+    start = 0
+    while keys.shape[0] < m:
+        batch = max(1024, 2 * (m - keys.shape[0]))
+        z = splitmix64(seed, batch, start)
+        start += batch
+        a = _uniform_index(z >> np.uint64(32), n)
+        b = _uniform_index(z & np.uint64(0xFFFFFFFF), n)
+        ok = a != b
+        lo = np.minimum(a, b)[ok]
+        hi = np.maximum(a, b)[ok]
+        cand = np.concatenate([keys, lo * n + hi])
+        _, first = np.unique(cand, return_index=True)
+        keys = cand[np.sort(first)]
+    keys = keys[:m]
+    return from_edges(n, keys // n, keys % n, None, name or f"G({n},{m})#{seed}")
+
+
+def torus(L: int, seed: int, signed: bool = True, name: str = "") -> Graph:
+    """L x L periodic grid; node r*L+c joined to (r, c+1) and (r+1, c).
+
+    With ``signed`` each of the 2*L*L edges gets weight +1 or -1 with equal
+    probability from bit 0 of the SplitMix64 stream of ``seed`` (edge order:
+    all right-edges row-major, then all down-edges row-major).
+    """
+    if L < 3:
+        raise ValueError("torus needs L >= 3")
+    r, c = np.divmod(np.arange(L * L, dtype=np.int64), L)
+    right = r * L + (c + 1) % L
+    down = ((r + 1) % L) * L + c
+    i = np.concatenate([r * L + c, r * L + c])
+    j = np.concatenate([right, down])
+    if signed:
+        bits = (splitmix64(seed, 2 * L * L) & np.uint64(1)).astype(np.int64)
+        w = 1 - 2 * bits
+    else:
+        w = np.ones(2 * L * L, dtype=np.int64)
+    return from_edges(L * L, i, j, w, name or f"torus{L}{'pm' if signed else ''}#{seed}")
+
+
+def cycle(n: int) -> Graph:
+    i = np.arange(n)
+    return from_edges(n, i, (i + 1) % n, None, f"C{n}")
+
+
+def complete(n: int, weight: int = 1) -> Graph:
+    i, j = np.triu_indices(n, 1)
+    return from_edges(n, i, j, np.full(i.shape, weight), f"K{n}")
+
+
+def linear_betas(beta0: float, beta1: float, K: int) -> np.ndarray:
+    """beta_k = beta0 + (beta1 - beta0) * k / (K - 1), k = 0..K-1, in FP64."""
+    if K == 1:
+        return np.array([float(beta0)])
+    return np.array([beta0 + (beta1 - beta0) * k / (K - 1) for k in range(K)], dtype=np.float64)
+
+
+def natural_order(n: int) -> np.ndarray:
+    return np.arange(n, dtype=np.int32)
+
+
+def checkerboard_order(L: int) -> np.ndarray:
+    """Sites with (r + c) even in row-major order, then the odd sites."""
+    r, c = np.divmod(np.arange(L * L), L)
+    even = np.nonzero((r + c) % 2 == 0)[0]
+    odd = np.nonzero((r + c) % 2 == 1)[0]
+    return np.concatenate([even, odd]).astype(np.int32)
+
+
+# ---------------------------------------------------------------------------
+# Named workloads (graph + schedule + population) shaped like the paper's runs.
+# ---------------------------------------------------------------------------
+
+def workload(name: str) -> dict:
+    """Return a dict with graph, betas, sweeps, order, R, seed, inst, AS/NL params.
+
+    * ``small800``: random G(800, 4000) seed 1, R=128, 50 linear steps
+      0.1 -> 3.0, 10 sweeps/step, natural order.
+    * ``brute20``: random G(20, 60) seed 2, same schedule, checked against
+      exhaustive search.
+    * ``g63like``: random G(7000, 41459) seed 3 (the G63 shape), R=4096,
+      2000 steps 0.1 -> 5.0, 10 sweeps/step, natural order, adaptive
+      stochasticity and non-local moves on.
+    * ``torus100``: 100 x 100 torus with +-1 weights, seed 4, R=16384,
+      1000 steps 0.1 -> 4.0, 5 sweeps/step, checkerboard order.
+    """
+    base = dict(seed=42, as_enable=0, as_stall_steps=20, as_max_level=4,
+                as_frozen_inv=256, as_gamma=0.8, nl_period=0)
+    if name == "small800":
+        g = random_graph(800, 4000, 1, "small800")
+        return dict(base, graph=g, betas=linear_betas(0.1, 3.0, 50), sweeps=10,
+                    order=natural_order(g.n), R=128, inst=0)
+    if name == "brute20":
+        g = random_graph(20, 60, 2, "brute20")
+        return dict(base, graph=g, betas=linear_betas(0.1, 3.0, 50), sweeps=10,
+                    order=natural_order(g.n), R=128, inst=0)
+    if name == "g63like":
+        g = random_graph(7000, 41459, 3, "g63like")
+        return dict(base, graph=g, betas=linear_betas(0.1, 5.0, 2000), sweeps=10,
+                    order=natural_order(g.n), R=4096, inst=1,
+                    as_enable=1, nl_period=10)
+    if name == "torus100":
+        g = torus(100, 4, True, "torus100")
+        return dict(base, graph=g, betas=linear_betas(0.1, 4.0, 1000), sweeps=5,
+                    order=checkerboard_order(100), R=16384, inst=2)
+    raise KeyError(name)

@@ -1,0 +1,360 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+None of these compare the oracle with itself: each checks it against a
+published value, a definition written independently in ``tests/refs.py``, a
+closed form, a special case, an invariant, or a statistical law.
+"""
+import math
+import os
+from decimal import Decimal, getcontext
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2510_21105_amd import workloads as W
+from paper_2510_21105_amd.hexcfg import config_to_hex, hex_to_config
+from tests import refs
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ------------------------------------------------------------------ RNG ----
+
+def test_philox_known_answers():
+    """Philox4x32-10 against the Random123 known-answer vectors (SC'11)."""
+    rows = [l.split() for l in open(os.path.join(GOLDEN, "philox4x32_10_kat.txt"))
+            if l.strip() and not l.startswith("#")]
+    assert len(rows) == 3
+    for r in rows:
+        v = [int(t, 16) for t in r]
+        out = O.philox(v[0:4], v[4:6])
+        assert [int(t) for t in out] == v[6:10]
+
+
+def test_draw_layout():
+    """A draw is word (r & 3) of the Philox block keyed by the seed."""
+    seed, inst = 0x1234_5678_9ABC_DEF0, 7
+    for (tag, s, k, i, r) in [(0, 0, 0, 0, 0), (0, 3, 11, 99, 6), (1, 0, 0, 5, 13), (3, 0, 9, 0, 2)]:
+        blk = O.philox([i, s | (tag << 16), k, (r >> 2) | (inst << 16)],
+                       [seed & 0xFFFFFFFF, seed >> 32])
+        assert O.draw(seed, inst, tag, s, k, i, r) == int(blk[r & 3])
+
+
+def test_philox_uniformity():
+    """Chi-square of the top 4 bits of 2^16 Metropolis draws (sanity of the stream)."""
+    vals = np.array([O.draw(42, 0, 0, 0, 0, i, r) for i in range(256) for r in range(256)],
+                    dtype=np.uint64)
+    counts = np.bincount((vals >> np.uint64(28)).astype(np.int64), minlength=16)
+    exp = vals.shape[0] / 16
+    chi2 = float(((counts - exp) ** 2 / exp).sum())
+    assert chi2 < 45.0   # 15 dof: p ~ 1e-4
+
+
+# -------------------------------------------------------------- tables ----
+
+def _exact_floor(arg: float) -> tuple[int, bool]:
+    """floor(2^32 * exp(-arg)) in 60-digit decimal; flag if within 1e-6 of an integer."""
+    getcontext().prec = 60
+    v = (Decimal(-arg).exp()) * (Decimal(2) ** 32)
+    f = int(v)
+    frac = v - f
+    return f, (frac < Decimal("1e-6") or frac > 1 - Decimal("1e-6"))
+
+
+@pytest.mark.parametrize("beta", [0.0, 1e-9, 0.1, 0.5, 0.8 * 2.2, 3.0, 5.0, 11.2])
+def test_threshold_matches_high_precision_exp(beta):
+    for m in range(1, 31):
+        t = O.threshold(beta, m)
+        f, edge = _exact_floor(beta * (2 * m))
+        assert abs(t - f) <= (1 if edge else 0)
+        assert 0 <= t <= 2 ** 32
+    assert O.threshold(0.0, 5) == 2 ** 32
+    # monotone: non-increasing in m and in beta
+    for m in range(1, 30):
+        assert O.threshold(beta, m + 1) <= O.threshold(beta, m)
+        assert O.threshold(beta + 0.25, m) <= O.threshold(beta, m)
+
+
+@pytest.mark.parametrize("dbeta", [0.0, 0.00245123, 0.0591837, 0.5])
+def test_weight_matches_high_precision_exp(dbeta):
+    for n in [0, 1, 2, 7, 100, 1000, 9000]:
+        wv = O.weight(dbeta, n)
+        f, edge = _exact_floor(dbeta * n)
+        assert abs(wv - f) <= (1 if edge else 0)
+    assert O.weight(dbeta, 0) == 2 ** 32
+    assert O.weight(0.0, 10 ** 6) == 2 ** 32
+
+
+def test_level_beta_products():
+    assert O.level_beta(2.0, 0.8, 0) == 2.0
+    assert O.level_beta(2.0, 0.8, 3) == 2.0 * (0.8 * 0.8 * 0.8)
+    assert abs(O.level_beta(1.0, 0.8, 4) - 0.8 ** 4) < 1e-15
+
+
+# ------------------------------------------------------- objective (1) ----
+
+@pytest.mark.parametrize("gen", ["random", "torus"])
+def test_energy_cut_identity(gen):
+    """cut = (W_tot - E) / 2: oracle energy vs eq. (1) evaluated edge by edge."""
+    g = W.random_graph(300, 1500, 11) if gen == "random" else W.torus(12, 5, True)
+    rng = np.random.default_rng(0)
+    i, j, w = g.edges()
+    w_tot = int(w.sum())
+    for _ in range(20):
+        x = rng.choice(np.array([-1, 1], np.int8), size=g.n)
+        assert (w_tot - O.energy(g, x)) == 2 * refs.cut_eq1(g, x)
+        side = x > 0
+        assert refs.cut_eq1(g, x) == refs.cut_by_sides(g, side)
+
+
+def test_paper_configuration_format():
+    """Section 3: 1,750 hex digits expand to exactly 7,000 variables."""
+    lines = [l.strip() for l in open(os.path.join(GOLDEN, "g63_config_section3.txt"))
+             if l.strip() and not l.startswith("#")]
+    s = "".join(lines)
+    assert len(s) == 1750
+    x = hex_to_config(s, 7000)
+    assert x.shape == (7000,)
+    assert int((x == 1).sum()) == 3425 and int((x == -1).sum()) == 3575
+    assert config_to_hex(x) == s
+    # variable 1 is the MSB of the first digit 'd' = 1101
+    assert list(x[:4]) == [1, 1, -1, 1]
+
+
+# ---------------------------------------------------- whole-run pins ----
+
+def _run(g, betas, sweeps=10, R=64, seed=42, **kw):
+    return O.run(g, betas, sweeps, R, seed, **kw)
+
+
+def test_brute_force_20_nodes():
+    """20-node, 60-edge random graph: PA best cut equals exhaustive search."""
+    wl = W.workload("brute20")
+    r = O.run_workload(wl)
+    exact = refs.brute_force_max_cut(wl["graph"])
+    assert r.best_cut == exact
+    assert refs.cut_eq1(wl["graph"], r.best_x) == exact
+
+
+@pytest.mark.parametrize("seed", [2, 7, 19])
+def test_brute_force_small_random(seed):
+    g = W.random_graph(16, 40, seed)
+    r = _run(g, W.linear_betas(0.1, 3.0, 40), R=64)
+    assert r.best_cut == refs.brute_force_max_cut(g)
+
+
+@pytest.mark.parametrize("n", [10, 11, 30, 31])
+def test_cycle_closed_form(n):
+    # a random visiting order: in natural order the accepted zero-cost moves
+    # carry every domain wall once round the ring per sweep, so walls never meet
+    g = W.cycle(n)
+    order = np.random.default_rng(n).permutation(n).astype(np.int32)
+    r = _run(g, W.linear_betas(0.1, 4.0, 60), R=64, order=order)
+    assert r.best_cut == (n if n % 2 == 0 else n - 1)
+
+
+@pytest.mark.parametrize("n", [7, 8, 9])
+def test_complete_graph_closed_form(n):
+    r = _run(W.complete(n), W.linear_betas(0.1, 3.0, 30), R=32)
+    assert r.best_cut == (n // 2) * ((n + 1) // 2)
+
+
+def test_all_negative_weights_cut_zero():
+    g = W.complete(9, weight=-1)
+    r = _run(g, W.linear_betas(0.1, 3.0, 30), R=32)
+    assert r.best_cut == 0
+
+
+@pytest.mark.parametrize("L", [6, 8])
+def test_bipartite_torus_cuts_every_edge(L):
+    g = W.torus(L, 0, signed=False)
+    r = _run(g, W.linear_betas(0.1, 4.0, 80), R=64, order=W.checkerboard_order(L))
+    assert r.best_cut == 2 * L * L
+
+
+def test_beta_zero_sweep_negates_every_spin():
+    """At beta = 0 every proposal is accepted: one sweep maps x to -x."""
+    g = W.random_graph(100, 300, 3)
+    r1 = _run(g, [0.0], sweeps=1, R=16)
+    assert np.array_equal(r1.x, -r1.x_init)
+    e0 = [O.energy(g, x) for x in r1.x_init]
+    assert np.array_equal(r1.E, np.array(e0, np.int32))
+    assert r1.stats[0, 2] == r1.stats[0, 3]           # uphill attempts == accepts
+    r2 = _run(g, [0.0], sweeps=2, R=16)
+    assert np.array_equal(r2.x, r2.x_init)
+
+
+def test_beta_infinite_is_greedy_local_search():
+    """beta -> infinity: the sweep is single-flip local search (cut-gain form)."""
+    g = W.random_graph(200, 900, 4)
+    order = np.random.default_rng(1).permutation(g.n).astype(np.int32)
+    r = _run(g, [1000.0], sweeps=3, R=8, order=order)
+    for q in range(8):
+        side = refs.greedy_local_search(g, r.x_init[q] > 0, order, 3)
+        assert np.array_equal(side, r.x[q] > 0)
+
+
+def test_metropolis_samples_boltzmann_distribution():
+    """Fixed beta, many sweeps: replica states follow exp(-beta E) / Z."""
+    g = W.from_edges(8, [0, 0, 1, 2, 3, 4, 5, 6, 1, 2, 0, 3],
+                     [1, 2, 3, 4, 5, 6, 7, 7, 5, 6, 7, 6],
+                     [1, -1, 1, 1, -1, 1, 1, -1, 1, 1, -1, 1])
+    beta = 0.6
+    R = 32768
+    r = _run(g, [beta], sweeps=64, R=R, seed=5)
+    E = refs.all_energies(g)
+    p = np.exp(-beta * (E - E.min()))
+    p /= p.sum()
+    obs = np.bincount(refs.state_index(r.x), minlength=p.shape[0])
+    exp = R * p
+    chi2 = float(((obs - exp) ** 2 / exp).sum())
+    # 255 degrees of freedom: mean 255, sd ~22.6; 400 is ~6 sd
+    assert chi2 < 400.0
+    # the wrong exponent (no factor 2 in dE = 2m) is far off
+    p_bad = np.exp(-0.5 * beta * (E - E.min()))
+    p_bad /= p_bad.sum()
+    chi2_bad = float(((obs - R * p_bad) ** 2 / (R * p_bad)).sum())
+    assert chi2_bad > 2000.0
+
+
+def test_free_energy_estimator_matches_enumeration():
+    """Reweighting: sum_k ln(<exp(-dbeta_k E)>) reproduces ln Z(beta) exactly enumerated."""
+    g = W.random_graph(12, 30, 9)
+    betas = W.linear_betas(0.0, 1.5, 31)
+    R = 20000
+    r = _run(g, betas, sweeps=5, R=R, seed=3)
+    est = g.n * math.log(2.0)
+    for k in range(len(betas) - 1):
+        dbeta = betas[k + 1] - betas[k]
+        S = float(r.stats[k, 7])
+        est += math.log(S / (R * 2.0 ** 32)) - dbeta * float(r.stats[k, 0])
+    E = refs.all_energies(g)
+    b = betas[-1]
+    exact = float(np.log(np.exp(-b * (E - E.min())).sum()) - b * E.min())
+    assert abs(est - exact) < 0.03
+
+
+# -------------------------------------------------------- resampling ----
+
+def test_resample_counts_invariants():
+    rng = np.random.default_rng(7)
+    for trial in range(200):
+        R = int(rng.integers(1, 300))
+        Wv = rng.integers(0, 2 ** 32 + 1, size=R, dtype=np.uint64)
+        Wv[rng.random(R) < 0.3] = 0
+        if Wv.sum() == 0:
+            Wv[0] = 1
+        U = int(rng.integers(0, 2 ** 63)) * 2 + int(rng.integers(0, 2))
+        n, S = O.resample_counts(Wv, U)
+        assert S == int(Wv.astype(object).sum())
+        assert int(n.sum()) == R
+        assert np.all(n[Wv == 0] == 0)
+        ideal = [R * int(w) / S for w in Wv]
+        for q in range(R):
+            assert math.floor(ideal[q]) <= n[q] <= math.ceil(ideal[q])
+
+
+def test_resample_identity_for_equal_weights():
+    for R in [1, 2, 17, 128, 4096]:
+        for U in [0, 1, 2 ** 63, 2 ** 64 - 1]:
+            n, _ = O.resample_counts(np.full(R, 2 ** 32, np.uint64), U)
+            assert np.all(n == 1)
+
+
+def test_resample_unbiased():
+    """E[n_r] = R W_r / S over the uniform U."""
+    Wv = np.array([2 ** 32, 3 * 2 ** 30, 2 ** 20, 0, 12345678, 2 ** 31], dtype=np.uint64)
+    R = Wv.shape[0]
+    rng = np.random.default_rng(3)
+    tot = np.zeros(R)
+    T = 20000
+    for _ in range(T):
+        n, S = O.resample_counts(Wv, int(rng.integers(0, 2 ** 63)) * 2)
+        tot += n
+    ideal = R * Wv.astype(float) / float(Wv.astype(float).sum())
+    assert np.allclose(tot / T, ideal, atol=0.02)
+
+
+def test_constant_beta_resampling_is_identity_in_run():
+    g = W.random_graph(60, 200, 8)
+    r = _run(g, [0.7] * 6, sweeps=2, R=40)
+    assert np.all(r.counts[:-1] == 1)
+    assert np.all(r.stats[:-1, 6] == 40)
+
+
+# ------------------------------------------------------ non-local move ----
+
+def test_cluster_move_invariants():
+    g = W.random_graph(400, 1200, 12)
+    rng = np.random.default_rng(4)
+    for t in range(30):
+        xa = rng.choice(np.array([-1, 1], np.int8), size=g.n)
+        xb = xa.copy()
+        flip = rng.random(g.n) < rng.uniform(0.05, 0.6)
+        xb[flip] *= -1
+        d = int(rng.integers(0, 2 ** 32))
+        ea, eb = O.energy(g, xa), O.energy(g, xb)
+        ya, yb, mask, size = O.icm_pair(g, xa, xb, d)
+        D = xa != xb
+        idx = np.nonzero(D)[0]
+        seed_node = idx[(d * idx.shape[0]) >> 32]
+        comp = refs.component_of(g, D, seed_node)
+        assert np.array_equal(mask, comp) and size == int(comp.sum())
+        assert np.array_equal(ya[comp], -xa[comp]) and np.array_equal(ya[~comp], xa[~comp])
+        assert np.array_equal(yb[comp], -xb[comp]) and np.array_equal(yb[~comp], xb[~comp])
+        assert O.energy(g, ya) + O.energy(g, yb) == ea + eb
+
+
+def test_cluster_move_identical_replicas_is_noop():
+    g = W.random_graph(50, 100, 1)
+    x = np.ones(g.n, np.int8)
+    ya, yb, mask, size = O.icm_pair(g, x, x, 123)
+    assert size == 0 and not mask.any() and np.array_equal(ya, x)
+
+
+# --------------------------------------------------------- run invariants ----
+
+@pytest.mark.parametrize("name,over", [
+    ("small800", {}),
+    ("small800", dict(as_enable=1, as_stall_steps=2, nl_period=3, R=100)),
+    ("torus_small", {}),
+])
+def test_run_invariants(name, over):
+    if name == "torus_small":
+        g = W.torus(20, 4, True)
+        wl = dict(W.workload("small800"), graph=g, order=W.checkerboard_order(20), R=96,
+                  betas=W.linear_betas(0.1, 4.0, 30), sweeps=5)
+    else:
+        wl = W.workload(name)
+    r = O.run_workload(wl, **over)
+    g = wl["graph"]
+    R = r.E.shape[0]
+    i, j, w = g.edges()
+    for q in range(R):
+        xq = r.x[q].astype(np.int64)
+        assert int(r.E[q]) == int(np.sum(w * xq[i] * xq[j]))
+    assert r.best_cut == refs.cut_eq1(g, r.best_x)
+    assert r.best_E <= int(r.E.min())
+    assert r.stats[-1, 5] == r.best_E
+    assert np.all(np.diff(r.stats[:, 5]) <= 0)
+    lmax = wl.get("as_max_level", 4) if over.get("as_enable", wl["as_enable"]) else 0
+    assert np.all((r.stats[:, 4] >= 0) & (r.stats[:, 4] <= lmax))
+    assert np.all(r.counts[:-1].sum(axis=1) == R)
+    assert np.all(r.stats[:, 3] <= r.stats[:, 2])
+
+
+def test_thread_count_does_not_change_results():
+    wl = W.workload("small800")
+    a = O.run_workload(wl, nthreads=1, as_enable=1, nl_period=5)
+    b = O.run_workload(wl, nthreads=4, as_enable=1, nl_period=5)
+    assert np.array_equal(a.x, b.x) and np.array_equal(a.stats, b.stats)
+    assert a.best_E == b.best_E and np.array_equal(a.best_x, b.best_x)
+
+
+def test_rejects_bad_arguments():
+    g = W.random_graph(30, 60, 1)
+    with pytest.raises(ValueError):
+        _run(g, [0.5, 0.4])          # decreasing beta
+    with pytest.raises(ValueError):
+        _run(g, [0.5], R=7, nl_period=2)   # odd population with pairing

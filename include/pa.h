@@ -1,0 +1,171 @@
+/*
+ * pa.h -- C ABI of the MI355X population-annealing Max-Cut engine.
+ *
+ * Problem (paper arXiv 2510.21105, section 1, eq. (1)): given an undirected
+ * graph with weights w_ij, find x in {-1,+1}^N maximising
+ *     cut(x) = 1/2 * sum_{i<j} w_ij (1 - x_i x_j).
+ * Section 2: this is the ground state of the Ising energy with couplings
+ * J_ij = -w_ij, E(x) = sum_{i<j} w_ij x_i x_j, and cut = (W_tot - E) / 2 with
+ * W_tot = sum_{i<j} w_ij.
+ * Method (abstract, section 3): population annealing Monte Carlo with
+ * adaptive control of stochasticity and periodic non-local moves. The
+ * paper names these parts without defining them; the exact integer rules
+ * implemented here (Philox4x32-10 draws, fixed-point Metropolis thresholds,
+ * systematic resampling, noise levels, Houdayer cluster moves) are spelled
+ * out with pa_run below and in the project's design notes.
+ *
+ * Conventions for every call:
+ *  - Every function returns pa_status; PA_OK is 0 and errors are negative.
+ *    No C++ exception crosses this boundary. On error, pa_last_error()
+ *    returns a thread-local, NUL-terminated description that stays valid
+ *    until the next call on the same thread.
+ *  - Host pointers are read during the call only (inputs are copied).
+ *  - Device memory is never allocated by the library: pa_run works inside a
+ *    caller-owned device workspace and on a caller-owned HIP stream.
+ *  - Nodes are 0-based; the paper's variable v is node v-1.
+ */
+#ifndef PA_H
+#define PA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PA_OK = 0,
+    PA_EINVAL = -1,     /* malformed graph, schedule or argument          */
+    PA_ERANGE = -2,     /* a size or count outside the supported range    */
+    PA_EWORKSPACE = -3, /* workspace missing, too small or misaligned     */
+    PA_EDEVICE = -4,    /* HIP runtime error (text in pa_last_error)      */
+    PA_ESTATE = -5      /* call out of order, e.g. results before a run   */
+} pa_status;
+
+/* Opaque solver: one validated graph. Owned by the caller from pa_create
+ * until pa_destroy. Not thread-safe: one thread at a time per solver. */
+typedef struct pa_solver pa_solver;
+
+/* Annealing schedule. All pointers are host memory, copied by pa_run. */
+typedef struct {
+    int32_t n_steps;          /* K >= 1 temperature steps                         */
+    const double *beta;       /* K inverse temperatures: finite, >= 0, non-decreasing */
+    int32_t sweeps_per_step;  /* S, 1..65535 Metropolis sweeps per step           */
+    const int32_t *order;     /* NULL = nodes 0..N-1; else a permutation of 0..N-1 */
+    int32_t as_enable;        /* adaptive stochasticity: 0 off, 1 on              */
+    int32_t as_stall_steps;   /* steps without a new best before raising the level, >= 1 */
+    int32_t as_max_level;     /* highest noise level, 0..15                       */
+    int32_t as_frozen_inv;    /* raise only if frozen_inv * uphill_accepts < uphill_attempts, >= 1 */
+    double as_gamma;          /* level l sweeps at beta_k * gamma^l, 0 < gamma <= 1 */
+    int32_t nl_period;        /* non-local cluster moves every nl_period steps, 0 = off */
+    int32_t tile_replicas;    /* replicas per workgroup: 0 = automatic, else 16, 32 or 64;
+                                 results never depend on it                       */
+    int32_t record;           /* bit 0: keep per-step copy counts; bit 1: keep the
+                                 initial population (both for pa_get_* below)     */
+} pa_schedule;
+
+/* Text of the last error on this thread ("" if none). */
+const char *pa_last_error(void);
+
+/*
+ * Validate and keep a graph (host only; no device call).
+ *   n        number of nodes, 2 <= n <= 65536
+ *   row_ptr  n+1 int32, row_ptr[0] = 0, non-decreasing
+ *   col      row_ptr[n] int32 neighbour ids in [0, n)
+ *   w        row_ptr[n] int8 weights, each -1 or +1 (the G-set's binary
+ *            signed or unsigned weights, paper section 1)
+ * The CSR must be symmetric (j in row i with weight w iff i in row j with
+ * weight w), without self loops or repeated neighbours, and every node needs
+ * degree <= 4096. Errors: PA_EINVAL (malformed), PA_ERANGE (sizes).
+ */
+pa_status pa_create(pa_solver **out, int32_t n, const int32_t *row_ptr,
+                    const int32_t *col, const int8_t *w);
+
+/* Release the solver (NULL is accepted). The workspace of its last run is
+ * the caller's and is not touched. */
+pa_status pa_destroy(pa_solver *s);
+
+/* Graph facts: n, nnz (directed entries), W_tot = sum_{i<j} w_ij, max degree. */
+pa_status pa_graph_info(const pa_solver *s, int64_t out[4]);
+
+/* Device workspace bytes pa_run needs for this schedule and population R.
+ * The workspace must be 256-byte aligned. */
+pa_status pa_workspace_bytes(const pa_solver *s, const pa_schedule *sch, int32_t R,
+                             size_t *bytes);
+
+/*
+ * Run population annealing with R replicas (1 <= R <= 32768; even when
+ * nl_period > 0), 64-bit seed and instance id (0..65535). Asynchronous on
+ * `stream` (a hipStream_t; NULL is the default stream) inside `workspace`
+ * (device memory of at least pa_workspace_bytes, 256-byte aligned). The
+ * workspace holds the results and must stay untouched until the last
+ * pa_best_* / pa_get_* call for this run. Every output is a pure function of
+ * (graph, schedule except tile_replicas, R, seed, instance).
+ *
+ * Per step k = 0..K-1 (all integer on the device):
+ *   1. S sweeps over `order`; for node i of replica r:
+ *      m = -x_i h_i with h_i = sum_j w_ij x_j; accept iff m <= 0 or
+ *      draw(0, s, k, i, r) < floor(2^32 exp(-(beta_k gamma^l * 2m))); the best
+ *      configuration is tracked after every sweep.
+ *   2. Every nl_period steps: Houdayer cluster move on replica pairs
+ *      (p, p + R/2), then a best check.
+ *   3. Noise level update (adaptive stochasticity).
+ *   4. If k < K-1: weights floor(2^32 exp(-((beta_{k+1}-beta_k)(E_r-E_min)))),
+ *      systematic resampling back to R replicas.
+ * draw(tag, s, k, i, r) is word (r & 3) of Philox4x32-10 with key
+ * (lo32 seed, hi32 seed) and counter (i, s | tag << 16, k, (r >> 2) | instance << 16).
+ */
+pa_status pa_run(pa_solver *s, const pa_schedule *sch, int32_t R, uint64_t seed,
+                 uint32_t instance, void *workspace, size_t workspace_bytes, void *stream);
+
+/* Best cut found by the last run: cut = (W_tot - E) / 2 (eq. (1)) and its
+ * Ising energy E. Synchronises the run's stream. PA_ESTATE before a run. */
+pa_status pa_best_cut(pa_solver *s, int64_t *cut, int32_t *energy);
+
+/* Where the best was found: {E, step, sweep, replica}; step -1 means the
+ * initial population, sweep == S means right after a non-local move. */
+pa_status pa_best_info(pa_solver *s, int64_t out[4]);
+
+/* Best configuration, n int8 values in {-1,+1} (caller-allocated). */
+pa_status pa_best_config(pa_solver *s, int8_t *x);
+
+/* Best configuration in the paper's hexadecimal format (section 3): digit p
+ * holds variables 4p+1..4p+4, most significant bit first, bit 1 = spin +1,
+ * zero-padded to a multiple of 4 variables. Needs len >= ceil(n/4) + 1. */
+pa_status pa_best_config_hex(pa_solver *s, char *buf, size_t len);
+
+/* Final population of the last run: x (R*n int8, replica-major, +-1) and
+ * E (R int32). Either pointer may be NULL. Synchronises the stream. */
+pa_status pa_get_population(pa_solver *s, int8_t *x, int32_t *E);
+
+/* Initial population (R*n int8); needs schedule.record bit 1. */
+pa_status pa_get_initial_population(pa_solver *s, int8_t *x);
+
+/* Per-step records, K*8 int64: E_min (after sweeps and cluster moves, before
+ * resampling), E_sum, uphill attempts (m > 0), uphill accepts, noise level
+ * used, best E after the step, replicas with at least one copy, weight sum
+ * (the last two are 0 on the last step). */
+pa_status pa_get_step_stats(pa_solver *s, int64_t *out);
+
+/* Copy counts n_r of every resampling, K*R int32 (row K-1 is zero); needs
+ * schedule.record bit 0. */
+pa_status pa_get_counts(pa_solver *s, int32_t *out);
+
+/* Launch facts of the last run: {replicas per workgroup, threads per
+ * workgroup, workgroups per sweep launch, dynamic LDS bytes per workgroup,
+ * levels per sweep, sweep launches}. */
+pa_status pa_get_launch_info(pa_solver *s, int64_t out[6]);
+
+/* Timing mode for measurement: when on, pa_run records HIP events around
+ * each sweep-kernel launch on the run's stream; pa_get_sweep_time then
+ * returns the summed sweep-kernel time in ms and the number of launches
+ * (synchronising the stream). Off by default; results are unchanged. */
+pa_status pa_set_timing(pa_solver *s, int32_t on);
+pa_status pa_get_sweep_time(pa_solver *s, double *ms, int64_t *launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PA_H */

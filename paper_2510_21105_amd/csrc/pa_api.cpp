@@ -1,0 +1,752 @@
+// pa_api.cpp -- host side of the C ABI declared in include/pa.h.
+//
+// Validates the graph (paper section 1: undirected graph, binary weights),
+// builds the device-friendly CSR, the dependency-level schedule of the sweep
+// order, and the fixed-point tables of the Metropolis thresholds and
+// resampling weights (FP64 exp on the host, then floor(2^32 * value)), lays
+// out the caller's workspace and enqueues the step loop on the caller's
+// stream. Device work is in pa_kernels.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <new>
+#include <vector>
+
+#include "pa.h"
+#include "pa_device.h"
+
+namespace {
+
+thread_local char g_error[512] = "";
+
+pa_status fail(pa_status st, const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_error, sizeof g_error, fmt, ap);
+    va_end(ap);
+    return st;
+}
+
+pa_status hip_fail(hipError_t e, const char *what)
+{
+    return fail(PA_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIP_TRY(call)                                                    \
+    do {                                                                 \
+        hipError_t _e = (call);                                          \
+        if (_e != hipSuccess) return hip_fail(_e, #call);                \
+    } while (0)
+
+#define LAUNCH_TRY(call)                                                 \
+    do {                                                                 \
+        if ((call) != 0) return fail(PA_EDEVICE, "%s", pa::last_hip_error()); \
+    } while (0)
+
+constexpr int kMaxN = 65536;
+constexpr int kMaxDegree = 4096;
+constexpr int kMaxR = 32768;
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t b, size_t a = kAlign) { return (b + a - 1) / a * a; }
+
+struct Layout {
+    size_t row_ptr, col, npos, sched, level_off, thr, wtab, wtab_off, wtab_len;
+    size_t X0, X1, E0, E1, cand, snap, counters, as_state, best, best_x, stats, parent;
+    size_t counts, xinit, total;
+};
+
+struct Plan {
+    int K = 0, S = 0, R = 0, G = 0, Rp = 0, W = 0, threads = 0, nblk = 0, nw32 = 0;
+    int lmax1 = 1, n_levels = 0, record = 0;
+    std::vector<int> sched, level_off;
+    std::vector<uint64_t> thr, wtab;
+    std::vector<int> wtab_off, wtab_len;
+    Layout L{};
+};
+
+}  // namespace
+
+struct pa_solver {
+    int n = 0;
+    long long nnz = 0;
+    int dmax = 0;
+    long long w_tot = 0;
+    std::vector<int> row_ptr, col, npos;
+    // last run
+    bool has_run = false;
+    Plan plan;
+    unsigned char *ws = nullptr;
+    hipStream_t stream = nullptr;
+    size_t final_x = 0, final_E = 0;
+    int device = 0;
+    // timing
+    int timing = 0;
+    std::vector<hipEvent_t> ev;
+    int ev_used = 0;
+};
+
+extern "C" const char *pa_last_error(void) { return g_error; }
+
+// --------------------------------------------------------------- create ----
+
+extern "C" pa_status pa_create(pa_solver **out, int32_t n, const int32_t *row_ptr,
+                               const int32_t *col, const int8_t *w)
+{
+    g_error[0] = 0;
+    if (!out || !row_ptr || (!col && row_ptr && n > 0 && row_ptr[n] > 0) || (!w && col))
+        return fail(PA_EINVAL, "pa_create: null pointer argument");
+    *out = nullptr;
+    if (n < 2 || n > kMaxN) return fail(PA_ERANGE, "pa_create: n=%d outside [2, %d]", n, kMaxN);
+    if (row_ptr[0] != 0) return fail(PA_EINVAL, "pa_create: row_ptr[0] must be 0");
+    for (int i = 0; i < n; ++i)
+        if (row_ptr[i + 1] < row_ptr[i]) return fail(PA_EINVAL, "pa_create: row_ptr decreases at %d", i);
+    const long long nnz = row_ptr[n];
+    std::vector<std::vector<std::pair<int, int>>> rows(n);
+    int dmax = 0;
+    for (int i = 0; i < n; ++i) {
+        const int d = row_ptr[i + 1] - row_ptr[i];
+        if (d > kMaxDegree) return fail(PA_ERANGE, "pa_create: degree %d of node %d > %d", d, i, kMaxDegree);
+        dmax = std::max(dmax, d);
+        rows[i].reserve(d);
+        for (int e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
+            const int j = col[e];
+            if (j < 0 || j >= n) return fail(PA_EINVAL, "pa_create: column %d out of range in row %d", j, i);
+            if (j == i) return fail(PA_EINVAL, "pa_create: self loop at node %d", i);
+            if (w[e] != 1 && w[e] != -1)
+                return fail(PA_EINVAL, "pa_create: weight %d of edge (%d,%d) is not +-1", (int)w[e], i, j);
+            rows[i].push_back({j, (int)w[e]});
+        }
+        std::sort(rows[i].begin(), rows[i].end());
+        for (size_t q = 1; q < rows[i].size(); ++q)
+            if (rows[i][q].first == rows[i][q - 1].first)
+                return fail(PA_EINVAL, "pa_create: repeated neighbour %d in row %d", rows[i][q].first, i);
+    }
+    long long wsum = 0;
+    for (int i = 0; i < n; ++i)
+        for (auto &jw : rows[i]) {
+            auto &rj = rows[jw.first];
+            auto it = std::lower_bound(rj.begin(), rj.end(), std::make_pair(i, -2));
+            if (it == rj.end() || it->first != i || it->second != jw.second)
+                return fail(PA_EINVAL, "pa_create: edge (%d,%d) has no symmetric partner", i, jw.first);
+            wsum += jw.second;
+        }
+    pa_solver *s = new (std::nothrow) pa_solver;
+    if (!s) return fail(PA_ERANGE, "pa_create: out of host memory");
+    s->n = n;
+    s->nnz = nnz;
+    s->dmax = dmax;
+    s->w_tot = wsum / 2;
+    s->row_ptr.resize(n + 1);
+    s->col.resize(nnz);
+    s->npos.resize(n);
+    long long e = 0;
+    for (int i = 0; i < n; ++i) {
+        s->row_ptr[i] = (int)e;
+        int np = 0;
+        for (auto &jw : rows[i])
+            if (jw.second > 0) { s->col[e++] = jw.first; ++np; }
+        for (auto &jw : rows[i])
+            if (jw.second < 0) s->col[e++] = jw.first;
+        s->npos[i] = np;
+    }
+    s->row_ptr[n] = (int)e;
+    *out = s;
+    return PA_OK;
+}
+
+extern "C" pa_status pa_destroy(pa_solver *s)
+{
+    if (!s) return PA_OK;
+    if (s->has_run && s->stream) (void)hipStreamSynchronize(s->stream);
+    for (hipEvent_t e : s->ev) (void)hipEventDestroy(e);
+    delete s;
+    return PA_OK;
+}
+
+extern "C" pa_status pa_graph_info(const pa_solver *s, int64_t out[4])
+{
+    if (!s || !out) return fail(PA_EINVAL, "pa_graph_info: null argument");
+    out[0] = s->n;
+    out[1] = s->nnz;
+    out[2] = s->w_tot;
+    out[3] = s->dmax;
+    return PA_OK;
+}
+
+// ----------------------------------------------------------------- plan ----
+
+static pa_status check_schedule(const pa_solver *s, const pa_schedule *sch, int R)
+{
+    if (!s || !sch) return fail(PA_EINVAL, "null solver or schedule");
+    if (sch->n_steps < 1) return fail(PA_EINVAL, "n_steps must be >= 1");
+    if (!sch->beta) return fail(PA_EINVAL, "beta is null");
+    if (sch->sweeps_per_step < 1 || sch->sweeps_per_step > 65535)
+        return fail(PA_ERANGE, "sweeps_per_step=%d outside [1, 65535]", sch->sweeps_per_step);
+    for (int k = 0; k < sch->n_steps; ++k) {
+        const double b = sch->beta[k];
+        if (!std::isfinite(b) || b < 0.0) return fail(PA_EINVAL, "beta[%d] is not finite and >= 0", k);
+        if (k > 0 && b < sch->beta[k - 1]) return fail(PA_EINVAL, "beta decreases at step %d", k);
+    }
+    if (sch->as_enable != 0 && sch->as_enable != 1) return fail(PA_EINVAL, "as_enable must be 0 or 1");
+    if (sch->as_enable) {
+        if (sch->as_stall_steps < 1) return fail(PA_EINVAL, "as_stall_steps must be >= 1");
+        if (sch->as_max_level < 0 || sch->as_max_level > 15)
+            return fail(PA_ERANGE, "as_max_level outside [0, 15]");
+        if (sch->as_frozen_inv < 1) return fail(PA_EINVAL, "as_frozen_inv must be >= 1");
+        if (!(sch->as_gamma > 0.0 && sch->as_gamma <= 1.0)) return fail(PA_EINVAL, "as_gamma outside (0, 1]");
+    }
+    if (sch->nl_period < 0) return fail(PA_EINVAL, "nl_period must be >= 0");
+    if (R < 1 || R > kMaxR) return fail(PA_ERANGE, "R=%d outside [1, %d]", R, kMaxR);
+    if (sch->nl_period > 0 && (R & 1)) return fail(PA_EINVAL, "non-local moves pair replicas: R must be even");
+    if (sch->tile_replicas != 0 && sch->tile_replicas != 16 && sch->tile_replicas != 32 &&
+        sch->tile_replicas != 64)
+        return fail(PA_EINVAL, "tile_replicas must be 0, 16, 32 or 64");
+    if (sch->record < 0 || sch->record > 3) return fail(PA_EINVAL, "record must be in [0, 3]");
+    if (sch->order) {
+        std::vector<char> seen(s->n, 0);
+        for (int t = 0; t < s->n; ++t) {
+            const int i = sch->order[t];
+            if (i < 0 || i >= s->n || seen[i]) return fail(PA_EINVAL, "order is not a permutation (position %d)", t);
+            seen[i] = 1;
+        }
+    }
+    return PA_OK;
+}
+
+// Dependency levels of the sweep order: level(i) = 1 + max level of the
+// neighbours visited before i (0 if none). Nodes of one level are pairwise
+// non-adjacent, and visiting levels in increasing order reproduces the
+// sequential sweep exactly, since each attempt only reads its neighbours.
+static void build_levels(const pa_solver *s, const int32_t *order, Plan &p)
+{
+    const int n = s->n;
+    std::vector<int> pos(n), lvl(n, 0);
+    for (int t = 0; t < n; ++t) pos[order ? order[t] : t] = t;
+    int nl = 0;
+    for (int t = 0; t < n; ++t) {
+        const int i = order ? order[t] : t;
+        int l = 0;
+        for (int e = s->row_ptr[i]; e < s->row_ptr[i + 1]; ++e) {
+            const int j = s->col[e];
+            if (pos[j] < t) l = std::max(l, lvl[j] + 1);
+        }
+        lvl[i] = l;
+        nl = std::max(nl, l + 1);
+    }
+    p.n_levels = nl;
+    p.level_off.assign(nl + 1, 0);
+    for (int i = 0; i < n; ++i) p.level_off[lvl[i] + 1]++;
+    for (int l = 0; l < nl; ++l) p.level_off[l + 1] += p.level_off[l];
+    std::vector<int> fill(p.level_off.begin(), p.level_off.end() - 1);
+    p.sched.assign(n, 0);
+    for (int t = 0; t < n; ++t) {
+        const int i = order ? order[t] : t;
+        p.sched[fill[lvl[i]]++] = i;
+    }
+}
+
+// floor(2^32 * exp(-(beta * 2m))): the acceptance threshold of an uphill
+// flip raising E by 2m at inverse temperature beta.
+static uint64_t threshold_fixed(double beta, int m)
+{
+    const double x = std::exp(-(beta * (double)(2 * m)));
+    return (uint64_t)std::floor(std::ldexp(x, 32));
+}
+
+// floor(2^32 * exp(-(dbeta * n))): Boltzmann reweighting factor of a replica
+// n above the population minimum when beta grows by dbeta.
+static uint64_t weight_fixed(double dbeta, long long n)
+{
+    const double x = std::exp(-(dbeta * (double)n));
+    return (uint64_t)std::floor(std::ldexp(x, 32));
+}
+
+static pa_status build_plan(pa_solver *s, const pa_schedule *sch, int R, Plan &p, bool tables)
+{
+    const int n = s->n;
+    p.K = sch->n_steps;
+    p.S = sch->sweeps_per_step;
+    p.R = R;
+    p.G = (R + 63) / 64;
+    p.Rp = p.G * 64;
+    p.nw32 = (n + 31) / 32;
+    p.record = sch->record;
+    p.lmax1 = sch->as_enable ? sch->as_max_level + 1 : 1;
+
+    int dev = 0, cus = 256, max_lds = 65536;
+    if (hipGetDevice(&dev) == hipSuccess) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) cus = v;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && v > 0)
+            max_lds = v;
+    } else {
+        (void)hipGetLastError();
+        max_lds = 160 * 1024;
+    }
+    int W = sch->tile_replicas;
+    if (W == 0) {
+        W = 64;
+        while (W > 16 && (R + W - 1) / W < cus) W >>= 1;
+        while (W > 16 && pa::sweep_lds_bytes(W, n, s->dmax) > max_lds) W >>= 1;
+    }
+    if (pa::sweep_lds_bytes(W, n, s->dmax) > max_lds)
+        return fail(PA_ERANGE, "graph of %d nodes does not fit LDS with %d replicas per workgroup", n, W);
+    p.W = W;
+    p.threads = pa::kMaxThreads;
+    p.nblk = (R + W - 1) / W;
+
+    build_levels(s, sch->order, p);
+
+    // Weight-table sizes (needed for the workspace size even without tables).
+    const long long span = s->nnz;  // E_r - E_min <= sum |w_ij| over both directions
+    p.wtab_off.assign(p.K, 0);
+    p.wtab_len.assign(p.K, 0);
+    std::map<uint64_t, std::pair<int, int>> seen;
+    long long total = 0;
+    for (int k = 0; k + 1 < p.K; ++k) {
+        const double db = sch->beta[k + 1] - sch->beta[k];
+        uint64_t key;
+        std::memcpy(&key, &db, sizeof key);
+        auto it = seen.find(key);
+        if (it == seen.end()) {
+            long long len = 0;
+            while (len <= span && weight_fixed(db, len) != 0) ++len;
+            if (tables)
+                for (long long q = 0; q < len; ++q) p.wtab.push_back(weight_fixed(db, q));
+            it = seen.emplace(key, std::make_pair((int)total, (int)len)).first;
+            total += len;
+        }
+        p.wtab_off[k] = it->second.first;
+        p.wtab_len[k] = it->second.second;
+    }
+    if (total == 0) {
+        total = 1;
+        if (tables) p.wtab.push_back(0);
+    }
+    if (tables) {
+        const int D = s->dmax + 1;
+        p.thr.assign((size_t)p.K * p.lmax1 * D, 0);
+        for (int k = 0; k < p.K; ++k) {
+            double g = 1.0;
+            for (int l = 0; l < p.lmax1; ++l) {
+                const double b = sch->beta[k] * g;
+                uint64_t *row = &p.thr[((size_t)k * p.lmax1 + l) * D];
+                row[0] = 0;
+                for (int m = 1; m < D; ++m) row[m] = threshold_fixed(b, m);
+                g = g * sch->as_gamma;
+            }
+        }
+    }
+
+    Layout &L = p.L;
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = o;
+        o = align_up(o + std::max<size_t>(bytes, 1));
+        return at;
+    };
+    L.row_ptr = take(sizeof(int) * (n + 1));
+    L.col = take(sizeof(int) * s->nnz);
+    L.npos = take(sizeof(int) * n);
+    L.sched = take(sizeof(int) * n);
+    L.level_off = take(sizeof(int) * (p.n_levels + 1));
+    L.thr = take(sizeof(uint64_t) * (size_t)p.K * p.lmax1 * (s->dmax + 1));
+    L.wtab = take(sizeof(uint64_t) * (size_t)total);
+    L.wtab_off = take(sizeof(int) * p.K);
+    L.wtab_len = take(sizeof(int) * p.K);
+    L.X0 = take(sizeof(uint64_t) * (size_t)p.G * n);
+    L.X1 = take(sizeof(uint64_t) * (size_t)p.G * n);
+    L.E0 = take(sizeof(int) * p.Rp);
+    L.E1 = take(sizeof(int) * p.Rp);
+    L.cand = take(sizeof(uint64_t) * p.nblk);
+    L.snap = take(sizeof(uint32_t) * (size_t)p.nblk * p.nw32);
+    L.counters = take(sizeof(uint64_t) * 2);
+    L.as_state = take(sizeof(int) * 4);
+    L.best = take(sizeof(int) * 8);
+    L.best_x = take(sizeof(uint32_t) * p.nw32);
+    L.stats = take(sizeof(long long) * (size_t)p.K * pa::kStatFields);
+    L.parent = take(sizeof(int) * p.Rp);
+    L.counts = (p.record & 1) ? take(sizeof(int) * (size_t)p.K * R) : 0;
+    L.xinit = (p.record & 2) ? take(sizeof(uint64_t) * (size_t)p.G * n) : 0;
+    L.total = o;
+    return PA_OK;
+}
+
+extern "C" pa_status pa_workspace_bytes(const pa_solver *s, const pa_schedule *sch, int32_t R,
+                                        size_t *bytes)
+{
+    g_error[0] = 0;
+    if (!bytes) return fail(PA_EINVAL, "pa_workspace_bytes: null output");
+    pa_status st = check_schedule(s, sch, R);
+    if (st != PA_OK) return st;
+    Plan p;
+    st = build_plan(const_cast<pa_solver *>(s), sch, R, p, false);
+    if (st != PA_OK) return st;
+    *bytes = p.L.total;
+    return PA_OK;
+}
+
+// ------------------------------------------------------------------ run ----
+
+extern "C" pa_status pa_run(pa_solver *s, const pa_schedule *sch, int32_t R, uint64_t seed,
+                            uint32_t instance, void *workspace, size_t workspace_bytes, void *stream)
+{
+    g_error[0] = 0;
+    pa_status st = check_schedule(s, sch, R);
+    if (st != PA_OK) return st;
+    if (instance > 65535) return fail(PA_ERANGE, "instance=%u outside [0, 65535]", instance);
+    if (!workspace) return fail(PA_EWORKSPACE, "workspace is null");
+    if (((uintptr_t)workspace) % kAlign) return fail(PA_EWORKSPACE, "workspace must be 256-byte aligned");
+    // Host staging buffers of the previous run may still be in flight.
+    if (s->has_run && s->stream) HIP_TRY(hipStreamSynchronize(s->stream));
+    s->has_run = false;
+    Plan p;
+    st = build_plan(s, sch, R, p, true);
+    if (st != PA_OK) return st;
+    if (workspace_bytes < p.L.total)
+        return fail(PA_EWORKSPACE, "workspace of %zu bytes < %zu needed", workspace_bytes, p.L.total);
+
+    s->plan = std::move(p);
+    Plan &P = s->plan;
+    const Layout &L = P.L;
+    unsigned char *ws = static_cast<unsigned char *>(workspace);
+    hipStream_t hs = static_cast<hipStream_t>(stream);
+    s->ws = ws;
+    s->stream = hs;
+    HIP_TRY(hipGetDevice(&s->device));
+    const int n = s->n;
+
+    HIP_TRY(hipMemcpyAsync(ws + L.row_ptr, s->row_ptr.data(), sizeof(int) * (n + 1), hipMemcpyHostToDevice, hs));
+    if (s->nnz)
+        HIP_TRY(hipMemcpyAsync(ws + L.col, s->col.data(), sizeof(int) * s->nnz, hipMemcpyHostToDevice, hs));
+    HIP_TRY(hipMemcpyAsync(ws + L.npos, s->npos.data(), sizeof(int) * n, hipMemcpyHostToDevice, hs));
+    HIP_TRY(hipMemcpyAsync(ws + L.sched, P.sched.data(), sizeof(int) * n, hipMemcpyHostToDevice, hs));
+    HIP_TRY(hipMemcpyAsync(ws + L.level_off, P.level_off.data(), sizeof(int) * (P.n_levels + 1),
+                           hipMemcpyHostToDevice, hs));
+    HIP_TRY(hipMemcpyAsync(ws + L.thr, P.thr.data(), sizeof(uint64_t) * P.thr.size(), hipMemcpyHostToDevice, hs));
+    HIP_TRY(hipMemcpyAsync(ws + L.wtab, P.wtab.data(), sizeof(uint64_t) * P.wtab.size(), hipMemcpyHostToDevice, hs));
+    HIP_TRY(hipMemcpyAsync(ws + L.wtab_off, P.wtab_off.data(), sizeof(int) * P.K, hipMemcpyHostToDevice, hs));
+    HIP_TRY(hipMemcpyAsync(ws + L.wtab_len, P.wtab_len.data(), sizeof(int) * P.K, hipMemcpyHostToDevice, hs));
+
+    auto U64 = [&](size_t off) { return reinterpret_cast<unsigned long long *>(ws + off); };
+    LAUNCH_TRY(pa::launch_fill_u64(U64(L.counters), 0ull, 2, hs));
+    LAUNCH_TRY(pa::launch_fill_u64(U64(L.as_state), 0ull, 2, hs));
+    LAUNCH_TRY(pa::launch_fill_u64(U64(L.best), 0ull, 4, hs));
+    LAUNCH_TRY(pa::launch_fill_u64(U64(L.stats), 0ull, (long long)P.K * pa::kStatFields, hs));
+    if (P.record & 1) LAUNCH_TRY(pa::launch_fill_u64(U64(L.counts), 0ull, ((long long)P.K * R + 1) / 2, hs));
+
+    pa::GraphDev gd;
+    gd.n = n;
+    gd.dmax = s->dmax;
+    gd.row_ptr = reinterpret_cast<const int *>(ws + L.row_ptr);
+    gd.col = reinterpret_cast<const int *>(ws + L.col);
+    gd.npos = reinterpret_cast<const int *>(ws + L.npos);
+    const uint32_t seed_lo = (uint32_t)seed, seed_hi = (uint32_t)(seed >> 32);
+
+    size_t Xc = L.X0, Xn = L.X1, Ec = L.E0, En = L.E1;
+    pa::InitArgs ia;
+    ia.g = gd;
+    ia.R = R;
+    ia.G = P.G;
+    ia.seed_lo = seed_lo;
+    ia.seed_hi = seed_hi;
+    ia.inst = instance;
+    ia.X = reinterpret_cast<uint64_t *>(ws + Xc);
+    ia.E = reinterpret_cast<int *>(ws + Ec);
+    LAUNCH_TRY(pa::launch_init(ia, hs));
+    LAUNCH_TRY(pa::launch_energy(ia, hs));
+    if (P.record & 2)
+        HIP_TRY(hipMemcpyAsync(ws + L.xinit, ws + Xc, sizeof(uint64_t) * (size_t)P.G * n,
+                               hipMemcpyDeviceToDevice, hs));
+
+    pa::EpiArgs ea{};
+    ea.R = R;
+    ea.n = n;
+    ea.nw32 = P.nw32;
+    ea.nblk = P.nblk;
+    ea.W = P.W;
+    ea.K = P.K;
+    ea.S = P.S;
+    ea.as_enable = sch->as_enable;
+    ea.as_stall = sch->as_stall_steps;
+    ea.as_lmax = sch->as_enable ? sch->as_max_level : 0;
+    ea.as_frozen_inv = sch->as_frozen_inv;
+    ea.as_state = reinterpret_cast<int *>(ws + L.as_state);
+    ea.cand = U64(L.cand);
+    ea.snap = reinterpret_cast<const uint32_t *>(ws + L.snap);
+    ea.best = reinterpret_cast<int *>(ws + L.best);
+    ea.best_x = reinterpret_cast<uint32_t *>(ws + L.best_x);
+    ea.counters = U64(L.counters);
+    ea.stats = reinterpret_cast<long long *>(ws + L.stats);
+    ea.wtab = reinterpret_cast<const uint64_t *>(ws + L.wtab);
+    ea.wtab_off = reinterpret_cast<const int *>(ws + L.wtab_off);
+    ea.wtab_len = reinterpret_cast<const int *>(ws + L.wtab_len);
+    ea.seed_lo = seed_lo;
+    ea.seed_hi = seed_hi;
+    ea.inst = instance;
+    ea.parent = reinterpret_cast<int *>(ws + L.parent);
+    ea.counts_rec = (P.record & 1) ? reinterpret_cast<int *>(ws + L.counts) : nullptr;
+
+    // Best of the initial population.
+    {
+        pa::EpiArgs e0 = ea;
+        e0.k = 0;
+        e0.do_pop = 1;
+        e0.pop_step = -1;
+        e0.pop_sweep = -1;
+        e0.E = reinterpret_cast<const int *>(ws + Ec);
+        e0.X = reinterpret_cast<const uint64_t *>(ws + Xc);
+        LAUNCH_TRY(pa::launch_epilogue(e0, hs));
+    }
+
+    pa::SweepArgs sa;
+    sa.g = gd;
+    sa.R = R;
+    sa.S = P.S;
+    sa.lmax1 = P.lmax1;
+    sa.n_levels = P.n_levels;
+    sa.seed_lo = seed_lo;
+    sa.seed_hi = seed_hi;
+    sa.inst = instance;
+    sa.sched = reinterpret_cast<const int *>(ws + L.sched);
+    sa.level_off = reinterpret_cast<const int *>(ws + L.level_off);
+    sa.thr = reinterpret_cast<const uint64_t *>(ws + L.thr);
+    sa.as_state = reinterpret_cast<const int *>(ws + L.as_state);
+    sa.best_E = reinterpret_cast<const int *>(ws + L.best);
+    sa.cand = U64(L.cand);
+    sa.snap = reinterpret_cast<uint32_t *>(ws + L.snap);
+    sa.counters = U64(L.counters);
+    sa.nw32 = P.nw32;
+
+    if (s->timing) {
+        const size_t need = 2 * (size_t)P.K;
+        while (s->ev.size() < need) {
+            hipEvent_t e;
+            HIP_TRY(hipEventCreate(&e));
+            s->ev.push_back(e);
+        }
+    }
+    s->ev_used = 0;
+
+    for (int k = 0; k < P.K; ++k) {
+        sa.k = k;
+        sa.X = reinterpret_cast<uint64_t *>(ws + Xc);
+        sa.E = reinterpret_cast<int *>(ws + Ec);
+        if (s->timing) HIP_TRY(hipEventRecord(s->ev[2 * k], hs));
+        LAUNCH_TRY(pa::launch_sweep(P.W, P.threads, P.nblk, sa, hs));
+        if (s->timing) {
+            HIP_TRY(hipEventRecord(s->ev[2 * k + 1], hs));
+            s->ev_used = k + 1;
+        }
+        pa::EpiArgs e = ea;
+        e.k = k;
+        e.E = reinterpret_cast<const int *>(ws + Ec);
+        e.X = reinterpret_cast<const uint64_t *>(ws + Xc);
+        const bool nl = sch->nl_period > 0 && (k + 1) % sch->nl_period == 0;
+        if (nl) {
+            pa::EpiArgs e1 = e;
+            e1.do_cand = 1;
+            LAUNCH_TRY(pa::launch_epilogue(e1, hs));
+            pa::IcmArgs ic;
+            ic.g = gd;
+            ic.R = R;
+            ic.k = k;
+            ic.nw32 = P.nw32;
+            ic.seed_lo = seed_lo;
+            ic.seed_hi = seed_hi;
+            ic.inst = instance;
+            ic.X = reinterpret_cast<uint64_t *>(ws + Xc);
+            ic.E = reinterpret_cast<int *>(ws + Ec);
+            LAUNCH_TRY(pa::launch_icm(ic, hs));
+            e.do_pop = 1;
+            e.pop_step = k;
+            e.pop_sweep = P.S;
+            e.do_rest = 1;
+        } else {
+            e.do_cand = 1;
+            e.do_rest = 1;
+        }
+        LAUNCH_TRY(pa::launch_epilogue(e, hs));
+        if (k + 1 < P.K) {
+            pa::GatherArgs ga;
+            ga.n = n;
+            ga.R = R;
+            ga.G = P.G;
+            ga.parent = reinterpret_cast<const int *>(ws + L.parent);
+            ga.Xin = reinterpret_cast<const uint64_t *>(ws + Xc);
+            ga.Xout = reinterpret_cast<uint64_t *>(ws + Xn);
+            ga.Ein = reinterpret_cast<const int *>(ws + Ec);
+            ga.Eout = reinterpret_cast<int *>(ws + En);
+            LAUNCH_TRY(pa::launch_gather(ga, hs));
+            std::swap(Xc, Xn);
+            std::swap(Ec, En);
+        }
+    }
+    s->final_x = Xc;
+    s->final_E = Ec;
+    s->has_run = true;
+    return PA_OK;
+}
+
+// -------------------------------------------------------------- results ----
+
+static pa_status fetch(pa_solver *s, void *dst, size_t off, size_t bytes)
+{
+    if (!s || !s->has_run) return fail(PA_ESTATE, "no completed pa_run on this solver");
+    HIP_TRY(hipSetDevice(s->device));
+    HIP_TRY(hipMemcpyAsync(dst, s->ws + off, bytes, hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    return PA_OK;
+}
+
+extern "C" pa_status pa_best_info(pa_solver *s, int64_t out[4])
+{
+    if (!out) return fail(PA_EINVAL, "null output");
+    int b[8];
+    pa_status st = fetch(s, b, s ? s->plan.L.best : 0, sizeof b);
+    if (st != PA_OK) return st;
+    for (int q = 0; q < 4; ++q) out[q] = b[q];
+    return PA_OK;
+}
+
+extern "C" pa_status pa_best_cut(pa_solver *s, int64_t *cut, int32_t *energy)
+{
+    int64_t info[4];
+    pa_status st = pa_best_info(s, info);
+    if (st != PA_OK) return st;
+    if (cut) *cut = (s->w_tot - info[0]) / 2;
+    if (energy) *energy = (int32_t)info[0];
+    return PA_OK;
+}
+
+extern "C" pa_status pa_best_config(pa_solver *s, int8_t *x)
+{
+    if (!x) return fail(PA_EINVAL, "null output");
+    if (!s || !s->has_run) return fail(PA_ESTATE, "no completed pa_run on this solver");
+    std::vector<uint32_t> bits(s->plan.nw32);
+    pa_status st = fetch(s, bits.data(), s->plan.L.best_x, sizeof(uint32_t) * bits.size());
+    if (st != PA_OK) return st;
+    for (int i = 0; i < s->n; ++i) x[i] = ((bits[i >> 5] >> (i & 31)) & 1u) ? 1 : -1;
+    return PA_OK;
+}
+
+extern "C" pa_status pa_best_config_hex(pa_solver *s, char *buf, size_t len)
+{
+    if (!buf) return fail(PA_EINVAL, "null output");
+    if (!s || !s->has_run) return fail(PA_ESTATE, "no completed pa_run on this solver");
+    const size_t digits = ((size_t)s->n + 3) / 4;
+    if (len < digits + 1) return fail(PA_ERANGE, "hex buffer of %zu bytes < %zu needed", len, digits + 1);
+    std::vector<int8_t> x(s->n);
+    pa_status st = pa_best_config(s, x.data());
+    if (st != PA_OK) return st;
+    static const char hexd[] = "0123456789abcdef";
+    for (size_t p = 0; p < digits; ++p) {
+        int v = 0;
+        for (int q = 0; q < 4; ++q) {
+            const size_t i = 4 * p + q;
+            v = (v << 1) | ((i < (size_t)s->n && x[i] > 0) ? 1 : 0);
+        }
+        buf[p] = hexd[v];
+    }
+    buf[digits] = 0;
+    return PA_OK;
+}
+
+static void unpack_population(const std::vector<uint64_t> &X, int n, int R, int8_t *x)
+{
+    for (int r = 0; r < R; ++r) {
+        const uint64_t *Xg = &X[(size_t)(r >> 6) * n];
+        const int b = r & 63;
+        int8_t *xr = x + (size_t)r * n;
+        for (int i = 0; i < n; ++i) xr[i] = ((Xg[i] >> b) & 1ull) ? 1 : -1;
+    }
+}
+
+extern "C" pa_status pa_get_population(pa_solver *s, int8_t *x, int32_t *E)
+{
+    if (!s || !s->has_run) return fail(PA_ESTATE, "no completed pa_run on this solver");
+    const Plan &P = s->plan;
+    if (x) {
+        std::vector<uint64_t> X((size_t)P.G * s->n);
+        pa_status st = fetch(s, X.data(), s->final_x, sizeof(uint64_t) * X.size());
+        if (st != PA_OK) return st;
+        unpack_population(X, s->n, P.R, x);
+    }
+    if (E) {
+        pa_status st = fetch(s, E, s->final_E, sizeof(int) * P.R);
+        if (st != PA_OK) return st;
+    }
+    return PA_OK;
+}
+
+extern "C" pa_status pa_get_initial_population(pa_solver *s, int8_t *x)
+{
+    if (!x) return fail(PA_EINVAL, "null output");
+    if (!s || !s->has_run) return fail(PA_ESTATE, "no completed pa_run on this solver");
+    const Plan &P = s->plan;
+    if (!(P.record & 2)) return fail(PA_ESTATE, "run did not record the initial population (record bit 1)");
+    std::vector<uint64_t> X((size_t)P.G * s->n);
+    pa_status st = fetch(s, X.data(), P.L.xinit, sizeof(uint64_t) * X.size());
+    if (st != PA_OK) return st;
+    unpack_population(X, s->n, P.R, x);
+    return PA_OK;
+}
+
+extern "C" pa_status pa_get_step_stats(pa_solver *s, int64_t *out)
+{
+    if (!out) return fail(PA_EINVAL, "null output");
+    if (!s || !s->has_run) return fail(PA_ESTATE, "no completed pa_run on this solver");
+    return fetch(s, out, s->plan.L.stats, sizeof(long long) * (size_t)s->plan.K * pa::kStatFields);
+}
+
+extern "C" pa_status pa_get_counts(pa_solver *s, int32_t *out)
+{
+    if (!out) return fail(PA_EINVAL, "null output");
+    if (!s || !s->has_run) return fail(PA_ESTATE, "no completed pa_run on this solver");
+    if (!(s->plan.record & 1)) return fail(PA_ESTATE, "run did not record copy counts (record bit 0)");
+    return fetch(s, out, s->plan.L.counts, sizeof(int) * (size_t)s->plan.K * s->plan.R);
+}
+
+extern "C" pa_status pa_get_launch_info(pa_solver *s, int64_t out[6])
+{
+    if (!out) return fail(PA_EINVAL, "null output");
+    if (!s || !s->has_run) return fail(PA_ESTATE, "no completed pa_run on this solver");
+    const Plan &P = s->plan;
+    out[0] = P.W;
+    out[1] = P.threads;
+    out[2] = P.nblk;
+    out[3] = pa::sweep_lds_bytes(P.W, s->n, s->dmax);
+    out[4] = P.n_levels;
+    out[5] = P.K;
+    return PA_OK;
+}
+
+extern "C" pa_status pa_set_timing(pa_solver *s, int32_t on)
+{
+    if (!s) return fail(PA_EINVAL, "null solver");
+    s->timing = on ? 1 : 0;
+    return PA_OK;
+}
+
+extern "C" pa_status pa_get_sweep_time(pa_solver *s, double *ms, int64_t *launches)
+{
+    if (!s || !s->has_run) return fail(PA_ESTATE, "no completed pa_run on this solver");
+    if (!s->timing) return fail(PA_ESTATE, "timing mode was off during the run");
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    double tot = 0.0;
+    for (int k = 0; k < s->ev_used; ++k) {
+        float t = 0.f;
+        HIP_TRY(hipEventElapsedTime(&t, s->ev[2 * k], s->ev[2 * k + 1]));
+        tot += t;
+    }
+    if (ms) *ms = tot;
+    if (launches) *launches = s->ev_used;
+    return PA_OK;
+}

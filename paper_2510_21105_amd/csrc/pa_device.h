@@ -1,0 +1,108 @@
+// pa_device.h -- argument blocks shared by the host driver (pa_api.cpp) and
+// the gfx950 kernels (pa_kernels.hip). Plain structs passed by value.
+//
+// Device data layout (all inside the caller's workspace):
+//   X[g][i]   uint64: bit b is the spin of replica 64g+b at node i (1 = +1).
+//             Group-major, so the 64-replica group g is n contiguous words.
+//   E[r]      int32 Ising energy sum_{i<j} w_ij x_i x_j of replica r.
+//   CSR       row_ptr[n+1], col[nnz] with each row's +1-weight neighbours
+//             first, npos[i] = their count.
+//   sched     nodes grouped by dependency level of the sweep order: nodes in
+//             one level are pairwise non-adjacent, and every node comes after
+//             all its earlier-ordered neighbours' levels.
+#pragma once
+#include <stdint.h>
+
+namespace pa {
+
+constexpr int kStatFields = 8;
+constexpr int kMaxThreads = 1024;
+
+struct GraphDev {
+    int n;
+    int dmax;
+    const int *row_ptr;
+    const int *col;
+    const int *npos;
+};
+
+struct SweepArgs {
+    GraphDev g;
+    int R;            // real replicas
+    int S;            // sweeps in this step
+    int k;            // step index
+    int lmax1;        // number of noise levels
+    int n_levels;
+    uint32_t seed_lo, seed_hi, inst;
+    const int *sched;
+    const int *level_off;
+    const uint64_t *thr;        // [K][lmax1][dmax+1]
+    const int *as_state;        // [0] level
+    uint64_t *X;                // [G][n]
+    int *E;                     // [Rp]
+    const int *best_E;          // global best so far
+    unsigned long long *cand;   // [nblk] (E+2^31)<<32 | s<<15 | r, or ~0
+    uint32_t *snap;             // [nblk][nw32]
+    unsigned long long *counters; // [0] uphill attempts, [1] uphill accepts
+    int nw32;
+};
+
+struct EpiArgs {
+    int R, n, nw32, nblk, W, k, K, S;
+    int do_cand, do_pop, do_rest;
+    int pop_step, pop_sweep;    // best record when the population check wins
+    int as_enable, as_stall, as_lmax, as_frozen_inv;
+    int *as_state;              // [0] level, [1] stall, [2] improved this step
+    const unsigned long long *cand;
+    const uint32_t *snap;
+    int *best;                  // [0] E, [1] step, [2] sweep, [3] replica, [4] valid
+    uint32_t *best_x;           // [nw32]
+    unsigned long long *counters;
+    const int *E;
+    const uint64_t *X;
+    long long *stats;           // [K][8]
+    const uint64_t *wtab;       // weight tables
+    const int *wtab_off;        // [K] offset of step k's table (k < K-1)
+    const int *wtab_len;        // [K]
+    uint32_t seed_lo, seed_hi, inst;
+    int *parent;                // [R] parent replica of each new slot
+    int *counts_rec;            // [K][R] or null
+};
+
+struct GatherArgs {
+    int n, R, G;
+    const int *parent;
+    const uint64_t *Xin;
+    uint64_t *Xout;
+    const int *Ein;
+    int *Eout;
+};
+
+struct IcmArgs {
+    GraphDev g;
+    int R, k, nw32;
+    uint32_t seed_lo, seed_hi, inst;
+    uint64_t *X;
+    int *E;
+};
+
+struct InitArgs {
+    GraphDev g;
+    int R, G;
+    uint32_t seed_lo, seed_hi, inst;
+    uint64_t *X;
+    int *E;
+};
+
+// Host-side launchers (defined in pa_kernels.hip).
+int launch_init(const InitArgs &a, void *stream);
+int launch_energy(const InitArgs &a, void *stream);
+int sweep_lds_bytes(int W, int n, int dmax);
+int launch_sweep(int W, int threads, int nblk, const SweepArgs &a, void *stream);
+int launch_epilogue(const EpiArgs &a, void *stream);
+int launch_gather(const GatherArgs &a, void *stream);
+int launch_icm(const IcmArgs &a, void *stream);
+int launch_fill_u64(unsigned long long *p, unsigned long long v, long long count, void *stream);
+const char *last_hip_error();
+
+}  // namespace pa

@@ -1,0 +1,776 @@
+// pa_kernels.hip -- gfx950 kernels of the population-annealing Max-Cut engine.
+//
+// Paper: arXiv 2510.21105. Objective eq. (1) (section 1), Ising mapping with
+// J_ij = -w_ij (section 2), population annealing with adaptive stochasticity
+// and non-local moves (abstract, section 3). Everything here is integer: the
+// FP64 Metropolis thresholds and resampling weights arrive as fixed-point
+// tables built on the host.
+//
+// Design (MI355X): the population lives bit-packed, 64 replicas per 64-bit
+// word per node. One workgroup owns W replicas (W = 16, 32 or 64) for a whole
+// temperature step: it loads their N*W bits into LDS, runs all S sweeps there
+// and writes them back once, so the hot loop never touches HBM. Local fields
+// are recomputed from the neighbours' spin bits (one LDS read per neighbour,
+// no stored field array), which keeps W replicas of a 20,000-node graph inside
+// 160 KB of LDS. Lanes are replicas; a wave handles 64/W nodes at a time, and
+// the workgroup's waves cover all nodes of one dependency level of the sweep
+// order in parallel (those nodes are pairwise non-adjacent), with a barrier
+// between levels -- the same result as the sequential sweep.
+#include <hip/hip_runtime.h>
+
+#include "pa_device.h"
+
+namespace pa {
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two
+// 32x32->64 products with multipliers 0xD2511F53 / 0xCD9E8D57 and a Weyl key
+// schedule 0x9E3779B9 / 0xBB67AE85.
+// ---------------------------------------------------------------------------
+struct U4 {
+    uint32_t x, y, z, w;
+};
+
+__device__ __forceinline__ U4 philox10(U4 c, uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int round = 0; round < 10; ++round) {
+        const uint32_t lo0 = 0xD2511F53u * c.x;
+        const uint32_t hi0 = __umulhi(0xD2511F53u, c.x);
+        const uint32_t lo1 = 0xCD9E8D57u * c.z;
+        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c.z);
+        c = U4{hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0};
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return c;
+}
+
+// Word (r & 3) of Philox(key = seed, ctr = (i, s | tag << 16, k, (r >> 2) | inst << 16)).
+__device__ __forceinline__ uint32_t draw(uint32_t seed_lo, uint32_t seed_hi, uint32_t inst,
+                                         uint32_t tag, uint32_t s, uint32_t k, uint32_t i,
+                                         uint32_t r)
+{
+    const U4 o = philox10(U4{i, s | (tag << 16), k, (r >> 2) | (inst << 16)}, seed_lo, seed_hi);
+    const uint32_t q = r & 3u;
+    return q == 0 ? o.x : (q == 1 ? o.y : (q == 2 ? o.z : o.w));
+}
+
+// ---------------------------------------------------------------------------
+// Small wave / block reductions (wave64).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ long long wave_sum_ll(long long v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ __forceinline__ unsigned long long wave_min_u64(unsigned long long v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const unsigned long long t = __shfl_xor(v, o, 64);
+        v = t < v ? t : v;
+    }
+    return v;
+}
+
+// Block-wide reductions for blockDim.x a multiple of 64 (<= 1024). `red`
+// is >= 16 entries of shared scratch. Every thread gets the result.
+__device__ unsigned long long block_min_u64(unsigned long long v, unsigned long long *red)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    v = wave_min_u64(v);
+    __syncthreads();
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    unsigned long long r = red[0];
+    for (int w = 1; w < nw; ++w) r = red[w] < r ? red[w] : r;
+    __syncthreads();
+    return r;
+}
+
+__device__ long long block_sum_ll(long long v, long long *red)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    v = wave_sum_ll(v);
+    __syncthreads();
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    long long r = 0;
+    for (int w = 0; w < nw; ++w) r += red[w];
+    __syncthreads();
+    return r;
+}
+
+__host__ __device__ constexpr size_t align16(size_t b) { return (b + 15) & ~size_t(15); }
+
+// ---------------------------------------------------------------------------
+// Initial population: x_i^r = +1 iff bit 0 of draw(1, 0, 0, i, r).
+// One wave per (group, node chunk); the ballot of the 64 lanes is the word.
+// ---------------------------------------------------------------------------
+constexpr int kInitNodesPerWave = 16;
+
+__global__ __launch_bounds__(256) void init_kernel(InitArgs a)
+{
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int g = blockIdx.y;
+    const int r = g * 64 + lane;
+    const int i0 = (blockIdx.x * 4 + wave) * kInitNodesPerWave;
+    for (int t = 0; t < kInitNodesPerWave; ++t) {
+        const int i = i0 + t;
+        if (i >= a.g.n) break;
+        const int bit = r < a.R ? (int)(draw(a.seed_lo, a.seed_hi, a.inst, 1, 0, 0, (uint32_t)i,
+                                             (uint32_t)r) & 1u)
+                                : 0;
+        const unsigned long long mask = __ballot(bit);
+        if (lane == 0) a.X[(size_t)g * a.g.n + i] = mask;
+    }
+}
+
+// E_r = sum_{i<j} w_ij x_i x_j from the bit-packed population (E zeroed first).
+__global__ __launch_bounds__(256) void energy_kernel(InitArgs a)
+{
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int g = blockIdx.y;
+    const int r = g * 64 + lane;
+    const int n = a.g.n;
+    const uint64_t *Xg = a.X + (size_t)g * n;
+    const int i0 = (blockIdx.x * 4 + wave) * kInitNodesPerWave;
+    int acc = 0;
+    for (int t = 0; t < kInitNodesPerWave; ++t) {
+        const int i = i0 + t;
+        if (i >= n) break;
+        const int bi = (int)((Xg[i] >> lane) & 1ull);
+        const int e0 = a.g.row_ptr[i], e1 = a.g.row_ptr[i + 1], em = e0 + a.g.npos[i];
+        for (int e = e0; e < e1; ++e) {
+            const int j = a.g.col[e];
+            if (j <= i) continue;
+            const int bj = (int)((Xg[j] >> lane) & 1ull);
+            const int neg = e >= em;
+            acc += 1 - 2 * (bi ^ bj ^ neg);
+        }
+    }
+    if (r < a.R && acc != 0) atomicAdd(&a.E[r], acc);
+}
+
+// ---------------------------------------------------------------------------
+// Sweep kernel: all S sweeps of one step for W replicas per workgroup.
+// ---------------------------------------------------------------------------
+struct SweepLds {
+    size_t xs, thr, part, eblk, misc, total;
+};
+
+__host__ __device__ inline SweepLds sweep_lds_layout(int W, int n, int dmax)
+{
+    SweepLds L;
+    L.xs = 0;
+    L.thr = align16((size_t)n * (size_t)(W / 8));
+    L.part = L.thr + align16((size_t)(dmax + 1) * 8);
+    L.eblk = L.part + (size_t)kMaxThreads * 4;
+    L.misc = L.eblk + 64 * 4;
+    L.total = L.misc + 16 * 8;
+    return L;
+}
+
+int sweep_lds_bytes(int W, int n, int dmax) { return (int)sweep_lds_layout(W, n, dmax).total; }
+
+template <int W>
+struct SpinTile {
+    // LDS spin words: W = 64 as two 32-bit halves per node, W = 32 one word,
+    // W = 16 one 16-bit word. bit(j, q) is the spin bit of block replica q.
+    unsigned char *base;
+    __device__ __forceinline__ int bit(int j, int q) const
+    {
+        if constexpr (W == 64) {
+            const uint32_t *p = reinterpret_cast<const uint32_t *>(base);
+            return (int)((p[2 * j + (q >> 5)] >> (q & 31)) & 1u);
+        } else if constexpr (W == 32) {
+            const uint32_t *p = reinterpret_cast<const uint32_t *>(base);
+            return (int)((p[j] >> q) & 1u);
+        } else {
+            const uint16_t *p = reinterpret_cast<const uint16_t *>(base);
+            return (int)((p[j] >> q) & 1u);
+        }
+    }
+    __device__ __forceinline__ void load(int i, uint64_t v, int sub)
+    {
+        if constexpr (W == 64) {
+            uint32_t *p = reinterpret_cast<uint32_t *>(base);
+            p[2 * i] = (uint32_t)v;
+            p[2 * i + 1] = (uint32_t)(v >> 32);
+        } else if constexpr (W == 32) {
+            reinterpret_cast<uint32_t *>(base)[i] = (uint32_t)(v >> (32 * sub));
+        } else {
+            reinterpret_cast<uint16_t *>(base)[i] = (uint16_t)(v >> (16 * sub));
+        }
+    }
+    // Flip the spins of node i selected by the slot's ballot bits.
+    __device__ __forceinline__ void flip(int i, unsigned long long ballot, int slot, int rl)
+    {
+        if constexpr (W == 64) {
+            uint32_t *p = reinterpret_cast<uint32_t *>(base);
+            if (rl == 0) p[2 * i] ^= (uint32_t)ballot;
+            if (rl == 32) p[2 * i + 1] ^= (uint32_t)(ballot >> 32);
+        } else if constexpr (W == 32) {
+            if (rl == 0) reinterpret_cast<uint32_t *>(base)[i] ^= (uint32_t)(ballot >> (32 * slot));
+        } else {
+            if (rl == 0)
+                reinterpret_cast<uint16_t *>(base)[i] ^= (uint16_t)(ballot >> (16 * slot));
+        }
+    }
+    __device__ __forceinline__ void store(uint64_t *Xg, int i, int sub) const
+    {
+        if constexpr (W == 64) {
+            const uint32_t *p = reinterpret_cast<const uint32_t *>(base);
+            Xg[i] = ((uint64_t)p[2 * i + 1] << 32) | p[2 * i];
+        } else if constexpr (W == 32) {
+            reinterpret_cast<uint32_t *>(Xg + i)[sub] = reinterpret_cast<const uint32_t *>(base)[i];
+        } else {
+            reinterpret_cast<uint16_t *>(Xg + i)[sub] = reinterpret_cast<const uint16_t *>(base)[i];
+        }
+    }
+};
+
+template <int W>
+__global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs a)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    constexpr int NS = 64 / W;  // node slots per wave
+    const int n = a.g.n;
+    const int dmax = a.g.dmax;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int nwaves = blockDim.x >> 6;
+    const int blk = blockIdx.x;
+    const int r0 = blk * W;
+    const int grp = r0 >> 6;
+    const int sub = (r0 & 63) / W;
+    const int slot_w = lane / W;
+    const int rl = lane % W;
+    const int r = r0 + rl;
+    const int real = r < a.R ? 1 : 0;
+
+    const SweepLds L = sweep_lds_layout(W, n, dmax);
+    SpinTile<W> xs{smem + L.xs};
+    uint64_t *T = reinterpret_cast<uint64_t *>(smem + L.thr);
+    int *part = reinterpret_cast<int *>(smem + L.part);
+    int *Eblk = reinterpret_cast<int *>(smem + L.eblk);
+    long long *misc = reinterpret_cast<long long *>(smem + L.misc);
+    // misc[0] local best E, misc[1] candidate key, misc[2] replica to snapshot
+
+    uint64_t *Xg = a.X + (size_t)grp * n;
+    for (int i = tid; i < n; i += blockDim.x) xs.load(i, Xg[i], sub);
+    const int level = a.as_state[0];
+    const uint64_t *trow = a.thr + ((size_t)a.k * a.lmax1 + level) * (size_t)(dmax + 1);
+    for (int m = tid; m <= dmax; m += blockDim.x) T[m] = trow[m];
+    if (tid < W) Eblk[tid] = (r0 + tid < a.R) ? a.E[r0 + tid] : 0;
+    if (tid == 0) {
+        misc[0] = a.best_E[0];
+        misc[1] = -1;  // reinterpreted as ~0ull: no candidate
+    }
+    __syncthreads();
+
+    const uint32_t k = (uint32_t)a.k;
+    int dE = 0;
+    unsigned int att = 0, acc = 0;
+    for (int s = 0; s < a.S; ++s) {
+        for (int lv = 0; lv < a.n_levels; ++lv) {
+            const int beg = a.level_off[lv], end = a.level_off[lv + 1];
+            for (int base = beg + wave * NS; base < end; base += nwaves * NS) {
+                const int slot = base + slot_w;
+                const bool active = slot < end;
+                int accept = 0;
+                int i = 0;
+                if (active) {
+                    i = a.sched[slot];
+                    const int e0 = a.g.row_ptr[i], e1 = a.g.row_ptr[i + 1];
+                    const int em = e0 + a.g.npos[i];
+                    int c = 0;
+                    for (int e = e0; e < em; ++e) c += xs.bit(a.g.col[e], rl);
+                    int cn = 0;
+                    for (int e = em; e < e1; ++e) cn += xs.bit(a.g.col[e], rl);
+                    const int d = e1 - e0;
+                    c += (e1 - em) - cn;              // neighbours with w_ij x_j = +1
+                    const int u = xs.bit(i, rl) ? c : d - c;  // edges with w_ij x_i x_j = +1
+                    const int m = d - 2 * u;          // flip changes E by 2m
+                    if (m <= 0) {
+                        accept = 1;
+                    } else {
+                        const uint64_t t = T[m];
+                        att += (unsigned)real;
+                        if (t != 0) {
+                            const uint32_t x = draw(a.seed_lo, a.seed_hi, a.inst, 0, (uint32_t)s, k,
+                                                    (uint32_t)i, (uint32_t)r);
+                            accept = (uint64_t)x < t ? 1 : 0;
+                        }
+                        acc += (unsigned)(real & accept);
+                    }
+                    if (accept) dE += 2 * m;
+                }
+                const unsigned long long bal = __ballot(accept);
+                if (active) xs.flip(i, bal, slot_w, rl);
+            }
+            __syncthreads();
+        }
+        // Energies after sweep s and the block's best candidate.
+        part[tid] = dE;
+        dE = 0;
+        __syncthreads();
+        if (tid < W) {
+            int sum = 0;
+            for (int w = 0; w < nwaves; ++w)
+                for (int q = 0; q < NS; ++q) sum += part[w * 64 + q * W + tid];
+            Eblk[tid] += sum;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            long long be = misc[0];
+            int arg = -1;
+            for (int q = 0; q < W && r0 + q < a.R; ++q)
+                if ((long long)Eblk[q] < be) {
+                    be = Eblk[q];
+                    arg = q;
+                }
+            misc[2] = arg;
+            if (arg >= 0) {
+                misc[0] = be;
+                misc[1] = (long long)((((unsigned long long)((uint32_t)be ^ 0x80000000u)) << 32) |
+                                      ((unsigned long long)s << 15) | (unsigned long long)(r0 + arg));
+            }
+        }
+        __syncthreads();
+        const int sq = (int)misc[2];
+        if (sq >= 0) {
+            uint32_t *dst = a.snap + (size_t)blk * a.nw32;
+            for (int w = tid; w < a.nw32; w += blockDim.x) {
+                uint32_t bits = 0;
+                const int ib = w * 32;
+                for (int b = 0; b < 32 && ib + b < n; ++b) bits |= (uint32_t)xs.bit(ib + b, sq) << b;
+                dst[w] = bits;
+            }
+        }
+        __syncthreads();
+    }
+
+    for (int i = tid; i < n; i += blockDim.x) xs.store(Xg, i, sub);
+    if (tid < W && r0 + tid < a.R) a.E[r0 + tid] = Eblk[tid];
+    long long at = wave_sum_ll((long long)att), ac = wave_sum_ll((long long)acc);
+    if (lane == 0) {
+        if (at) atomicAdd(&a.counters[0], (unsigned long long)at);
+        if (ac) atomicAdd(&a.counters[1], (unsigned long long)ac);
+    }
+    if (tid == 0) a.cand[blk] = (unsigned long long)misc[1];
+}
+
+// ---------------------------------------------------------------------------
+// Step epilogue (one workgroup): best-candidate reduction, population best
+// check, noise-level update, statistics, reweighting and systematic
+// resampling counts -> parent list.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t sys_f(uint64_t c, uint64_t R, uint64_t u, uint64_t S)
+{
+    const uint64_t rc = R * c;
+    return rc <= u ? 0 : (rc - u + S - 1) / S;
+}
+
+__global__ __launch_bounds__(1024) void epilogue_kernel(EpiArgs a)
+{
+    __shared__ unsigned long long red_u[16];
+    __shared__ long long red_l[16];
+    __shared__ unsigned long long scan[kMaxThreads];
+    __shared__ int sbest[5];
+    __shared__ int simp;
+    const int tid = threadIdx.x;
+    const int nt = blockDim.x;
+    if (tid < 5) sbest[tid] = a.best[tid];
+    if (tid == 0) simp = a.as_state[2];
+    __syncthreads();
+
+    if (a.do_cand) {
+        unsigned long long key = ~0ull;
+        for (int b = tid; b < a.nblk; b += nt) key = a.cand[b] < key ? a.cand[b] : key;
+        key = block_min_u64(key, red_u);
+        if (key != ~0ull) {
+            const int E = (int)((uint32_t)(key >> 32) ^ 0x80000000u);
+            if (!sbest[4] || E < sbest[0]) {
+                const int s = (int)((key >> 15) & 0xFFFFull);
+                const int r = (int)(key & 0x7FFFull);
+                const uint32_t *src = a.snap + (size_t)(r / a.W) * a.nw32;
+                for (int w = tid; w < a.nw32; w += nt) a.best_x[w] = src[w];
+                __syncthreads();
+                if (tid == 0) {
+                    sbest[0] = E; sbest[1] = a.k; sbest[2] = s; sbest[3] = r; sbest[4] = 1;
+                    simp = 1;
+                }
+            }
+        }
+        __syncthreads();
+    }
+
+    if (a.do_pop) {
+        unsigned long long key = ~0ull;
+        for (int r = tid; r < a.R; r += nt) {
+            const unsigned long long kk =
+                ((unsigned long long)((uint32_t)a.E[r] ^ 0x80000000u) << 32) | (unsigned)r;
+            key = kk < key ? kk : key;
+        }
+        key = block_min_u64(key, red_u);
+        const int E = (int)((uint32_t)(key >> 32) ^ 0x80000000u);
+        const int r = (int)(key & 0xFFFFFFFFull);
+        if (!sbest[4] || E < sbest[0]) {
+            const uint64_t *Xr = a.X + (size_t)(r >> 6) * a.n;
+            const int b = r & 63;
+            for (int w = tid; w < a.nw32; w += nt) {
+                uint32_t bits = 0;
+                for (int q = 0; q < 32 && w * 32 + q < a.n; ++q)
+                    bits |= (uint32_t)((Xr[w * 32 + q] >> b) & 1ull) << q;
+                a.best_x[w] = bits;
+            }
+            __syncthreads();
+            if (tid == 0) {
+                sbest[0] = E; sbest[1] = a.pop_step; sbest[2] = a.pop_sweep; sbest[3] = r; sbest[4] = 1;
+                if (a.pop_step >= 0) simp = 1;
+            }
+        }
+        __syncthreads();
+    }
+
+    if (a.do_rest) {
+        long long emin_l = 0x7FFFFFFFLL, esum = 0;
+        {
+            unsigned long long key = ~0ull;
+            for (int r = tid; r < a.R; r += nt) {
+                const unsigned long long kk = (unsigned long long)((uint32_t)a.E[r] ^ 0x80000000u);
+                key = kk < key ? kk : key;
+                esum += a.E[r];
+            }
+            key = block_min_u64(key, red_u);
+            emin_l = (long long)(int)((uint32_t)key ^ 0x80000000u);
+            esum = block_sum_ll(esum, red_l);
+        }
+        const int emin = (int)emin_l;
+        long long *st = a.stats + (size_t)a.k * kStatFields;
+        if (tid == 0) {
+            const int level_used = a.as_state[0];
+            const unsigned long long att = a.counters[0], acc = a.counters[1];
+            int level = level_used, stall = a.as_state[1];
+            if (a.as_enable) {
+                if (simp) {
+                    level = 0;
+                    stall = 0;
+                } else {
+                    stall += 1;
+                    if (stall >= a.as_stall &&
+                        (unsigned __int128)(unsigned)a.as_frozen_inv * acc < (unsigned __int128)att) {
+                        level = level + 1 < a.as_lmax ? level + 1 : a.as_lmax;
+                        stall = 0;
+                    }
+                }
+            }
+            a.as_state[0] = level;
+            a.as_state[1] = stall;
+            a.as_state[2] = 0;
+            a.counters[0] = 0;
+            a.counters[1] = 0;
+            st[0] = emin; st[1] = esum; st[2] = (long long)att; st[3] = (long long)acc;
+            st[4] = level_used; st[5] = sbest[0];
+            st[6] = 0; st[7] = 0;
+        }
+        if (a.k < a.K - 1) {
+            const int R = a.R;
+            const int per = (R + nt - 1) / nt;
+            const int lo = tid * per < R ? tid * per : R;
+            const int hi = lo + per < R ? lo + per : R;
+            const int off = a.wtab_off[a.k], len = a.wtab_len[a.k];
+            uint64_t ws = 0;
+            for (int r = lo; r < hi; ++r) {
+                const int nn = a.E[r] - emin;
+                ws += nn < len ? a.wtab[off + nn] : 0ull;
+            }
+            scan[tid] = ws;
+            __syncthreads();
+            // Hillis-Steele inclusive scan over the per-thread sums.
+            for (int o = 1; o < nt; o <<= 1) {
+                const uint64_t v = tid >= o ? scan[tid - o] : 0ull;
+                __syncthreads();
+                scan[tid] += v;
+                __syncthreads();
+            }
+            const uint64_t S = scan[nt - 1];
+            const uint64_t excl = scan[tid] - ws;
+            const U4 o = philox10(U4{0u, 2u << 16, (uint32_t)a.k, a.inst << 16}, a.seed_lo, a.seed_hi);
+            const uint64_t U = (uint64_t)o.x | ((uint64_t)o.y << 32);
+            const uint64_t u = __umul64hi(U, S);
+            uint64_t C = excl;
+            uint64_t fprev = sys_f(C, (uint64_t)R, u, S);
+            long long parents = 0;
+            for (int r = lo; r < hi; ++r) {
+                const int nn = a.E[r] - emin;
+                C += nn < len ? a.wtab[off + nn] : 0ull;
+                const uint64_t f = sys_f(C, (uint64_t)R, u, S);
+                for (uint64_t q = fprev; q < f; ++q) a.parent[q] = r;
+                if (a.counts_rec) a.counts_rec[(size_t)a.k * R + r] = (int)(f - fprev);
+                parents += f > fprev;
+                fprev = f;
+            }
+            parents = block_sum_ll(parents, red_l);
+            if (tid == 0) {
+                st[6] = parents;
+                st[7] = (long long)S;
+            }
+        }
+    }
+    __syncthreads();
+    if (tid < 5) a.best[tid] = sbest[tid];
+    if (tid == 0) a.as_state[2] = a.do_rest ? 0 : simp;
+}
+
+// ---------------------------------------------------------------------------
+// Resampling gather: slot q takes the spins and energy of parent(q). The
+// parents of consecutive slots are non-decreasing, so a wave's 64 loads hit
+// one or two groups.
+// ---------------------------------------------------------------------------
+constexpr int kGatherNodesPerWave = 32;
+
+__global__ __launch_bounds__(256) void gather_kernel(GatherArgs a)
+{
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int g = blockIdx.y;
+    const int q = g * 64 + lane;
+    const int p = q < a.R ? a.parent[q] : -1;
+    const int i0 = (blockIdx.x * 4 + wave) * kGatherNodesPerWave;
+    const uint64_t *src = p >= 0 ? a.Xin + (size_t)(p >> 6) * a.n : a.Xin;
+    const int pb = p & 63;
+    for (int t = 0; t < kGatherNodesPerWave; ++t) {
+        const int i = i0 + t;
+        if (i >= a.n) break;
+        const int bit = p >= 0 ? (int)((src[i] >> pb) & 1ull) : 0;
+        const unsigned long long mask = __ballot(bit);
+        if (lane == 0) a.Xout[(size_t)g * a.n + i] = mask;
+    }
+    if (blockIdx.x == 0 && wave == 0 && q < a.R) a.Eout[q] = a.Ein[p];
+}
+
+// ---------------------------------------------------------------------------
+// Non-local move: Houdayer cluster move on the pair (p, p + R/2). One
+// workgroup per pair; bitmaps of the disagreement set D, the cluster and the
+// BFS frontiers live in LDS.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void icm_kernel(IcmArgs a)
+{
+    extern __shared__ __align__(16) uint32_t bm[];
+    __shared__ long long red_l[16];
+    const int tid = threadIdx.x, lane = tid & 63, nt = blockDim.x;
+    const int n = a.g.n, nw = a.nw32;
+    uint32_t *D = bm, *V = bm + nw, *F = bm + 2 * nw, *Nx = bm + 3 * nw;
+    const int p = blockIdx.x, half = a.R / 2;
+    const int ra = p, rb = p + half;
+    const int ba = ra & 63, bb = rb & 63;
+    const uint64_t *Xa = a.X + (size_t)(ra >> 6) * n;
+    const uint64_t *Xb = a.X + (size_t)(rb >> 6) * n;
+
+    for (int w = tid; w < nw; w += nt) { V[w] = 0; F[w] = 0; Nx[w] = 0; }
+    long long cnt = 0;
+    for (int base = 0; base < nw * 32; base += nt) {
+        const int i = base + tid;
+        const int bit = i < n ? (int)(((Xa[i] >> ba) ^ (Xb[i] >> bb)) & 1ull) : 0;
+        const unsigned long long m = __ballot(bit);
+        const int w0 = (base + (tid & ~63)) >> 5;
+        if (lane == 0 && w0 < nw) D[w0] = (uint32_t)m;
+        if (lane == 32 && w0 + 1 < nw) D[w0 + 1] = (uint32_t)(m >> 32);
+        cnt += bit;
+    }
+    cnt = block_sum_ll(cnt, red_l);
+    if (cnt == 0) return;
+    // Seed node: the pick-th element of D in node order.
+    const uint32_t d = draw(a.seed_lo, a.seed_hi, a.inst, 3, 0, (uint32_t)a.k, 0u, (uint32_t)p);
+    const long long pick = (long long)(((uint64_t)d * (uint64_t)cnt) >> 32);
+    if (tid == 0) {
+        long long c = 0;
+        int w = 0;
+        for (; w < nw; ++w) {
+            const int pc = __popc(D[w]);
+            if (c + pc > pick) break;
+            c += pc;
+        }
+        uint32_t bits = D[w];
+        for (long long t = c; t < pick; ++t) bits &= bits - 1;
+        const int s0 = w * 32 + __ffs(bits) - 1;
+        V[s0 >> 5] |= 1u << (s0 & 31);
+        F[s0 >> 5] |= 1u << (s0 & 31);
+    }
+    __syncthreads();
+    // Level-synchronous BFS inside D.
+    for (;;) {
+        long long grew = 0;
+        for (int w = tid; w < nw; w += nt) {
+            uint32_t f = F[w];
+            while (f) {
+                const int b = __ffs(f) - 1;
+                f &= f - 1;
+                const int i = w * 32 + b;
+                for (int e = a.g.row_ptr[i]; e < a.g.row_ptr[i + 1]; ++e) {
+                    const int j = a.g.col[e];
+                    const uint32_t jb = 1u << (j & 31);
+                    if ((D[j >> 5] & jb) && !(V[j >> 5] & jb)) {
+                        const uint32_t old = atomicOr(&V[j >> 5], jb);
+                        if (!(old & jb)) {
+                            atomicOr(&Nx[j >> 5], jb);
+                            grew = 1;
+                        }
+                    }
+                }
+            }
+        }
+        grew = block_sum_ll(grew, red_l);
+        if (grew == 0) break;
+        uint32_t *t = F; F = Nx; Nx = t;
+        for (int w = tid; w < nw; w += nt) Nx[w] = 0;
+        __syncthreads();
+    }
+    // Energy change of replica a: edges leaving the cluster change sign.
+    long long dEa = 0;
+    for (int w = tid; w < nw; w += nt) {
+        uint32_t c = V[w];
+        while (c) {
+            const int b = __ffs(c) - 1;
+            c &= c - 1;
+            const int i = w * 32 + b;
+            const int bi = (int)((Xa[i] >> ba) & 1ull);
+            const int e0 = a.g.row_ptr[i], e1 = a.g.row_ptr[i + 1], em = e0 + a.g.npos[i];
+            for (int e = e0; e < e1; ++e) {
+                const int j = a.g.col[e];
+                if (V[j >> 5] & (1u << (j & 31))) continue;
+                const int bj = (int)((Xa[j] >> ba) & 1ull);
+                const int neg = e >= em;
+                dEa += -2 * (1 - 2 * (bi ^ bj ^ neg));
+            }
+        }
+    }
+    dEa = block_sum_ll(dEa, red_l);
+    // Flip the cluster in both replicas (other workgroups own other bits of
+    // the same words, hence the atomics).
+    unsigned long long *Xw = reinterpret_cast<unsigned long long *>(a.X);
+    for (int w = tid; w < nw; w += nt) {
+        uint32_t c = V[w];
+        while (c) {
+            const int b = __ffs(c) - 1;
+            c &= c - 1;
+            const int i = w * 32 + b;
+            atomicXor(&Xw[(size_t)(ra >> 6) * n + i], 1ull << ba);
+            atomicXor(&Xw[(size_t)(rb >> 6) * n + i], 1ull << bb);
+        }
+    }
+    if (tid == 0) {
+        a.E[ra] += (int)dEa;
+        a.E[rb] -= (int)dEa;
+    }
+}
+
+__global__ void fill_u64_kernel(unsigned long long *p, unsigned long long v, long long count)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) p[i] = v;
+}
+
+// ---------------------------------------------------------------------------
+// Host launchers.
+// ---------------------------------------------------------------------------
+static thread_local char g_err[256];
+
+static int check(const char *what)
+{
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        snprintf(g_err, sizeof g_err, "%s: %s", what, hipGetErrorString(e));
+        return -1;
+    }
+    return 0;
+}
+
+const char *last_hip_error() { return g_err; }
+
+int launch_fill_u64(unsigned long long *p, unsigned long long v, long long count, void *stream)
+{
+    if (count <= 0) return 0;
+    const int tb = 256;
+    const long long nb = (count + tb - 1) / tb;
+    hipLaunchKernelGGL(fill_u64_kernel, dim3((unsigned)nb), dim3(tb), 0, (hipStream_t)stream, p, v,
+                       count);
+    return check("fill");
+}
+
+int launch_init(const InitArgs &a, void *stream)
+{
+    const int per_block = 4 * kInitNodesPerWave;
+    dim3 grid((a.g.n + per_block - 1) / per_block, a.G);
+    hipLaunchKernelGGL(init_kernel, grid, dim3(256), 0, (hipStream_t)stream, a);
+    return check("init_kernel");
+}
+
+int launch_energy(const InitArgs &a, void *stream)
+{
+    if (launch_fill_u64(reinterpret_cast<unsigned long long *>(a.E), 0ull, (long long)a.G * 32,
+                        stream))
+        return -1;
+    const int per_block = 4 * kInitNodesPerWave;
+    dim3 grid((a.g.n + per_block - 1) / per_block, a.G);
+    hipLaunchKernelGGL(energy_kernel, grid, dim3(256), 0, (hipStream_t)stream, a);
+    return check("energy_kernel");
+}
+
+template <int W>
+static int launch_sweep_w(int threads, int nblk, const SweepArgs &a, void *stream)
+{
+    const int lds = sweep_lds_bytes(W, a.g.n, a.g.dmax);
+    static int configured = 0;
+    if (configured < lds) {
+        if (hipFuncSetAttribute(reinterpret_cast<const void *>(&sweep_kernel<W>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess)
+            return check("hipFuncSetAttribute(sweep)");
+        configured = lds;
+    }
+    hipLaunchKernelGGL(sweep_kernel<W>, dim3(nblk), dim3(threads), lds, (hipStream_t)stream, a);
+    return check("sweep_kernel");
+}
+
+int launch_sweep(int W, int threads, int nblk, const SweepArgs &a, void *stream)
+{
+    switch (W) {
+    case 16: return launch_sweep_w<16>(threads, nblk, a, stream);
+    case 32: return launch_sweep_w<32>(threads, nblk, a, stream);
+    case 64: return launch_sweep_w<64>(threads, nblk, a, stream);
+    default:
+        snprintf(g_err, sizeof g_err, "unsupported tile width %d", W);
+        return -1;
+    }
+}
+
+int launch_epilogue(const EpiArgs &a, void *stream)
+{
+    hipLaunchKernelGGL(epilogue_kernel, dim3(1), dim3(kMaxThreads), 0, (hipStream_t)stream, a);
+    return check("epilogue_kernel");
+}
+
+int launch_gather(const GatherArgs &a, void *stream)
+{
+    const int per_block = 4 * kGatherNodesPerWave;
+    dim3 grid((a.n + per_block - 1) / per_block, a.G);
+    hipLaunchKernelGGL(gather_kernel, grid, dim3(256), 0, (hipStream_t)stream, a);
+    return check("gather_kernel");
+}
+
+int launch_icm(const IcmArgs &a, void *stream)
+{
+    const int lds = 4 * a.nw32 * 4;
+    hipLaunchKernelGGL(icm_kernel, dim3(a.R / 2), dim3(256), lds, (hipStream_t)stream, a);
+    return check("icm_kernel");
+}
+
+}  // namespace pa

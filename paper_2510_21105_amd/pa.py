@@ -1,0 +1,268 @@
+"""Python binding of the C ABI in ``include/pa.h`` (argument marshalling only).
+
+Every step of the annealing runs in the HIP kernels of ``libpa.so``; PyTorch
+only supplies the device workspace (a uint8 tensor) and the HIP stream. There
+is no CPU fallback: if the library is missing this module raises on import
+of the library.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpa.so")
+STAT_FIELDS = 8
+STAT_NAMES = ("E_min", "E_sum", "uphill_attempts", "uphill_accepts", "level",
+              "best_E", "parents", "weight_sum")
+
+PA_OK, PA_EINVAL, PA_ERANGE, PA_EWORKSPACE, PA_EDEVICE, PA_ESTATE = 0, -1, -2, -3, -4, -5
+_STATUS = {PA_EINVAL: "PA_EINVAL", PA_ERANGE: "PA_ERANGE", PA_EWORKSPACE: "PA_EWORKSPACE",
+           PA_EDEVICE: "PA_EDEVICE", PA_ESTATE: "PA_ESTATE"}
+
+EXPORTS = ("pa_last_error", "pa_create", "pa_destroy", "pa_graph_info", "pa_workspace_bytes",
+           "pa_run", "pa_best_cut", "pa_best_info", "pa_best_config", "pa_best_config_hex",
+           "pa_get_population", "pa_get_initial_population", "pa_get_step_stats",
+           "pa_get_counts", "pa_get_launch_info", "pa_set_timing", "pa_get_sweep_time")
+
+
+class PAError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Schedule(ctypes.Structure):
+    _fields_ = [
+        ("n_steps", ctypes.c_int32),
+        ("beta", ctypes.POINTER(ctypes.c_double)),
+        ("sweeps_per_step", ctypes.c_int32),
+        ("order", ctypes.POINTER(ctypes.c_int32)),
+        ("as_enable", ctypes.c_int32),
+        ("as_stall_steps", ctypes.c_int32),
+        ("as_max_level", ctypes.c_int32),
+        ("as_frozen_inv", ctypes.c_int32),
+        ("as_gamma", ctypes.c_double),
+        ("nl_period", ctypes.c_int32),
+        ("tile_replicas", ctypes.c_int32),
+        ("record", ctypes.c_int32),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    """Load ``libpa.so``; raise if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -c 'import __graft_entry__ as g; g.build()'`")
+        L = ctypes.CDLL(LIB_PATH)
+        P, i32, i64, u32, u64 = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64,
+                                 ctypes.c_uint32, ctypes.c_uint64)
+        L.pa_last_error.restype = ctypes.c_char_p
+        L.pa_last_error.argtypes = []
+        sigs = {
+            "pa_create": [ctypes.POINTER(P), i32, P, P, P],
+            "pa_destroy": [P],
+            "pa_graph_info": [P, P],
+            "pa_workspace_bytes": [P, ctypes.POINTER(Schedule), i32, ctypes.POINTER(ctypes.c_size_t)],
+            "pa_run": [P, ctypes.POINTER(Schedule), i32, u64, u32, P, ctypes.c_size_t, P],
+            "pa_best_cut": [P, ctypes.POINTER(i64), ctypes.POINTER(i32)],
+            "pa_best_info": [P, P],
+            "pa_best_config": [P, P],
+            "pa_best_config_hex": [P, ctypes.c_char_p, ctypes.c_size_t],
+            "pa_get_population": [P, P, P],
+            "pa_get_initial_population": [P, P],
+            "pa_get_step_stats": [P, P],
+            "pa_get_counts": [P, P],
+            "pa_get_launch_info": [P, P],
+            "pa_set_timing": [P, i32],
+            "pa_get_sweep_time": [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)],
+        }
+        for name, args in sigs.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _check(st: int):
+    if st != PA_OK:
+        raise PAError(st, lib().pa_last_error().decode(errors="replace"))
+
+
+def _p(a):
+    return None if a is None else ctypes.c_void_p(a.ctypes.data)
+
+
+@dataclass
+class RunParams:
+    betas: np.ndarray
+    sweeps: int
+    R: int
+    seed: int
+    inst: int = 0
+    order: np.ndarray | None = None
+    as_enable: int = 0
+    as_stall_steps: int = 20
+    as_max_level: int = 4
+    as_frozen_inv: int = 256
+    as_gamma: float = 0.8
+    nl_period: int = 0
+    tile_replicas: int = 0
+    record: int = 0
+
+
+class Solver:
+    """One validated graph; runs population annealing on the current HIP device."""
+
+    def __init__(self, graph):
+        self.graph = graph
+        self.n = int(graph.n)
+        self._row_ptr = np.ascontiguousarray(graph.row_ptr, dtype=np.int32)
+        self._col = np.ascontiguousarray(graph.col, dtype=np.int32)
+        self._w = np.ascontiguousarray(graph.w, dtype=np.int8)
+        h = ctypes.c_void_p()
+        _check(lib().pa_create(ctypes.byref(h), self.n, _p(self._row_ptr), _p(self._col), _p(self._w)))
+        self._h = h
+        self._workspace = None
+        self._keep = None
+        self._R = 0
+        self._K = 0
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().pa_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self):
+        out = np.zeros(4, dtype=np.int64)
+        _check(lib().pa_graph_info(self._h, _p(out)))
+        return dict(n=int(out[0]), nnz=int(out[1]), w_tot=int(out[2]), dmax=int(out[3]))
+
+    def _schedule(self, p: RunParams):
+        betas = np.ascontiguousarray(p.betas, dtype=np.float64)
+        order = None if p.order is None else np.ascontiguousarray(p.order, dtype=np.int32)
+        sch = Schedule()
+        sch.n_steps = betas.shape[0]
+        sch.beta = betas.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        sch.sweeps_per_step = p.sweeps
+        sch.order = (order.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)) if order is not None
+                     else ctypes.POINTER(ctypes.c_int32)())
+        sch.as_enable = p.as_enable
+        sch.as_stall_steps = p.as_stall_steps
+        sch.as_max_level = p.as_max_level
+        sch.as_frozen_inv = p.as_frozen_inv
+        sch.as_gamma = p.as_gamma
+        sch.nl_period = p.nl_period
+        sch.tile_replicas = p.tile_replicas
+        sch.record = p.record
+        return sch, (betas, order)
+
+    def workspace_bytes(self, p: RunParams) -> int:
+        sch, keep = self._schedule(p)
+        b = ctypes.c_size_t()
+        _check(lib().pa_workspace_bytes(self._h, ctypes.byref(sch), p.R, ctypes.byref(b)))
+        return int(b.value)
+
+    def run(self, p: RunParams, stream=None, workspace=None):
+        """Enqueue a run on ``stream`` (torch.cuda stream; current one by default)."""
+        import torch
+        sch, keep = self._schedule(p)
+        need = self.workspace_bytes(p)
+        if workspace is None:
+            if self._workspace is None or self._workspace.numel() < need + 256:
+                self._workspace = torch.empty(need + 256, dtype=torch.uint8, device="cuda")
+            workspace = self._workspace
+        base = workspace.data_ptr()
+        aligned = (base + 255) // 256 * 256
+        avail = workspace.numel() - (aligned - base)
+        st = torch.cuda.current_stream() if stream is None else stream
+        _check(lib().pa_run(self._h, ctypes.byref(sch), p.R, p.seed, p.inst,
+                            ctypes.c_void_p(aligned), avail, ctypes.c_void_p(st.cuda_stream)))
+        self._keep = (keep, workspace)
+        self._R = p.R
+        self._K = int(sch.n_steps)
+        return self
+
+    # ---- results (each synchronises the run's stream) ----
+    def best_cut(self) -> int:
+        cut = ctypes.c_int64()
+        e = ctypes.c_int32()
+        _check(lib().pa_best_cut(self._h, ctypes.byref(cut), ctypes.byref(e)))
+        return int(cut.value)
+
+    def best_info(self):
+        out = np.zeros(4, dtype=np.int64)
+        _check(lib().pa_best_info(self._h, _p(out)))
+        return dict(E=int(out[0]), step=int(out[1]), sweep=int(out[2]), replica=int(out[3]))
+
+    def best_config(self) -> np.ndarray:
+        x = np.zeros(self.n, dtype=np.int8)
+        _check(lib().pa_best_config(self._h, _p(x)))
+        return x
+
+    def best_config_hex(self) -> str:
+        buf = ctypes.create_string_buffer((self.n + 3) // 4 + 1)
+        _check(lib().pa_best_config_hex(self._h, buf, len(buf)))
+        return buf.value.decode()
+
+    def population(self):
+        x = np.zeros((self._R, self.n), dtype=np.int8)
+        E = np.zeros(self._R, dtype=np.int32)
+        _check(lib().pa_get_population(self._h, _p(x), _p(E)))
+        return x, E
+
+    def initial_population(self):
+        x = np.zeros((self._R, self.n), dtype=np.int8)
+        _check(lib().pa_get_initial_population(self._h, _p(x)))
+        return x
+
+    def step_stats(self) -> np.ndarray:
+        out = np.zeros((self._K, STAT_FIELDS), dtype=np.int64)
+        _check(lib().pa_get_step_stats(self._h, _p(out)))
+        return out
+
+    def counts(self) -> np.ndarray:
+        out = np.zeros((self._K, self._R), dtype=np.int32)
+        _check(lib().pa_get_counts(self._h, _p(out)))
+        return out
+
+    def launch_info(self):
+        out = np.zeros(6, dtype=np.int64)
+        _check(lib().pa_get_launch_info(self._h, _p(out)))
+        keys = ("tile_replicas", "threads", "workgroups", "lds_bytes", "levels", "sweep_launches")
+        return dict(zip(keys, (int(v) for v in out)))
+
+    def set_timing(self, on: bool):
+        _check(lib().pa_set_timing(self._h, 1 if on else 0))
+
+    def sweep_time(self):
+        ms = ctypes.c_double()
+        n = ctypes.c_int64()
+        _check(lib().pa_get_sweep_time(self._h, ctypes.byref(ms), ctypes.byref(n)))
+        return float(ms.value), int(n.value)
+
+
+def params_from_workload(wl: dict, **over) -> RunParams:
+    d = dict(wl)
+    d.update(over)
+    return RunParams(betas=d["betas"], sweeps=d["sweeps"], R=d["R"], seed=d["seed"],
+                     inst=d.get("inst", 0), order=d.get("order"), as_enable=d["as_enable"],
+                     as_stall_steps=d["as_stall_steps"], as_max_level=d["as_max_level"],
+                     as_frozen_inv=d["as_frozen_inv"], as_gamma=d["as_gamma"],
+                     nl_period=d["nl_period"], tile_replicas=d.get("tile_replicas", 0),
+                     record=d.get("record", 0))

@@ -1,0 +1,183 @@
+"""Throughput benchmark of the population-annealing engine on one MI355X.
+
+One benchmark step is one complete solve -- every part of the hot path
+(setup, tables, initial population, all sweeps, best tracking, adaptive
+noise levels, cluster moves, reweighting and resampling) -- on the G63-shaped
+workload: random graph with 7,000 nodes and 41,459 edges (paper section 1),
+R = 4,096 replicas, 2,000 linear inverse-temperature steps 0.1 -> 5.0,
+10 sweeps per step, natural order, adaptive stochasticity and cluster moves
+every 10 steps. Inputs are synthetic (seeded generator) and resident on the
+device before the timed region.
+
+Prints one JSON line: spin-flip attempts/s (= R*N*S*K per solve / time per
+solve), the sweep kernel's roofline figures and the CPU oracle baseline.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+SWEEP_SOURCE = os.path.join(ROOT, "paper_2510_21105_amd", "csrc", "pa_kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_kernel_hbm_traffic_g63like.json")
+
+
+def kernel_source_hash() -> str:
+    with open(SWEEP_SOURCE, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def algorithmic_bytes_per_attempt(accept_rate: float, mean_degree: float, s_x=1, s_h=2) -> float:
+    """Bytes the sequential method must touch per attempt with int8 spins and
+    int16 fields: read x_i and h_i; on acceptance write x_i and update the
+    d fields of the neighbours (read + write)."""
+    return (s_x + s_h) + accept_rate * (s_x + 2 * s_h * mean_degree)
+
+
+def measured_traffic_per_launch():
+    """HBM bytes per sweep launch from the committed rocprofv3 counter summary,
+    or None when it is absent or was taken on a different kernel source."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    return t.get("bytes_per_launch")
+
+
+def cpu_baseline(wl, sample_steps: int):
+    from oracle import oracle as O
+    betas = wl["betas"][:sample_steps]
+    t0 = time.perf_counter()
+    O.run_workload(wl, betas=betas, want_population=False, want_counts=False)
+    dt = time.perf_counter() - t0
+    attempts = wl["R"] * wl["graph"].n * wl["sweeps"] * len(betas)
+    return {"value": attempts / dt, "unit": "attempts/s", "cores": O.num_threads(),
+            "kind": "oracle",
+            "sample": f"first {len(betas)} of {len(wl['betas'])} temperature steps of the same "
+                      f"workload (R={wl['R']}, N={wl['graph'].n}, S={wl['sweeps']}), "
+                      f"{dt:.1f} s on the host"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3, help="timed solves")
+    ap.add_argument("--warmup", type=int, default=1, help="untimed solves")
+    ap.add_argument("--workload", default="g63like")
+    ap.add_argument("--cpu-sample-steps", type=int, default=12)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first run a plain int32 elementwise kernel of known size "
+                         "(for scaling HBM counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2510_21105_amd import pa, workloads as W
+
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        src = torch.ones(64 << 20, dtype=torch.int32, device="cuda")   # 256 MiB
+        dst = torch.empty_like(src)
+        torch.add(src, 1, out=dst)
+        torch.cuda.synchronize()
+        print(f"[bench] calibration kernel: {src.numel() * 4} bytes read, "
+              f"{dst.numel() * 4} bytes written", file=sys.stderr, flush=True)
+        del src, dst
+
+    wl = W.workload(args.workload)
+    g = wl["graph"]
+    params = pa.params_from_workload(wl)
+    solver = pa.Solver(g)
+    K, S, R, N = len(params.betas), params.sweeps, params.R, g.n
+    attempts = R * N * S * K
+    print(f"[bench] workload {g.name}: N={N} edges={g.n_edges} R={R} K={K} S={S}",
+          file=sys.stderr, flush=True)
+    solver.set_timing(True)
+    for w in range(args.warmup):
+        solver.run(params)
+        torch.cuda.synchronize()
+        print(f"[bench] warmup {w + 1}/{args.warmup} done", file=sys.stderr, flush=True)
+
+    sweep_ms, sweep_launches = 0.0, 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for step in range(args.steps):
+        solver.run(params)
+        ms, nl = solver.sweep_time()          # synchronises the stream
+        sweep_ms += ms
+        sweep_launches += nl
+        print(f"[bench] timed solve {step + 1}/{args.steps} done", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    sec_per_step = (t1 - t0) / args.steps
+    value = attempts / sec_per_step
+
+    st = solver.step_stats()
+    att_up = int(st[:, 2].sum())
+    acc_up = int(st[:, 3].sum())
+    accepts = attempts - att_up + acc_up
+    a = accepts / attempts
+    dbar = 2.0 * g.n_edges / N
+    b_alg = algorithmic_bytes_per_attempt(a, dbar)
+    per_launch_attempts = R * N * S
+    avg_launch_s = sweep_ms / 1000.0 / max(sweep_launches, 1)
+    achieved_gbs = b_alg * per_launch_attempts / avg_launch_s / 1e9
+    traffic = measured_traffic_per_launch()
+    roof = {"bound": "hbm", "achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved_gbs / HBM_PEAK_GBS, 4), "traffic": traffic}
+
+    out = {
+        "metric": "spin-flip attempts/s",
+        "value": value,
+        "unit": "attempts/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": sec_per_step * 1000.0,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: random G(N={N}, M={g.n_edges}) seed 3 "
+                               f"(G63 shape), R={R}, K={K} linear beta 0.1->5.0, S={S}, "
+                               f"adaptive stochasticity + cluster moves every "
+                               f"{params.nl_period} steps",
+                   "nodes": N, "edges": g.n_edges, "replicas": R, "temperature_steps": K,
+                   "sweeps_per_step": S, "attempts_per_solve": attempts},
+        "roofline": roof,
+        "sweep_kernel": {"avg_launch_ms": avg_launch_s * 1e3, "launches": sweep_launches,
+                         "attempts_per_launch": per_launch_attempts,
+                         "attempts_per_s": per_launch_attempts / avg_launch_s,
+                         "accept_rate": a, "alg_bytes_per_attempt": b_alg,
+                         "launch": solver.launch_info()},
+        "best_cut": solver.best_cut(),
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] timing the CPU oracle on a sample", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_sample_steps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

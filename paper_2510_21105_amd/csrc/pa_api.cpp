@@ -49,7 +49,7 @@ pa_status hip_fail(hipError_t e, const char *what)
         if ((call) != 0) return fail(PA_EDEVICE, "%s", pa::last_hip_error()); \
     } while (0)
 
-constexpr int kMaxN = 65536;
+constexpr int kMaxN = 32767;   // node ids and LDS word indices fit 16 bits
 constexpr int kMaxDegree = 4096;
 constexpr int kMaxR = 32768;
 constexpr size_t kAlign = 256;
@@ -57,7 +57,7 @@ constexpr size_t kAlign = 256;
 size_t align_up(size_t b, size_t a = kAlign) { return (b + a - 1) / a * a; }
 
 struct Layout {
-    size_t row_ptr, col, npos, sched, level_off, thr, wtab, wtab_off, wtab_len;
+    size_t row_ptr, col, npos, sched, level_off, blocks, stream, thr, wtab, wtab_off, wtab_len;
     size_t X0, X1, E0, E1, cand, snap, counters, as_state, best, best_x, stats, parent;
     size_t counts, xinit, total;
 };
@@ -65,7 +65,10 @@ struct Layout {
 struct Plan {
     int K = 0, S = 0, R = 0, G = 0, Rp = 0, W = 0, threads = 0, nblk = 0, nw32 = 0;
     int lmax1 = 1, n_levels = 0, record = 0;
+    int sgn = 0, pre = 0, block_bytes = 0, qpad = 0;
     std::vector<int> sched, level_off;
+    std::vector<uint16_t> blocks;   // [n][block_bytes / 2]
+    std::vector<int> stream;        // [waves][qpad][2]
     std::vector<uint64_t> thr, wtab;
     std::vector<int> wtab_off, wtab_len;
     Layout L{};
@@ -78,6 +81,7 @@ struct pa_solver {
     long long nnz = 0;
     int dmax = 0;
     long long w_tot = 0;
+    int has_neg = 0;
     std::vector<int> row_ptr, col, npos;
     // last run
     bool has_run = false;
@@ -153,7 +157,7 @@ extern "C" pa_status pa_create(pa_solver **out, int32_t n, const int32_t *row_pt
         for (auto &jw : rows[i])
             if (jw.second > 0) { s->col[e++] = jw.first; ++np; }
         for (auto &jw : rows[i])
-            if (jw.second < 0) s->col[e++] = jw.first;
+            if (jw.second < 0) { s->col[e++] = jw.first; s->has_neg = 1; }
         s->npos[i] = np;
     }
     s->row_ptr[n] = (int)e;
@@ -252,6 +256,67 @@ static void build_levels(const pa_solver *s, const int32_t *order, Plan &p)
     }
 }
 
+// Adjacency blocks in schedule order, one fixed-size block per slot:
+// u16 {node, degree, 0, 0, neighbour word indices..., zero-word padding}.
+// A neighbour joined by a negative weight points at the complemented copy of
+// its spin word (index n + j), so every entry counts "w_ij x_j = +1" by a
+// plain bit read. Indices are stored as LDS byte offsets when they fit.
+// Each wave's pass stream lists {first slot, largest degree in the pass}.
+static void build_blocks(const pa_solver *s, Plan &p)
+{
+    const int n = s->n;
+    const int NS = 64 / p.W, NW = p.threads / 64;
+    const int sh = p.W == 16 ? 1 : (p.W == 32 ? 2 : 3);
+    const int words = p.sgn ? 2 * n : n;
+    const int dummy = words;
+    p.pre = ((long long)(words + 1) << sh) <= 65536 ? 1 : 0;
+    p.block_bytes = 16 * ((2 * (4 + s->dmax) + 15) / 16);
+    const int bw = p.block_bytes / 2;
+    auto enc = [&](int idx) { return (uint16_t)(p.pre ? (idx << sh) : idx); };
+    p.blocks.assign((size_t)n * bw + 32, enc(dummy));
+    for (int t = 0; t < n; ++t) {
+        const int i = p.sched[t];
+        uint16_t *b = &p.blocks[(size_t)t * bw];
+        const int e0 = s->row_ptr[i], e1 = s->row_ptr[i + 1];
+        b[0] = (uint16_t)i;
+        b[1] = (uint16_t)(e1 - e0);
+        b[2] = 0;
+        b[3] = 0;
+        for (int e = e0; e < e1; ++e) {
+            const int j = s->col[e];
+            const bool neg = e >= e0 + s->npos[i];
+            b[4 + (e - e0)] = enc(neg ? n + j : j);
+        }
+    }
+    std::vector<std::vector<int>> st(NW);
+    for (int l = 0; l < p.n_levels; ++l) {
+        const int beg = p.level_off[l], end = p.level_off[l + 1], Lsz = end - beg;
+        for (int w = 0; w < NW; ++w) {
+            const int npass = Lsz > w * NS ? (Lsz - w * NS + NW * NS - 1) / (NW * NS) : 0;
+            for (int q = 0; q < npass; ++q) {
+                const int base = beg + w * NS + q * NW * NS;
+                int md = 0;
+                for (int t = base; t < base + NS && t < end; ++t) {
+                    const int i = p.sched[t];
+                    md = std::max(md, s->row_ptr[i + 1] - s->row_ptr[i]);
+                }
+                st[w].push_back(base);
+                st[w].push_back(md);
+            }
+        }
+    }
+    size_t qmax = 0;
+    for (auto &v : st) qmax = std::max(qmax, v.size() / 2);
+    p.qpad = (int)qmax + 4;
+    p.stream.assign((size_t)NW * p.qpad * 2, 0);
+    for (int w = 0; w < NW; ++w)
+        for (int q = 0; q < p.qpad; ++q) {
+            const bool have = (size_t)q < st[w].size() / 2;
+            p.stream[((size_t)w * p.qpad + q) * 2] = have ? st[w][2 * q] : -1;
+            p.stream[((size_t)w * p.qpad + q) * 2 + 1] = have ? st[w][2 * q + 1] : 0;
+        }
+}
+
 // floor(2^32 * exp(-(beta * 2m))): the acceptance threshold of an uphill
 // flip raising E by 2m at inverse temperature beta.
 static uint64_t threshold_fixed(double beta, int m)
@@ -290,19 +355,21 @@ static pa_status build_plan(pa_solver *s, const pa_schedule *sch, int R, Plan &p
         (void)hipGetLastError();
         max_lds = 160 * 1024;
     }
+    p.threads = pa::kMaxThreads;
+    p.sgn = s->has_neg;
     int W = sch->tile_replicas;
     if (W == 0) {
         W = 64;
         while (W > 16 && (R + W - 1) / W < cus) W >>= 1;
-        while (W > 16 && pa::sweep_lds_bytes(W, n, s->dmax) > max_lds) W >>= 1;
+        while (W > 16 && pa::sweep_lds_bytes(W, p.sgn, n, s->dmax, p.threads) > max_lds) W >>= 1;
     }
-    if (pa::sweep_lds_bytes(W, n, s->dmax) > max_lds)
+    if (pa::sweep_lds_bytes(W, p.sgn, n, s->dmax, p.threads) > max_lds)
         return fail(PA_ERANGE, "graph of %d nodes does not fit LDS with %d replicas per workgroup", n, W);
     p.W = W;
-    p.threads = pa::kMaxThreads;
     p.nblk = (R + W - 1) / W;
 
     build_levels(s, sch->order, p);
+    build_blocks(s, p);
 
     // Weight-table sizes (needed for the workspace size even without tables).
     const long long span = s->nnz;  // E_r - E_min <= sum |w_ij| over both directions
@@ -357,6 +424,8 @@ static pa_status build_plan(pa_solver *s, const pa_schedule *sch, int R, Plan &p
     L.npos = take(sizeof(int) * n);
     L.sched = take(sizeof(int) * n);
     L.level_off = take(sizeof(int) * (p.n_levels + 1));
+    L.blocks = take((size_t)p.block_bytes * n + 64);
+    L.stream = take(sizeof(int) * p.stream.size());
     L.thr = take(sizeof(uint64_t) * (size_t)p.K * p.lmax1 * (s->dmax + 1));
     L.wtab = take(sizeof(uint64_t) * (size_t)total);
     L.wtab_off = take(sizeof(int) * p.K);
@@ -429,6 +498,10 @@ extern "C" pa_status pa_run(pa_solver *s, const pa_schedule *sch, int32_t R, uin
     HIP_TRY(hipMemcpyAsync(ws + L.npos, s->npos.data(), sizeof(int) * n, hipMemcpyHostToDevice, hs));
     HIP_TRY(hipMemcpyAsync(ws + L.sched, P.sched.data(), sizeof(int) * n, hipMemcpyHostToDevice, hs));
     HIP_TRY(hipMemcpyAsync(ws + L.level_off, P.level_off.data(), sizeof(int) * (P.n_levels + 1),
+                           hipMemcpyHostToDevice, hs));
+    HIP_TRY(hipMemcpyAsync(ws + L.blocks, P.blocks.data(), sizeof(uint16_t) * P.blocks.size(),
+                           hipMemcpyHostToDevice, hs));
+    HIP_TRY(hipMemcpyAsync(ws + L.stream, P.stream.data(), sizeof(int) * P.stream.size(),
                            hipMemcpyHostToDevice, hs));
     HIP_TRY(hipMemcpyAsync(ws + L.thr, P.thr.data(), sizeof(uint64_t) * P.thr.size(), hipMemcpyHostToDevice, hs));
     HIP_TRY(hipMemcpyAsync(ws + L.wtab, P.wtab.data(), sizeof(uint64_t) * P.wtab.size(), hipMemcpyHostToDevice, hs));
@@ -507,7 +580,12 @@ extern "C" pa_status pa_run(pa_solver *s, const pa_schedule *sch, int32_t R, uin
     }
 
     pa::SweepArgs sa;
-    sa.g = gd;
+    sa.n = n;
+    sa.dmax = s->dmax;
+    sa.blocks = reinterpret_cast<const uint4 *>(ws + L.blocks);
+    sa.block_u4 = P.block_bytes / 16;
+    sa.stream = reinterpret_cast<const int2 *>(ws + L.stream);
+    sa.qpad = P.qpad;
     sa.R = R;
     sa.S = P.S;
     sa.lmax1 = P.lmax1;
@@ -540,7 +618,7 @@ extern "C" pa_status pa_run(pa_solver *s, const pa_schedule *sch, int32_t R, uin
         sa.X = reinterpret_cast<uint64_t *>(ws + Xc);
         sa.E = reinterpret_cast<int *>(ws + Ec);
         if (s->timing) HIP_TRY(hipEventRecord(s->ev[2 * k], hs));
-        LAUNCH_TRY(pa::launch_sweep(P.W, P.threads, P.nblk, sa, hs));
+        LAUNCH_TRY(pa::launch_sweep(P.W, P.sgn, P.pre, P.threads, P.nblk, sa, hs));
         if (s->timing) {
             HIP_TRY(hipEventRecord(s->ev[2 * k + 1], hs));
             s->ev_used = k + 1;
@@ -722,7 +800,7 @@ extern "C" pa_status pa_get_launch_info(pa_solver *s, int64_t out[6])
     out[0] = P.W;
     out[1] = P.threads;
     out[2] = P.nblk;
-    out[3] = pa::sweep_lds_bytes(P.W, s->n, s->dmax);
+    out[3] = pa::sweep_lds_bytes(P.W, P.sgn, s->n, s->dmax, P.threads);
     out[4] = P.n_levels;
     out[5] = P.K;
     return PA_OK;

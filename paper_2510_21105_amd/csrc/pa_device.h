@@ -11,6 +11,7 @@
 //             one level are pairwise non-adjacent, and every node comes after
 //             all its earlier-ordered neighbours' levels.
 #pragma once
+#include <hip/hip_runtime.h>
 #include <stdint.h>
 
 namespace pa {
@@ -27,15 +28,20 @@ struct GraphDev {
 };
 
 struct SweepArgs {
-    GraphDev g;
+    int n;
+    int dmax;
     int R;            // real replicas
     int S;            // sweeps in this step
     int k;            // step index
     int lmax1;        // number of noise levels
     int n_levels;
     uint32_t seed_lo, seed_hi, inst;
-    const int *sched;
-    const int *level_off;
+    const int *sched;           // [n] nodes in level order
+    const int *level_off;       // [n_levels + 1]
+    const uint4 *blocks;        // [n][block_u4] adjacency block per schedule slot
+    int block_u4;
+    const int2 *stream;         // [waves][qpad] {first slot, max degree} per pass
+    int qpad;
     const uint64_t *thr;        // [K][lmax1][dmax+1]
     const int *as_state;        // [0] level
     uint64_t *X;                // [G][n]
@@ -97,8 +103,8 @@ struct InitArgs {
 // Host-side launchers (defined in pa_kernels.hip).
 int launch_init(const InitArgs &a, void *stream);
 int launch_energy(const InitArgs &a, void *stream);
-int sweep_lds_bytes(int W, int n, int dmax);
-int launch_sweep(int W, int threads, int nblk, const SweepArgs &a, void *stream);
+int sweep_lds_bytes(int W, int sgn, int n, int dmax, int threads);
+int launch_sweep(int W, int sgn, int pre, int threads, int nblk, const SweepArgs &a, void *stream);
 int launch_epilogue(const EpiArgs &a, void *stream);
 int launch_gather(const GatherArgs &a, void *stream);
 int launch_icm(const IcmArgs &a, void *stream);

@@ -159,89 +159,126 @@ __global__ __launch_bounds__(256) void energy_kernel(InitArgs a)
 
 // ---------------------------------------------------------------------------
 // Sweep kernel: all S sweeps of one step for W replicas per workgroup.
+//
+// LDS holds one W-bit spin word per node (and, for graphs with negative
+// weights, a complemented copy so that a negative edge reads "w_ij x_j = +1"
+// directly), one always-zero word that padded adjacency entries point to,
+// the step's threshold row, the level-ordered node list and a per-wave
+// buffer of Philox draws.
+//
+// The host lays the adjacency out as one fixed-size block per schedule slot
+// (node, degree, then the LDS word indices of the neighbours, padded with the
+// zero word), and gives every wave its stream of passes (first slot of the
+// pass and the largest degree among the pass's 64/W slots). A pass reads its
+// block from registers loaded one pass ahead, so no global-memory latency
+// sits on the per-attempt chain.
+//
+// Draws: one Philox call gives the draws of 4 consecutive replicas at one
+// node, so every fourth pass each of the 64 lanes computes one call for the
+// wave's next 4 passes and parks the 4 words in LDS; a pass then reads one
+// word per lane.
 // ---------------------------------------------------------------------------
 struct SweepLds {
-    size_t xs, thr, part, eblk, misc, total;
+    size_t xs, thr, part, eblk, misc, sched, draws, total;
 };
 
-__host__ __device__ inline SweepLds sweep_lds_layout(int W, int n, int dmax)
+__host__ __device__ inline SweepLds sweep_lds_layout(int W, int sgn, int n, int dmax, int nwaves)
 {
     SweepLds L;
+    const size_t words = (size_t)(sgn ? 2 * n : n) + 1;
     L.xs = 0;
-    L.thr = align16((size_t)n * (size_t)(W / 8));
+    L.thr = align16(words * (size_t)(W / 8));
     L.part = L.thr + align16((size_t)(dmax + 1) * 8);
     L.eblk = L.part + (size_t)kMaxThreads * 4;
     L.misc = L.eblk + 64 * 4;
-    L.total = L.misc + 16 * 8;
+    L.sched = L.misc + 16 * 8;
+    L.draws = L.sched + align16((size_t)n * 2);
+    L.total = L.draws + (size_t)nwaves * 256 * 4;
     return L;
 }
 
-int sweep_lds_bytes(int W, int n, int dmax) { return (int)sweep_lds_layout(W, n, dmax).total; }
+int sweep_lds_bytes(int W, int sgn, int n, int dmax, int threads)
+{
+    return (int)sweep_lds_layout(W, sgn, n, dmax, threads / 64).total;
+}
 
 template <int W>
 struct SpinTile {
-    // LDS spin words: W = 64 as two 32-bit halves per node, W = 32 one word,
-    // W = 16 one 16-bit word. bit(j, q) is the spin bit of block replica q.
+    // LDS spin words, addressed by word index: W = 64 as two 32-bit halves,
+    // W = 32 one 32-bit word, W = 16 one 16-bit word. bit(j, q) is the spin
+    // bit of block replica q in word j.
     unsigned char *base;
-    __device__ __forceinline__ int bit(int j, int q) const
+    static constexpr int SH = W == 16 ? 1 : (W == 32 ? 2 : 3);  // log2 bytes per word
+    __device__ __forceinline__ uint32_t read_at(uint32_t byte_off, int q) const
     {
         if constexpr (W == 64) {
-            const uint32_t *p = reinterpret_cast<const uint32_t *>(base);
-            return (int)((p[2 * j + (q >> 5)] >> (q & 31)) & 1u);
+            return *reinterpret_cast<const uint32_t *>(base + byte_off + 4 * (q >> 5));
         } else if constexpr (W == 32) {
-            const uint32_t *p = reinterpret_cast<const uint32_t *>(base);
-            return (int)((p[j] >> q) & 1u);
+            return *reinterpret_cast<const uint32_t *>(base + byte_off);
         } else {
-            const uint16_t *p = reinterpret_cast<const uint16_t *>(base);
-            return (int)((p[j] >> q) & 1u);
+            return *reinterpret_cast<const uint16_t *>(base + byte_off);
         }
     }
-    __device__ __forceinline__ void load(int i, uint64_t v, int sub)
+    __device__ __forceinline__ int bit_at(uint32_t byte_off, int q) const
+    {
+        return (int)((read_at(byte_off, q) >> (q & (W == 64 ? 31 : W - 1))) & 1u);
+    }
+    __device__ __forceinline__ int bit(int j, int q) const { return bit_at((uint32_t)j << SH, q); }
+    __device__ __forceinline__ void put(int j, uint64_t v)
     {
         if constexpr (W == 64) {
             uint32_t *p = reinterpret_cast<uint32_t *>(base);
-            p[2 * i] = (uint32_t)v;
-            p[2 * i + 1] = (uint32_t)(v >> 32);
+            p[2 * j] = (uint32_t)v;
+            p[2 * j + 1] = (uint32_t)(v >> 32);
         } else if constexpr (W == 32) {
-            reinterpret_cast<uint32_t *>(base)[i] = (uint32_t)(v >> (32 * sub));
+            reinterpret_cast<uint32_t *>(base)[j] = (uint32_t)v;
         } else {
-            reinterpret_cast<uint16_t *>(base)[i] = (uint16_t)(v >> (16 * sub));
+            reinterpret_cast<uint16_t *>(base)[j] = (uint16_t)v;
         }
     }
-    // Flip the spins of node i selected by the slot's ballot bits.
-    __device__ __forceinline__ void flip(int i, unsigned long long ballot, int slot, int rl)
-    {
-        if constexpr (W == 64) {
-            uint32_t *p = reinterpret_cast<uint32_t *>(base);
-            if (rl == 0) p[2 * i] ^= (uint32_t)ballot;
-            if (rl == 32) p[2 * i + 1] ^= (uint32_t)(ballot >> 32);
-        } else if constexpr (W == 32) {
-            if (rl == 0) reinterpret_cast<uint32_t *>(base)[i] ^= (uint32_t)(ballot >> (32 * slot));
-        } else {
-            if (rl == 0)
-                reinterpret_cast<uint16_t *>(base)[i] ^= (uint16_t)(ballot >> (16 * slot));
-        }
-    }
-    __device__ __forceinline__ void store(uint64_t *Xg, int i, int sub) const
+    __device__ __forceinline__ uint64_t get(int j) const
     {
         if constexpr (W == 64) {
             const uint32_t *p = reinterpret_cast<const uint32_t *>(base);
-            Xg[i] = ((uint64_t)p[2 * i + 1] << 32) | p[2 * i];
+            return ((uint64_t)p[2 * j + 1] << 32) | p[2 * j];
         } else if constexpr (W == 32) {
-            reinterpret_cast<uint32_t *>(Xg + i)[sub] = reinterpret_cast<const uint32_t *>(base)[i];
+            return reinterpret_cast<const uint32_t *>(base)[j];
         } else {
-            reinterpret_cast<uint16_t *>(Xg + i)[sub] = reinterpret_cast<const uint16_t *>(base)[i];
+            return reinterpret_cast<const uint16_t *>(base)[j];
+        }
+    }
+    // Flip the spins of word j selected by the slot's ballot bits.
+    __device__ __forceinline__ void flip(int j, unsigned long long ballot, int slot, int rl)
+    {
+        if constexpr (W == 64) {
+            uint32_t *p = reinterpret_cast<uint32_t *>(base);
+            if (rl == 0) p[2 * j] ^= (uint32_t)ballot;
+            if (rl == 32) p[2 * j + 1] ^= (uint32_t)(ballot >> 32);
+        } else if constexpr (W == 32) {
+            if (rl == 0) reinterpret_cast<uint32_t *>(base)[j] ^= (uint32_t)(ballot >> (32 * slot));
+        } else {
+            if (rl == 0) reinterpret_cast<uint16_t *>(base)[j] ^= (uint16_t)(ballot >> (16 * slot));
         }
     }
 };
 
 template <int W>
+__device__ __forceinline__ uint64_t field_of(uint64_t v, int sub)
+{
+    if constexpr (W == 64) return v;
+    else return (v >> (W * sub)) & ((1ull << W) - 1ull);
+}
+
+constexpr int kRegCols = 28;   // neighbour entries held in registers (64-byte block head)
+
+template <int W, bool SIGNED, bool PRE>
 __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    constexpr int NS = 64 / W;  // node slots per wave
-    const int n = a.g.n;
-    const int dmax = a.g.dmax;
+    constexpr int NS = 64 / W;      // node slots per wave
+    constexpr int GPS = W / 4;      // Philox calls per slot
+    constexpr int SH = SpinTile<W>::SH;
+    const int n = a.n;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -255,65 +292,122 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs a)
     const int r = r0 + rl;
     const int real = r < a.R ? 1 : 0;
 
-    const SweepLds L = sweep_lds_layout(W, n, dmax);
+    const SweepLds L = sweep_lds_layout(W, SIGNED ? 1 : 0, n, a.dmax, nwaves);
     SpinTile<W> xs{smem + L.xs};
     uint64_t *T = reinterpret_cast<uint64_t *>(smem + L.thr);
     int *part = reinterpret_cast<int *>(smem + L.part);
     int *Eblk = reinterpret_cast<int *>(smem + L.eblk);
     long long *misc = reinterpret_cast<long long *>(smem + L.misc);
-    // misc[0] local best E, misc[1] candidate key, misc[2] replica to snapshot
+    uint16_t *sched16 = reinterpret_cast<uint16_t *>(smem + L.sched);
+    uint32_t *dbuf = reinterpret_cast<uint32_t *>(smem + L.draws) + wave * 256;
 
     uint64_t *Xg = a.X + (size_t)grp * n;
-    for (int i = tid; i < n; i += blockDim.x) xs.load(i, Xg[i], sub);
+    for (int i = tid; i < n; i += blockDim.x) {
+        const uint64_t v = field_of<W>(Xg[i], sub);
+        xs.put(i, v);
+        if constexpr (SIGNED) xs.put(n + i, ~v & (W == 64 ? ~0ull : ((1ull << W) - 1ull)));
+        sched16[i] = (uint16_t)a.sched[i];
+    }
+    if (tid == 0) xs.put(SIGNED ? 2 * n : n, 0ull);
     const int level = a.as_state[0];
-    const uint64_t *trow = a.thr + ((size_t)a.k * a.lmax1 + level) * (size_t)(dmax + 1);
-    for (int m = tid; m <= dmax; m += blockDim.x) T[m] = trow[m];
+    const uint64_t *trow = a.thr + ((size_t)a.k * a.lmax1 + level) * (size_t)(a.dmax + 1);
+    for (int m = tid; m <= a.dmax; m += blockDim.x) T[m] = trow[m];
     if (tid < W) Eblk[tid] = (r0 + tid < a.R) ? a.E[r0 + tid] : 0;
     if (tid == 0) {
         misc[0] = a.best_E[0];
-        misc[1] = -1;  // reinterpreted as ~0ull: no candidate
+        misc[1] = -1;  // no candidate (reads back as ~0ull)
     }
     __syncthreads();
 
     const uint32_t k = (uint32_t)a.k;
+    const int2 *stream = a.stream + (size_t)wave * a.qpad;
+    const uint4 *blocks = a.blocks;
+    const int bu4 = a.block_u4;
+    const uint32_t rgrp = ((uint32_t)(r0 >> 2) + (uint32_t)((lane & 15) % GPS)) | (a.inst << 16);
+    const int fill_slot = (lane & 15) / GPS;
+    const int fill_pass = lane >> 4;
+
     int dE = 0;
     unsigned int att = 0, acc = 0;
     for (int s = 0; s < a.S; ++s) {
+        int q = 0;
+        int2 se = stream[0];
+        uint4 b0, b1, b2, b3;
+        {
+            // a wave without passes in this sweep still loads (and ignores) slot 0
+            const int t0 = se.x < 0 ? 0 : (se.x + slot_w < n ? se.x + slot_w : se.x);
+            const uint4 *bp = blocks + (size_t)t0 * bu4;
+            b0 = bp[0]; b1 = bp[1]; b2 = bp[2]; b3 = bp[3];
+        }
         for (int lv = 0; lv < a.n_levels; ++lv) {
             const int beg = a.level_off[lv], end = a.level_off[lv + 1];
-            for (int base = beg + wave * NS; base < end; base += nwaves * NS) {
-                const int slot = base + slot_w;
-                const bool active = slot < end;
+            const int Lsz = end - beg;
+            const int npass = Lsz > wave * NS ? (Lsz - wave * NS + nwaves * NS - 1) / (nwaves * NS) : 0;
+            for (int p = 0; p < npass; ++p, ++q) {
+                // Prefetch the next pass of this wave's stream (read-only graph data).
+                const int2 sn = stream[q + 1];
+                uint4 n0 = b0, n1 = b1, n2 = b2, n3 = b3;
+                if (sn.x >= 0) {
+                    const int tn = sn.x + slot_w < n ? sn.x + slot_w : sn.x;
+                    const uint4 *bp = blocks + (size_t)tn * bu4;
+                    n0 = bp[0]; n1 = bp[1]; n2 = bp[2]; n3 = bp[3];
+                }
+                if ((q & 3) == 0) {
+                    // Draws for passes q..q+3: lane computes one Philox call.
+                    const int2 e = stream[q + fill_pass];
+                    const int t2 = e.x + fill_slot;
+                    const uint32_t i2 = (e.x >= 0 && t2 < n) ? (uint32_t)sched16[t2] : 0u;
+                    const U4 o = philox10(U4{i2, (uint32_t)s, k, rgrp}, a.seed_lo, a.seed_hi);
+                    *reinterpret_cast<uint4 *>(dbuf + 4 * lane) = make_uint4(o.x, o.y, o.z, o.w);
+                    __builtin_amdgcn_wave_barrier();
+                }
+                const int t = se.x + slot_w;
+                const bool active = t < end;
+                const uint32_t w0 = b0.x;
+                const int node = (int)(w0 & 0xFFFFu);
+                const int d = (int)(w0 >> 16);
+                const int md = se.y;
+                const uint32_t cw[16] = {b0.x, b0.y, b0.z, b0.w, b1.x, b1.y, b1.z, b1.w,
+                                         b2.x, b2.y, b2.z, b2.w, b3.x, b3.y, b3.z, b3.w};
+                int c = 0;
+#pragma unroll
+                for (int kk = 0; kk < kRegCols; ++kk) {
+                    if (kk >= md) break;
+                    const uint32_t word = cw[2 + (kk >> 1)];
+                    uint32_t idx = (kk & 1) ? (word >> 16) : (word & 0xFFFFu);
+                    if constexpr (!PRE) idx <<= SH;
+                    c += xs.bit_at(idx, rl);
+                }
+                if (md > kRegCols) {
+                    const uint16_t *rest =
+                        reinterpret_cast<const uint16_t *>(blocks + (size_t)(active ? t : se.x) * bu4);
+                    for (int kk = kRegCols; kk < md; ++kk) {
+                        uint32_t idx = rest[4 + kk];
+                        if constexpr (!PRE) idx <<= SH;
+                        c += xs.bit_at(idx, rl);
+                    }
+                }
                 int accept = 0;
-                int i = 0;
                 if (active) {
-                    i = a.sched[slot];
-                    const int e0 = a.g.row_ptr[i], e1 = a.g.row_ptr[i + 1];
-                    const int em = e0 + a.g.npos[i];
-                    int c = 0;
-                    for (int e = e0; e < em; ++e) c += xs.bit(a.g.col[e], rl);
-                    int cn = 0;
-                    for (int e = em; e < e1; ++e) cn += xs.bit(a.g.col[e], rl);
-                    const int d = e1 - e0;
-                    c += (e1 - em) - cn;              // neighbours with w_ij x_j = +1
-                    const int u = xs.bit(i, rl) ? c : d - c;  // edges with w_ij x_i x_j = +1
-                    const int m = d - 2 * u;          // flip changes E by 2m
+                    const int u = xs.bit(node, rl) ? c : d - c;  // edges with w_ij x_i x_j = +1
+                    const int m = d - 2 * u;                     // flip changes E by 2m
                     if (m <= 0) {
                         accept = 1;
                     } else {
-                        const uint64_t t = T[m];
+                        const uint64_t th = T[m];
                         att += (unsigned)real;
-                        if (t != 0) {
-                            const uint32_t x = draw(a.seed_lo, a.seed_hi, a.inst, 0, (uint32_t)s, k,
-                                                    (uint32_t)i, (uint32_t)r);
-                            accept = (uint64_t)x < t ? 1 : 0;
-                        }
+                        if (th != 0) accept = (uint64_t)dbuf[(q & 3) * 64 + lane] < th ? 1 : 0;
                         acc += (unsigned)(real & accept);
                     }
                     if (accept) dE += 2 * m;
                 }
                 const unsigned long long bal = __ballot(accept);
-                if (active) xs.flip(i, bal, slot_w, rl);
+                if (active) {
+                    xs.flip(node, bal, slot_w, rl);
+                    if constexpr (SIGNED) xs.flip(n + node, bal, slot_w, rl);
+                }
+                se = sn;
+                b0 = n0; b1 = n1; b2 = n2; b3 = n3;
             }
             __syncthreads();
         }
@@ -324,17 +418,17 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs a)
         if (tid < W) {
             int sum = 0;
             for (int w = 0; w < nwaves; ++w)
-                for (int q = 0; q < NS; ++q) sum += part[w * 64 + q * W + tid];
+                for (int qq = 0; qq < NS; ++qq) sum += part[w * 64 + qq * W + tid];
             Eblk[tid] += sum;
         }
         __syncthreads();
         if (tid == 0) {
             long long be = misc[0];
             int arg = -1;
-            for (int q = 0; q < W && r0 + q < a.R; ++q)
-                if ((long long)Eblk[q] < be) {
-                    be = Eblk[q];
-                    arg = q;
+            for (int qq = 0; qq < W && r0 + qq < a.R; ++qq)
+                if ((long long)Eblk[qq] < be) {
+                    be = Eblk[qq];
+                    arg = qq;
                 }
             misc[2] = arg;
             if (arg >= 0) {
@@ -357,9 +451,14 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs a)
         __syncthreads();
     }
 
-    for (int i = tid; i < n; i += blockDim.x) xs.store(Xg, i, sub);
+    for (int i = tid; i < n; i += blockDim.x) {
+        const uint64_t v = xs.get(i);
+        if constexpr (W == 64) Xg[i] = v;
+        else if constexpr (W == 32) reinterpret_cast<uint32_t *>(Xg + i)[sub] = (uint32_t)v;
+        else reinterpret_cast<uint16_t *>(Xg + i)[sub] = (uint16_t)v;
+    }
     if (tid < W && r0 + tid < a.R) a.E[r0 + tid] = Eblk[tid];
-    long long at = wave_sum_ll((long long)att), ac = wave_sum_ll((long long)acc);
+    const long long at = wave_sum_ll((long long)att), ac = wave_sum_ll((long long)acc);
     if (lane == 0) {
         if (at) atomicAdd(&a.counters[0], (unsigned long long)at);
         if (ac) atomicAdd(&a.counters[1], (unsigned long long)ac);
@@ -725,27 +824,37 @@ int launch_energy(const InitArgs &a, void *stream)
     return check("energy_kernel");
 }
 
-template <int W>
-static int launch_sweep_w(int threads, int nblk, const SweepArgs &a, void *stream)
+template <int W, bool SG, bool PRE>
+static int launch_sweep_t(int threads, int nblk, const SweepArgs &a, void *stream)
 {
-    const int lds = sweep_lds_bytes(W, a.g.n, a.g.dmax);
+    const int lds = sweep_lds_bytes(W, SG ? 1 : 0, a.n, a.dmax, threads);
     static int configured = 0;
     if (configured < lds) {
-        if (hipFuncSetAttribute(reinterpret_cast<const void *>(&sweep_kernel<W>),
+        if (hipFuncSetAttribute(reinterpret_cast<const void *>(&sweep_kernel<W, SG, PRE>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess)
             return check("hipFuncSetAttribute(sweep)");
         configured = lds;
     }
-    hipLaunchKernelGGL(sweep_kernel<W>, dim3(nblk), dim3(threads), lds, (hipStream_t)stream, a);
+    hipLaunchKernelGGL((sweep_kernel<W, SG, PRE>), dim3(nblk), dim3(threads), lds,
+                       (hipStream_t)stream, a);
     return check("sweep_kernel");
 }
 
-int launch_sweep(int W, int threads, int nblk, const SweepArgs &a, void *stream)
+template <int W>
+static int launch_sweep_w(int sgn, int pre, int threads, int nblk, const SweepArgs &a, void *stream)
+{
+    if (sgn) return pre ? launch_sweep_t<W, true, true>(threads, nblk, a, stream)
+                        : launch_sweep_t<W, true, false>(threads, nblk, a, stream);
+    return pre ? launch_sweep_t<W, false, true>(threads, nblk, a, stream)
+               : launch_sweep_t<W, false, false>(threads, nblk, a, stream);
+}
+
+int launch_sweep(int W, int sgn, int pre, int threads, int nblk, const SweepArgs &a, void *stream)
 {
     switch (W) {
-    case 16: return launch_sweep_w<16>(threads, nblk, a, stream);
-    case 32: return launch_sweep_w<32>(threads, nblk, a, stream);
-    case 64: return launch_sweep_w<64>(threads, nblk, a, stream);
+    case 16: return launch_sweep_w<16>(sgn, pre, threads, nblk, a, stream);
+    case 32: return launch_sweep_w<32>(sgn, pre, threads, nblk, a, stream);
+    case 64: return launch_sweep_w<64>(sgn, pre, threads, nblk, a, stream);
     default:
         snprintf(g_err, sizeof g_err, "unsupported tile width %d", W);
         return -1;

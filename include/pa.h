@@ -59,8 +59,12 @@ typedef struct {
     int32_t as_frozen_inv;    /* raise only if frozen_inv * uphill_accepts < uphill_attempts, >= 1 */
     double as_gamma;          /* level l sweeps at beta_k * gamma^l, 0 < gamma <= 1 */
     int32_t nl_period;        /* non-local cluster moves every nl_period steps, 0 = off */
-    int32_t tile_replicas;    /* replicas per workgroup: 0 = automatic, else 16, 32 or 64;
-                                 results never depend on it                       */
+    int32_t sweep_kernel;     /* 0 = automatic; 1 = one node per lane over byte spin
+                                 records (max degree <= 127); 2 = one replica per lane
+                                 over bit spin words. Results never depend on it.  */
+    int32_t tile_replicas;    /* replicas per workgroup, 0 = automatic; kernel 1 takes
+                                 4, 8 or 16, kernel 2 takes 16, 32 or 64. Results
+                                 never depend on it.                              */
     int32_t record;           /* bit 0: keep per-step copy counts; bit 1: keep the
                                  initial population (both for pa_get_* below)     */
 } pa_schedule;
@@ -70,7 +74,7 @@ const char *pa_last_error(void);
 
 /*
  * Validate and keep a graph (host only; no device call).
- *   n        number of nodes, 2 <= n <= 65536
+ *   n        number of nodes, 2 <= n <= 32767
  *   row_ptr  n+1 int32, row_ptr[0] = 0, non-decreasing
  *   col      row_ptr[n] int32 neighbour ids in [0, n)
  *   w        row_ptr[n] int8 weights, each -1 or +1 (the G-set's binary
@@ -101,7 +105,7 @@ pa_status pa_workspace_bytes(const pa_solver *s, const pa_schedule *sch, int32_t
  * (device memory of at least pa_workspace_bytes, 256-byte aligned). The
  * workspace holds the results and must stay untouched until the last
  * pa_best_* / pa_get_* call for this run. Every output is a pure function of
- * (graph, schedule except tile_replicas, R, seed, instance).
+ * (graph, schedule except sweep_kernel and tile_replicas, R, seed, instance).
  *
  * Per step k = 0..K-1 (all integer on the device):
  *   1. S sweeps over `order`; for node i of replica r:
@@ -152,10 +156,11 @@ pa_status pa_get_step_stats(pa_solver *s, int64_t *out);
  * schedule.record bit 0. */
 pa_status pa_get_counts(pa_solver *s, int32_t *out);
 
-/* Launch facts of the last run: {replicas per workgroup, threads per
- * workgroup, workgroups per sweep launch, dynamic LDS bytes per workgroup,
- * levels per sweep, sweep launches}. */
-pa_status pa_get_launch_info(pa_solver *s, int64_t out[6]);
+/* Launch facts of the last run: {sweep kernel (1 or 2), replicas per
+ * workgroup, threads per workgroup, workgroups per sweep launch, dynamic LDS
+ * bytes per workgroup, dependency levels per sweep, workgroup rounds per
+ * sweep (kernel 1) or longest wave pass stream (kernel 2), sweep launches}. */
+pa_status pa_get_launch_info(pa_solver *s, int64_t out[8]);
 
 /* Timing mode for measurement: when on, pa_run records HIP events around
  * each sweep-kernel launch on the run's stream; pa_get_sweep_time then

@@ -51,6 +51,7 @@ pa_status hip_fail(hipError_t e, const char *what)
 
 constexpr int kMaxN = 32767;   // node ids and LDS word indices fit 16 bits
 constexpr int kMaxDegree = 4096;
+constexpr int kMaxBytesDegree = 127;   // byte counters of kernel 1 (2u must fit a byte)
 constexpr int kMaxR = 32768;
 constexpr size_t kAlign = 256;
 
@@ -65,10 +66,11 @@ struct Layout {
 struct Plan {
     int K = 0, S = 0, R = 0, G = 0, Rp = 0, W = 0, threads = 0, nblk = 0, nw32 = 0;
     int lmax1 = 1, n_levels = 0, record = 0;
-    int sgn = 0, pre = 0, block_bytes = 0, qpad = 0;
+    int kind = 2, sgn = 0, block_bytes = 0, qpad = 0, n_rounds = 0, flush_every = 1;
     std::vector<int> sched, level_off;
-    std::vector<uint16_t> blocks;   // [n][block_bytes / 2]
-    std::vector<int> stream;        // [waves][qpad][2]
+    std::vector<uint32_t> blocks;   // [n][block_bytes / 4] + 128 B
+    std::vector<int> stream;        // kernel 2: [waves][qpad][2]
+    std::vector<int> rounds;        // kernel 1: [n_rounds][4]
     std::vector<uint64_t> thr, wtab;
     std::vector<int> wtab_off, wtab_len;
     Layout L{};
@@ -209,9 +211,9 @@ static pa_status check_schedule(const pa_solver *s, const pa_schedule *sch, int 
     if (sch->nl_period < 0) return fail(PA_EINVAL, "nl_period must be >= 0");
     if (R < 1 || R > kMaxR) return fail(PA_ERANGE, "R=%d outside [1, %d]", R, kMaxR);
     if (sch->nl_period > 0 && (R & 1)) return fail(PA_EINVAL, "non-local moves pair replicas: R must be even");
-    if (sch->tile_replicas != 0 && sch->tile_replicas != 16 && sch->tile_replicas != 32 &&
-        sch->tile_replicas != 64)
-        return fail(PA_EINVAL, "tile_replicas must be 0, 16, 32 or 64");
+    if (sch->tile_replicas != 0 && sch->tile_replicas != 4 && sch->tile_replicas != 8 &&
+        sch->tile_replicas != 16 && sch->tile_replicas != 32 && sch->tile_replicas != 64)
+        return fail(PA_EINVAL, "tile_replicas must be 0, 4, 8, 16, 32 or 64");
     if (sch->record < 0 || sch->record > 3) return fail(PA_EINVAL, "record must be in [0, 3]");
     if (sch->order) {
         std::vector<char> seen(s->n, 0);
@@ -254,38 +256,83 @@ static void build_levels(const pa_solver *s, const int32_t *order, Plan &p)
         const int i = order ? order[t] : t;
         p.sched[fill[lvl[i]]++] = i;
     }
+    // Within a level the visiting order is free; grouping equal degrees
+    // keeps the slots of one pass (which loop to their largest degree) even.
+    auto deg = [&](int i) { return s->row_ptr[i + 1] - s->row_ptr[i]; };
+    for (int l = 0; l < nl; ++l)
+        std::stable_sort(p.sched.begin() + p.level_off[l], p.sched.begin() + p.level_off[l + 1],
+                         [&](int x, int y) { return deg(x) > deg(y); });
 }
 
 // Adjacency blocks in schedule order, one fixed-size block per slot:
-// u16 {node, degree, 0, 0, neighbour word indices..., zero-word padding}.
-// A neighbour joined by a negative weight points at the complemented copy of
-// its spin word (index n + j), so every entry counts "w_ij x_j = +1" by a
-// plain bit read. Indices are stored as LDS byte offsets when they fit.
-// Each wave's pass stream lists {first slot, largest degree in the pass}.
+// u32 {LDS byte offset of the node's spin word, degree, node, 0}, then the LDS
+// byte offsets of the neighbours' words, padded with the zero word to a
+// multiple of 4 entries. A neighbour joined by a negative weight points at
+// the complemented copy of its spin word (word n + j), so every entry counts
+// "w_ij x_j = +1" by a plain bit read. Each wave's pass stream lists
+// {first slot, largest degree among the pass's slots}.
 static void build_blocks(const pa_solver *s, Plan &p)
 {
     const int n = s->n;
+    const int cap = 4 * ((std::max(s->dmax, 1) + 3) / 4);
+    p.block_bytes = 16 + 4 * cap;
+    const int bw = p.block_bytes / 4;
+    if (p.kind == 1) {
+        // Kernel 1: entries are LDS byte offsets of W-byte spin records;
+        // negative edges point at the complemented record (n + j). Block n is
+        // an all-padding block for lanes without a node in a round.
+        const uint32_t W = (uint32_t)p.W;
+        const uint32_t zero = (uint32_t)(p.sgn ? 2 * n : n) * W;
+        p.blocks.assign((size_t)(n + 1) * bw + 32, zero);
+        for (int t = 0; t < n; ++t) {
+            const int i = p.sched[t];
+            uint32_t *b = &p.blocks[(size_t)t * bw];
+            const int e0 = s->row_ptr[i], e1 = s->row_ptr[i + 1];
+            b[0] = (uint32_t)i * W;
+            b[1] = (uint32_t)(e1 - e0);
+            b[2] = (uint32_t)i;
+            b[3] = 0;
+            for (int e = e0; e < e1; ++e) {
+                const int j = s->col[e];
+                const bool neg = e >= e0 + s->npos[i];
+                b[4 + (e - e0)] = (uint32_t)(neg ? n + j : j) * W;
+            }
+        }
+        uint32_t *pad = &p.blocks[(size_t)n * bw];
+        pad[1] = 0;
+        pad[2] = 0;
+        pad[3] = 0;
+        // Rounds: a level is cut into chunks of one node per thread.
+        p.rounds.clear();
+        for (int l = 0; l < p.n_levels; ++l) {
+            const int beg = p.level_off[l], end = p.level_off[l + 1];
+            for (int f = beg; f < end; f += p.threads) {
+                p.rounds.push_back(f);
+                p.rounds.push_back(end);
+                p.rounds.push_back(f + p.threads >= end ? 1 : 0);
+                p.rounds.push_back(0);
+            }
+        }
+        p.n_rounds = (int)p.rounds.size() / 4;
+        p.flush_every = std::max(1, 255 / std::max(s->dmax, 1));
+        return;
+    }
     const int NS = 64 / p.W, NW = p.threads / 64;
     const int sh = p.W == 16 ? 1 : (p.W == 32 ? 2 : 3);
-    const int words = p.sgn ? 2 * n : n;
-    const int dummy = words;
-    p.pre = ((long long)(words + 1) << sh) <= 65536 ? 1 : 0;
-    p.block_bytes = 16 * ((2 * (4 + s->dmax) + 15) / 16);
-    const int bw = p.block_bytes / 2;
-    auto enc = [&](int idx) { return (uint16_t)(p.pre ? (idx << sh) : idx); };
-    p.blocks.assign((size_t)n * bw + 32, enc(dummy));
+    const uint32_t zero = (uint32_t)(p.sgn ? 2 * n : n) << sh;
+    p.blocks.assign((size_t)n * bw + 32, zero);
     for (int t = 0; t < n; ++t) {
         const int i = p.sched[t];
-        uint16_t *b = &p.blocks[(size_t)t * bw];
+        uint32_t *b = &p.blocks[(size_t)t * bw];
         const int e0 = s->row_ptr[i], e1 = s->row_ptr[i + 1];
-        b[0] = (uint16_t)i;
-        b[1] = (uint16_t)(e1 - e0);
-        b[2] = 0;
+        b[0] = (uint32_t)i << sh;
+        b[1] = (uint32_t)(e1 - e0);
+        b[2] = (uint32_t)i;
         b[3] = 0;
         for (int e = e0; e < e1; ++e) {
             const int j = s->col[e];
             const bool neg = e >= e0 + s->npos[i];
-            b[4 + (e - e0)] = enc(neg ? n + j : j);
+            b[4 + (e - e0)] = (uint32_t)(neg ? n + j : j) << sh;
         }
     }
     std::vector<std::vector<int>> st(NW);
@@ -357,14 +404,39 @@ static pa_status build_plan(pa_solver *s, const pa_schedule *sch, int R, Plan &p
     }
     p.threads = pa::kMaxThreads;
     p.sgn = s->has_neg;
-    int W = sch->tile_replicas;
-    if (W == 0) {
-        W = 64;
-        while (W > 16 && (R + W - 1) / W < cus) W >>= 1;
-        while (W > 16 && pa::sweep_lds_bytes(W, p.sgn, n, s->dmax, p.threads) > max_lds) W >>= 1;
+    const int req = sch->sweep_kernel, tile = sch->tile_replicas;
+    if (req < 0 || req > 2) return fail(PA_EINVAL, "sweep_kernel must be 0, 1 or 2");
+    auto bytes_fit = [&](int W) { return pa::sweep_bytes_lds(W, p.sgn, n, s->dmax) <= max_lds; };
+    auto words_fit = [&](int W) { return pa::sweep_lds_bytes(W, p.sgn, n, s->dmax, p.threads) <= max_lds; };
+    int W = 0;
+    bool bytes_ok = s->dmax <= kMaxBytesDegree && (tile == 0 || tile <= 16);
+    if (req == 1 && !bytes_ok)
+        return fail(PA_EINVAL, "sweep kernel 1 needs max degree <= %d and tile 4, 8 or 16", kMaxBytesDegree);
+    if (req != 2 && bytes_ok) {
+        W = tile;
+        if (W == 0) {
+            W = 16;
+            while (W > 4 && ((R + W - 1) / W < cus || !bytes_fit(W))) W >>= 1;
+        }
+        if (!bytes_fit(W)) {
+            if (req == 1)
+                return fail(PA_ERANGE, "graph of %d nodes does not fit LDS with %d replicas per workgroup", n, W);
+            W = 0;
+        } else {
+            p.kind = 1;
+        }
     }
-    if (pa::sweep_lds_bytes(W, p.sgn, n, s->dmax, p.threads) > max_lds)
-        return fail(PA_ERANGE, "graph of %d nodes does not fit LDS with %d replicas per workgroup", n, W);
+    if (W == 0) {
+        if (req == 2 && tile != 0 && tile < 16) return fail(PA_EINVAL, "sweep kernel 2 takes tile 16, 32 or 64");
+        p.kind = 2;
+        W = tile >= 16 ? tile : 0;
+        if (W == 0) {
+            W = 64;
+            while (W > 16 && ((R + W - 1) / W < cus || !words_fit(W))) W >>= 1;
+        }
+        if (!words_fit(W))
+            return fail(PA_ERANGE, "graph of %d nodes does not fit LDS with %d replicas per workgroup", n, W);
+    }
     p.W = W;
     p.nblk = (R + W - 1) / W;
 
@@ -424,8 +496,8 @@ static pa_status build_plan(pa_solver *s, const pa_schedule *sch, int R, Plan &p
     L.npos = take(sizeof(int) * n);
     L.sched = take(sizeof(int) * n);
     L.level_off = take(sizeof(int) * (p.n_levels + 1));
-    L.blocks = take((size_t)p.block_bytes * n + 64);
-    L.stream = take(sizeof(int) * p.stream.size());
+    L.blocks = take(sizeof(uint32_t) * p.blocks.size());
+    L.stream = take(sizeof(int) * (p.kind == 1 ? p.rounds.size() : p.stream.size()));
     L.thr = take(sizeof(uint64_t) * (size_t)p.K * p.lmax1 * (s->dmax + 1));
     L.wtab = take(sizeof(uint64_t) * (size_t)total);
     L.wtab_off = take(sizeof(int) * p.K);
@@ -499,10 +571,14 @@ extern "C" pa_status pa_run(pa_solver *s, const pa_schedule *sch, int32_t R, uin
     HIP_TRY(hipMemcpyAsync(ws + L.sched, P.sched.data(), sizeof(int) * n, hipMemcpyHostToDevice, hs));
     HIP_TRY(hipMemcpyAsync(ws + L.level_off, P.level_off.data(), sizeof(int) * (P.n_levels + 1),
                            hipMemcpyHostToDevice, hs));
-    HIP_TRY(hipMemcpyAsync(ws + L.blocks, P.blocks.data(), sizeof(uint16_t) * P.blocks.size(),
+    HIP_TRY(hipMemcpyAsync(ws + L.blocks, P.blocks.data(), sizeof(uint32_t) * P.blocks.size(),
                            hipMemcpyHostToDevice, hs));
-    HIP_TRY(hipMemcpyAsync(ws + L.stream, P.stream.data(), sizeof(int) * P.stream.size(),
-                           hipMemcpyHostToDevice, hs));
+    if (P.kind == 1)
+        HIP_TRY(hipMemcpyAsync(ws + L.stream, P.rounds.data(), sizeof(int) * P.rounds.size(),
+                               hipMemcpyHostToDevice, hs));
+    else
+        HIP_TRY(hipMemcpyAsync(ws + L.stream, P.stream.data(), sizeof(int) * P.stream.size(),
+                               hipMemcpyHostToDevice, hs));
     HIP_TRY(hipMemcpyAsync(ws + L.thr, P.thr.data(), sizeof(uint64_t) * P.thr.size(), hipMemcpyHostToDevice, hs));
     HIP_TRY(hipMemcpyAsync(ws + L.wtab, P.wtab.data(), sizeof(uint64_t) * P.wtab.size(), hipMemcpyHostToDevice, hs));
     HIP_TRY(hipMemcpyAsync(ws + L.wtab_off, P.wtab_off.data(), sizeof(int) * P.K, hipMemcpyHostToDevice, hs));
@@ -586,6 +662,9 @@ extern "C" pa_status pa_run(pa_solver *s, const pa_schedule *sch, int32_t R, uin
     sa.block_u4 = P.block_bytes / 16;
     sa.stream = reinterpret_cast<const int2 *>(ws + L.stream);
     sa.qpad = P.qpad;
+    sa.rounds = reinterpret_cast<const int4 *>(ws + L.stream);
+    sa.n_rounds = P.n_rounds;
+    sa.flush_every = P.flush_every;
     sa.R = R;
     sa.S = P.S;
     sa.lmax1 = P.lmax1;
@@ -618,7 +697,8 @@ extern "C" pa_status pa_run(pa_solver *s, const pa_schedule *sch, int32_t R, uin
         sa.X = reinterpret_cast<uint64_t *>(ws + Xc);
         sa.E = reinterpret_cast<int *>(ws + Ec);
         if (s->timing) HIP_TRY(hipEventRecord(s->ev[2 * k], hs));
-        LAUNCH_TRY(pa::launch_sweep(P.W, P.sgn, P.pre, P.threads, P.nblk, sa, hs));
+        if (P.kind == 1) LAUNCH_TRY(pa::launch_sweep_bytes(P.W, P.sgn, P.threads, P.nblk, sa, hs));
+        else LAUNCH_TRY(pa::launch_sweep(P.W, P.sgn, P.threads, P.nblk, sa, hs));
         if (s->timing) {
             HIP_TRY(hipEventRecord(s->ev[2 * k + 1], hs));
             s->ev_used = k + 1;
@@ -792,17 +872,20 @@ extern "C" pa_status pa_get_counts(pa_solver *s, int32_t *out)
     return fetch(s, out, s->plan.L.counts, sizeof(int) * (size_t)s->plan.K * s->plan.R);
 }
 
-extern "C" pa_status pa_get_launch_info(pa_solver *s, int64_t out[6])
+extern "C" pa_status pa_get_launch_info(pa_solver *s, int64_t out[8])
 {
     if (!out) return fail(PA_EINVAL, "null output");
     if (!s || !s->has_run) return fail(PA_ESTATE, "no completed pa_run on this solver");
     const Plan &P = s->plan;
-    out[0] = P.W;
-    out[1] = P.threads;
-    out[2] = P.nblk;
-    out[3] = pa::sweep_lds_bytes(P.W, P.sgn, s->n, s->dmax, P.threads);
-    out[4] = P.n_levels;
-    out[5] = P.K;
+    out[0] = P.kind;
+    out[1] = P.W;
+    out[2] = P.threads;
+    out[3] = P.nblk;
+    out[4] = P.kind == 1 ? pa::sweep_bytes_lds(P.W, P.sgn, s->n, s->dmax)
+                         : pa::sweep_lds_bytes(P.W, P.sgn, s->n, s->dmax, P.threads);
+    out[5] = P.n_levels;
+    out[6] = P.kind == 1 ? P.n_rounds : P.qpad - 4;
+    out[7] = P.K;
     return PA_OK;
 }
 

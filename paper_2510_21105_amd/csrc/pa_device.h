@@ -38,10 +38,13 @@ struct SweepArgs {
     uint32_t seed_lo, seed_hi, inst;
     const int *sched;           // [n] nodes in level order
     const int *level_off;       // [n_levels + 1]
-    const uint4 *blocks;        // [n][block_u4] adjacency block per schedule slot
+    const uint4 *blocks;        // [n][block_u4] adjacency block per schedule slot (+128 B pad)
     int block_u4;
     const int2 *stream;         // [waves][qpad] {first slot, max degree} per pass
     int qpad;
+    const int4 *rounds;         // [n_rounds] {first slot, level end, last round of level, 0}
+    int n_rounds;
+    int flush_every;            // rounds between flushes of the byte energy accumulators
     const uint64_t *thr;        // [K][lmax1][dmax+1]
     const int *as_state;        // [0] level
     uint64_t *X;                // [G][n]
@@ -104,7 +107,9 @@ struct InitArgs {
 int launch_init(const InitArgs &a, void *stream);
 int launch_energy(const InitArgs &a, void *stream);
 int sweep_lds_bytes(int W, int sgn, int n, int dmax, int threads);
-int launch_sweep(int W, int sgn, int pre, int threads, int nblk, const SweepArgs &a, void *stream);
+int launch_sweep(int W, int sgn, int threads, int nblk, const SweepArgs &a, void *stream);
+int sweep_bytes_lds(int W, int sgn, int n, int dmax);
+int launch_sweep_bytes(int W, int sgn, int threads, int nblk, const SweepArgs &a, void *stream);
 int launch_epilogue(const EpiArgs &a, void *stream);
 int launch_gather(const GatherArgs &a, void *stream);
 int launch_icm(const IcmArgs &a, void *stream);

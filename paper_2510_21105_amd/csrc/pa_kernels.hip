@@ -160,18 +160,19 @@ __global__ __launch_bounds__(256) void energy_kernel(InitArgs a)
 // ---------------------------------------------------------------------------
 // Sweep kernel: all S sweeps of one step for W replicas per workgroup.
 //
-// LDS holds one W-bit spin word per node (and, for graphs with negative
-// weights, a complemented copy so that a negative edge reads "w_ij x_j = +1"
-// directly), one always-zero word that padded adjacency entries point to,
-// the step's threshold row, the level-ordered node list and a per-wave
-// buffer of Philox draws.
+// LDS (dynamic, starting at LDS address 0 -- the kernel declares no static
+// LDS, so the host can hand out raw LDS byte offsets) holds one W-bit spin
+// word per node, for graphs with negative weights a complemented copy (so a
+// negative edge reads "w_ij x_j = +1" directly), one always-zero word that
+// padded adjacency entries point to, the step's threshold row, the
+// level-ordered node list and a per-wave buffer of Philox draws.
 //
-// The host lays the adjacency out as one fixed-size block per schedule slot
-// (node, degree, then the LDS word indices of the neighbours, padded with the
-// zero word), and gives every wave its stream of passes (first slot of the
-// pass and the largest degree among the pass's 64/W slots). A pass reads its
-// block from registers loaded one pass ahead, so no global-memory latency
-// sits on the per-attempt chain.
+// The host lays the adjacency out as one fixed-size block per schedule slot:
+// u32 {LDS byte offset of the node's word, degree, node id, 0} followed by
+// the LDS byte offsets of the neighbours' words, padded with the zero word.
+// Every wave gets its stream of passes (first slot, largest degree among the
+// pass's 64/W slots); a pass keeps its block in registers, loaded one pass
+// ahead, so a neighbour costs one LDS read, one bit extract and half an add.
 //
 // Draws: one Philox call gives the draws of 4 consecutive replicas at one
 // node, so every fourth pass each of the 64 lanes computes one call for the
@@ -202,65 +203,24 @@ int sweep_lds_bytes(int W, int sgn, int n, int dmax, int threads)
     return (int)sweep_lds_layout(W, sgn, n, dmax, threads / 64).total;
 }
 
+typedef __attribute__((address_space(3))) uint16_t lds_u16;
+typedef __attribute__((address_space(3))) uint32_t lds_u32;
+
+// Spin words in LDS, addressed by byte offset. For W = 64 a lane reads the
+// 32-bit half that holds its replica (lanes 32..63: offset + 4).
 template <int W>
-struct SpinTile {
-    // LDS spin words, addressed by word index: W = 64 as two 32-bit halves,
-    // W = 32 one 32-bit word, W = 16 one 16-bit word. bit(j, q) is the spin
-    // bit of block replica q in word j.
-    unsigned char *base;
-    static constexpr int SH = W == 16 ? 1 : (W == 32 ? 2 : 3);  // log2 bytes per word
-    __device__ __forceinline__ uint32_t read_at(uint32_t byte_off, int q) const
-    {
-        if constexpr (W == 64) {
-            return *reinterpret_cast<const uint32_t *>(base + byte_off + 4 * (q >> 5));
-        } else if constexpr (W == 32) {
-            return *reinterpret_cast<const uint32_t *>(base + byte_off);
-        } else {
-            return *reinterpret_cast<const uint16_t *>(base + byte_off);
-        }
-    }
-    __device__ __forceinline__ int bit_at(uint32_t byte_off, int q) const
-    {
-        return (int)((read_at(byte_off, q) >> (q & (W == 64 ? 31 : W - 1))) & 1u);
-    }
-    __device__ __forceinline__ int bit(int j, int q) const { return bit_at((uint32_t)j << SH, q); }
-    __device__ __forceinline__ void put(int j, uint64_t v)
-    {
-        if constexpr (W == 64) {
-            uint32_t *p = reinterpret_cast<uint32_t *>(base);
-            p[2 * j] = (uint32_t)v;
-            p[2 * j + 1] = (uint32_t)(v >> 32);
-        } else if constexpr (W == 32) {
-            reinterpret_cast<uint32_t *>(base)[j] = (uint32_t)v;
-        } else {
-            reinterpret_cast<uint16_t *>(base)[j] = (uint16_t)v;
-        }
-    }
-    __device__ __forceinline__ uint64_t get(int j) const
-    {
-        if constexpr (W == 64) {
-            const uint32_t *p = reinterpret_cast<const uint32_t *>(base);
-            return ((uint64_t)p[2 * j + 1] << 32) | p[2 * j];
-        } else if constexpr (W == 32) {
-            return reinterpret_cast<const uint32_t *>(base)[j];
-        } else {
-            return reinterpret_cast<const uint16_t *>(base)[j];
-        }
-    }
-    // Flip the spins of word j selected by the slot's ballot bits.
-    __device__ __forceinline__ void flip(int j, unsigned long long ballot, int slot, int rl)
-    {
-        if constexpr (W == 64) {
-            uint32_t *p = reinterpret_cast<uint32_t *>(base);
-            if (rl == 0) p[2 * j] ^= (uint32_t)ballot;
-            if (rl == 32) p[2 * j + 1] ^= (uint32_t)(ballot >> 32);
-        } else if constexpr (W == 32) {
-            if (rl == 0) reinterpret_cast<uint32_t *>(base)[j] ^= (uint32_t)(ballot >> (32 * slot));
-        } else {
-            if (rl == 0) reinterpret_cast<uint16_t *>(base)[j] ^= (uint16_t)(ballot >> (16 * slot));
-        }
-    }
-};
+__device__ __forceinline__ uint32_t lds_word(uint32_t off)
+{
+    if constexpr (W == 16) return *(lds_u16 *)(uintptr_t)off;
+    else return *(lds_u32 *)(uintptr_t)off;
+}
+
+template <int W>
+__device__ __forceinline__ void lds_put(uint32_t off, uint32_t v)
+{
+    if constexpr (W == 16) *(lds_u16 *)(uintptr_t)off = (uint16_t)v;
+    else *(lds_u32 *)(uintptr_t)off = v;
+}
 
 template <int W>
 __device__ __forceinline__ uint64_t field_of(uint64_t v, int sub)
@@ -269,15 +229,30 @@ __device__ __forceinline__ uint64_t field_of(uint64_t v, int sub)
     else return (v >> (W * sub)) & ((1ull << W) - 1ull);
 }
 
-constexpr int kRegCols = 28;   // neighbour entries held in registers (64-byte block head)
+constexpr int kRegCols = 28;   // neighbour entries held in registers (128-byte block head)
 
-template <int W, bool SIGNED, bool PRE>
+// Philox4x32-10 written with 64-bit products (one v_mad_u64_u32 per product).
+__device__ __forceinline__ U4 philox10_wide(U4 c, uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int round = 0; round < 10; ++round) {
+        const uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c.x;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c.z;
+        c = U4{(uint32_t)(p1 >> 32) ^ c.y ^ k0, (uint32_t)p1, (uint32_t)(p0 >> 32) ^ c.w ^ k1,
+               (uint32_t)p0};
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return c;
+}
+
+template <int W, bool SIGNED>
 __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int NS = 64 / W;      // node slots per wave
     constexpr int GPS = W / 4;      // Philox calls per slot
-    constexpr int SH = SpinTile<W>::SH;
+    constexpr int SH = W == 16 ? 1 : (W == 32 ? 2 : 3);
     const int n = a.n;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -289,29 +264,45 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs a)
     const int sub = (r0 & 63) / W;
     const int slot_w = lane / W;
     const int rl = lane % W;
+    const int bitpos = rl & 31;
+    const uint32_t half4 = W == 64 ? 4u * (uint32_t)(rl >> 5) : 0u;
     const int r = r0 + rl;
     const int real = r < a.R ? 1 : 0;
 
     const SweepLds L = sweep_lds_layout(W, SIGNED ? 1 : 0, n, a.dmax, nwaves);
-    SpinTile<W> xs{smem + L.xs};
     uint64_t *T = reinterpret_cast<uint64_t *>(smem + L.thr);
     int *part = reinterpret_cast<int *>(smem + L.part);
     int *Eblk = reinterpret_cast<int *>(smem + L.eblk);
     long long *misc = reinterpret_cast<long long *>(smem + L.misc);
     uint16_t *sched16 = reinterpret_cast<uint16_t *>(smem + L.sched);
     uint32_t *dbuf = reinterpret_cast<uint32_t *>(smem + L.draws) + wave * 256;
+    const uint32_t comp = (uint32_t)n << SH;  // byte distance to the complemented copy
 
     uint64_t *Xg = a.X + (size_t)grp * n;
     for (int i = tid; i < n; i += blockDim.x) {
         const uint64_t v = field_of<W>(Xg[i], sub);
-        xs.put(i, v);
-        if constexpr (SIGNED) xs.put(n + i, ~v & (W == 64 ? ~0ull : ((1ull << W) - 1ull)));
+        const uint32_t off = (uint32_t)i << SH;
+        if constexpr (W == 64) {
+            lds_put<W>(off, (uint32_t)v);
+            lds_put<W>(off + 4, (uint32_t)(v >> 32));
+            if constexpr (SIGNED) {
+                lds_put<W>(comp + off, ~(uint32_t)v);
+                lds_put<W>(comp + off + 4, ~(uint32_t)(v >> 32));
+            }
+        } else {
+            lds_put<W>(off, (uint32_t)v);
+            if constexpr (SIGNED) lds_put<W>(comp + off, ~(uint32_t)v);
+        }
         sched16[i] = (uint16_t)a.sched[i];
     }
-    if (tid == 0) xs.put(SIGNED ? 2 * n : n, 0ull);
+    if (tid == 0) {
+        const uint32_t zoff = (uint32_t)(SIGNED ? 2 * n : n) << SH;
+        lds_put<W>(zoff, 0u);
+        if constexpr (W == 64) lds_put<W>(zoff + 4, 0u);
+    }
     const int level = a.as_state[0];
     const uint64_t *trow = a.thr + ((size_t)a.k * a.lmax1 + level) * (size_t)(a.dmax + 1);
-    for (int m = tid; m <= a.dmax; m += blockDim.x) T[m] = trow[m];
+    for (int m = tid; m <= a.dmax; m += blockDim.x) T[m] = m == 0 ? (1ull << 32) : trow[m];
     if (tid < W) Eblk[tid] = (r0 + tid < a.R) ? a.E[r0 + tid] : 0;
     if (tid == 0) {
         misc[0] = a.best_E[0];
@@ -332,12 +323,12 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs a)
     for (int s = 0; s < a.S; ++s) {
         int q = 0;
         int2 se = stream[0];
-        uint4 b0, b1, b2, b3;
+        uint4 h, c0, c1, c2, c3, c4, c5, c6;
         {
             // a wave without passes in this sweep still loads (and ignores) slot 0
             const int t0 = se.x < 0 ? 0 : (se.x + slot_w < n ? se.x + slot_w : se.x);
             const uint4 *bp = blocks + (size_t)t0 * bu4;
-            b0 = bp[0]; b1 = bp[1]; b2 = bp[2]; b3 = bp[3];
+            h = bp[0]; c0 = bp[1]; c1 = bp[2]; c2 = bp[3]; c3 = bp[4]; c4 = bp[5]; c5 = bp[6]; c6 = bp[7];
         }
         for (int lv = 0; lv < a.n_levels; ++lv) {
             const int beg = a.level_off[lv], end = a.level_off[lv + 1];
@@ -346,68 +337,79 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs a)
             for (int p = 0; p < npass; ++p, ++q) {
                 // Prefetch the next pass of this wave's stream (read-only graph data).
                 const int2 sn = stream[q + 1];
-                uint4 n0 = b0, n1 = b1, n2 = b2, n3 = b3;
+                uint4 nh = h, n0 = c0, n1 = c1, n2 = c2, n3 = c3, n4 = c4, n5 = c5, n6 = c6;
                 if (sn.x >= 0) {
                     const int tn = sn.x + slot_w < n ? sn.x + slot_w : sn.x;
                     const uint4 *bp = blocks + (size_t)tn * bu4;
-                    n0 = bp[0]; n1 = bp[1]; n2 = bp[2]; n3 = bp[3];
+                    nh = bp[0]; n0 = bp[1]; n1 = bp[2]; n2 = bp[3]; n3 = bp[4]; n4 = bp[5]; n5 = bp[6]; n6 = bp[7];
                 }
                 if ((q & 3) == 0) {
-                    // Draws for passes q..q+3: lane computes one Philox call.
+                    // Draws for passes q..q+3: every lane computes one Philox call.
                     const int2 e = stream[q + fill_pass];
                     const int t2 = e.x + fill_slot;
                     const uint32_t i2 = (e.x >= 0 && t2 < n) ? (uint32_t)sched16[t2] : 0u;
-                    const U4 o = philox10(U4{i2, (uint32_t)s, k, rgrp}, a.seed_lo, a.seed_hi);
+                    const U4 o = philox10_wide(U4{i2, (uint32_t)s, k, rgrp}, a.seed_lo, a.seed_hi);
                     *reinterpret_cast<uint4 *>(dbuf + 4 * lane) = make_uint4(o.x, o.y, o.z, o.w);
                     __builtin_amdgcn_wave_barrier();
                 }
                 const int t = se.x + slot_w;
                 const bool active = t < end;
-                const uint32_t w0 = b0.x;
-                const int node = (int)(w0 & 0xFFFFu);
-                const int d = (int)(w0 >> 16);
+                const uint32_t noff = h.x;
+                const int d = (int)h.y;
                 const int md = se.y;
-                const uint32_t cw[16] = {b0.x, b0.y, b0.z, b0.w, b1.x, b1.y, b1.z, b1.w,
-                                         b2.x, b2.y, b2.z, b2.w, b3.x, b3.y, b3.z, b3.w};
-                int c = 0;
-#pragma unroll
-                for (int kk = 0; kk < kRegCols; ++kk) {
-                    if (kk >= md) break;
-                    const uint32_t word = cw[2 + (kk >> 1)];
-                    uint32_t idx = (kk & 1) ? (word >> 16) : (word & 0xFFFFu);
-                    if constexpr (!PRE) idx <<= SH;
-                    c += xs.bit_at(idx, rl);
-                }
-                if (md > kRegCols) {
-                    const uint16_t *rest =
-                        reinterpret_cast<const uint16_t *>(blocks + (size_t)(active ? t : se.x) * bu4);
-                    for (int kk = kRegCols; kk < md; ++kk) {
-                        uint32_t idx = rest[4 + kk];
-                        if constexpr (!PRE) idx <<= SH;
-                        c += xs.bit_at(idx, rl);
+                // Count neighbours with w_ij x_j = +1 (padding reads the zero word).
+                int cnt = 0;
+#define PA_NB(off) (int)__builtin_amdgcn_ubfe(lds_word<W>((off) + half4), bitpos, 1)
+#define PA_CHUNK(v) cnt += PA_NB(v.x) + PA_NB(v.y) + PA_NB(v.z) + PA_NB(v.w)
+                PA_CHUNK(c0);
+                if (md > 4) {
+                    PA_CHUNK(c1);
+                    if (md > 8) {
+                        PA_CHUNK(c2);
+                        if (md > 12) {
+                            PA_CHUNK(c3);
+                            if (md > 16) {
+                                PA_CHUNK(c4);
+                                if (md > 20) {
+                                    PA_CHUNK(c5);
+                                    if (md > 24) {
+                                        PA_CHUNK(c6);
+                                        if (md > kRegCols) {
+                                            const uint32_t *rest = reinterpret_cast<const uint32_t *>(
+                                                blocks + (size_t)(active ? t : se.x) * bu4) + 4;
+                                            for (int kk = kRegCols; kk < md; ++kk) cnt += PA_NB(rest[kk]);
+                                        }
+                                    }
+                                }
+                            }
+                        }
                     }
                 }
-                int accept = 0;
-                if (active) {
-                    const int u = xs.bit(node, rl) ? c : d - c;  // edges with w_ij x_i x_j = +1
-                    const int m = d - 2 * u;                     // flip changes E by 2m
-                    if (m <= 0) {
-                        accept = 1;
-                    } else {
-                        const uint64_t th = T[m];
-                        att += (unsigned)real;
-                        if (th != 0) accept = (uint64_t)dbuf[(q & 3) * 64 + lane] < th ? 1 : 0;
-                        acc += (unsigned)(real & accept);
-                    }
-                    if (accept) dE += 2 * m;
-                }
+#undef PA_CHUNK
+#undef PA_NB
+                const uint32_t word = lds_word<W>(noff + half4);
+                const int bi = (int)__builtin_amdgcn_ubfe(word, bitpos, 1);
+                const int u = bi ? cnt : d - cnt;   // edges with w_ij x_i x_j = +1
+                const int m = d - 2 * u;            // flip changes E by 2m
+                const int mm = m > 0 ? m : 0;       // T[0] = 2^32: downhill always accepted
+                const uint32_t dr = dbuf[(q & 3) * 64 + lane];
+                const int accept = (active && (uint64_t)dr < T[mm]) ? 1 : 0;
+                const int up = (m > 0 && active) ? real : 0;
+                att += (unsigned)up;
+                acc += (unsigned)(up & accept);
+                dE += accept ? 2 * m : 0;
                 const unsigned long long bal = __ballot(accept);
                 if (active) {
-                    xs.flip(node, bal, slot_w, rl);
-                    if constexpr (SIGNED) xs.flip(n + node, bal, slot_w, rl);
+                    uint32_t fm;
+                    if constexpr (W == 64) fm = rl < 32 ? (uint32_t)bal : (uint32_t)(bal >> 32);
+                    else if constexpr (W == 32) fm = slot_w ? (uint32_t)(bal >> 32) : (uint32_t)bal;
+                    else fm = (uint32_t)(bal >> (16 * slot_w)) & 0xFFFFu;
+                    const uint32_t nw = word ^ fm;
+                    lds_put<W>(noff + half4, nw);
+                    if constexpr (SIGNED) lds_put<W>(comp + noff + half4, ~nw);
                 }
                 se = sn;
-                b0 = n0; b1 = n1; b2 = n2; b3 = n3;
+                h = nh; c0 = n0; c1 = n1; c2 = n2; c3 = n3; c4 = n4; c5 = n5; c6 = n6;
             }
             __syncthreads();
         }
@@ -441,10 +443,12 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs a)
         const int sq = (int)misc[2];
         if (sq >= 0) {
             uint32_t *dst = a.snap + (size_t)blk * a.nw32;
+            const uint32_t sh4 = W == 64 ? 4u * (uint32_t)(sq >> 5) : 0u;
             for (int w = tid; w < a.nw32; w += blockDim.x) {
                 uint32_t bits = 0;
                 const int ib = w * 32;
-                for (int b = 0; b < 32 && ib + b < n; ++b) bits |= (uint32_t)xs.bit(ib + b, sq) << b;
+                for (int b = 0; b < 32 && ib + b < n; ++b)
+                    bits |= __builtin_amdgcn_ubfe(lds_word<W>(((uint32_t)(ib + b) << SH) + sh4), sq & 31, 1) << b;
                 dst[w] = bits;
             }
         }
@@ -452,10 +456,381 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs a)
     }
 
     for (int i = tid; i < n; i += blockDim.x) {
-        const uint64_t v = xs.get(i);
-        if constexpr (W == 64) Xg[i] = v;
-        else if constexpr (W == 32) reinterpret_cast<uint32_t *>(Xg + i)[sub] = (uint32_t)v;
-        else reinterpret_cast<uint16_t *>(Xg + i)[sub] = (uint16_t)v;
+        const uint32_t off = (uint32_t)i << SH;
+        if constexpr (W == 64) Xg[i] = ((uint64_t)lds_word<W>(off + 4) << 32) | lds_word<W>(off);
+        else if constexpr (W == 32) reinterpret_cast<uint32_t *>(Xg + i)[sub] = lds_word<W>(off);
+        else reinterpret_cast<uint16_t *>(Xg + i)[sub] = (uint16_t)lds_word<W>(off);
+    }
+    if (tid < W && r0 + tid < a.R) a.E[r0 + tid] = Eblk[tid];
+    const long long at = wave_sum_ll((long long)att), ac = wave_sum_ll((long long)acc);
+    if (lane == 0) {
+        if (at) atomicAdd(&a.counters[0], (unsigned long long)at);
+        if (ac) atomicAdd(&a.counters[1], (unsigned long long)ac);
+    }
+    if (tid == 0) a.cand[blk] = (unsigned long long)misc[1];
+}
+
+// ---------------------------------------------------------------------------
+// Node-per-lane sweep kernel (multi-spin coding over W replicas).
+//
+// A workgroup owns W = 4, 8 or 16 replicas for a whole step. LDS holds one
+// W-byte record per node (byte b = spin of block replica b, 1 for +1), for
+// signed graphs a complemented record per node (so a negative edge reads
+// "w_ij x_j = +1" directly), and an all-zero record for padding. Each lane
+// handles one node of the current dependency level for all W replicas at
+// once: the neighbours' records are added bytewise (one LDS read and W/4
+// adds per neighbour give the W counts), and the per-replica Metropolis
+// tests run on the packed bytes. A lane computes exactly the W/4 Philox
+// calls its replicas need (one call = 4 consecutive replicas at one node).
+// Adjacency blocks are read once per node and prefetched one round ahead
+// into the other of two register buffers.
+//
+// Bytewise arithmetic needs every count below 256, so this path serves
+// graphs with maximum degree <= 255; the per-replica energy changes are
+// gathered in byte accumulators that are flushed before they can overflow.
+// ---------------------------------------------------------------------------
+struct BytesLds {
+    size_t rec, thr, edelta, misc, total;
+};
+
+__host__ __device__ inline BytesLds bytes_lds_layout(int W, int sgn, int n, int dmax)
+{
+    BytesLds L;
+    const size_t recs = (size_t)(sgn ? 2 * n : n) + 1;
+    L.rec = 0;
+    L.thr = align16(recs * (size_t)W);
+    L.edelta = L.thr + align16((size_t)(dmax + 1) * 8);
+    L.misc = L.edelta + 64 * 4;
+    L.total = L.misc + 16 * 8;
+    return L;
+}
+
+int sweep_bytes_lds(int W, int sgn, int n, int dmax)
+{
+    return (int)bytes_lds_layout(W, sgn, n, dmax).total;
+}
+
+typedef __attribute__((address_space(3))) uint64_t lds_u64;
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) u32x2 lds_u2;
+typedef __attribute__((address_space(3))) u32x4 lds_u4;
+
+// Spread the low 4 bits of v into the low bit of 4 bytes.
+__device__ __forceinline__ uint32_t spread4(uint32_t v)
+{
+    return ((v & 0xFu) * 0x00204081u) & 0x01010101u;
+}
+
+// Gather bit 0 of 4 bytes into 4 bits (byte b -> bit b).
+__device__ __forceinline__ uint32_t gather4(uint32_t v)
+{
+    return (((v & 0x01010101u) * 0x01020408u) >> 24) & 0xFu;
+}
+
+template <int NR>
+struct Rec {
+    uint32_t v[NR];
+};
+
+template <int NR>
+__device__ __forceinline__ Rec<NR> rec_load(uint32_t off)
+{
+    Rec<NR> r;
+    if constexpr (NR == 1) {
+        r.v[0] = *(lds_u32 *)(uintptr_t)off;
+    } else if constexpr (NR == 2) {
+        const u32x2 t = *(lds_u2 *)(uintptr_t)off;
+        r.v[0] = t.x; r.v[1] = t.y;
+    } else {
+        const u32x4 t = *(lds_u4 *)(uintptr_t)off;
+        r.v[0] = t.x; r.v[1] = t.y; r.v[2] = t.z; r.v[3] = t.w;
+    }
+    return r;
+}
+
+template <int NR>
+__device__ __forceinline__ void rec_store(uint32_t off, const Rec<NR> &r)
+{
+    if constexpr (NR == 1) *(lds_u32 *)(uintptr_t)off = r.v[0];
+    else if constexpr (NR == 2) *(lds_u2 *)(uintptr_t)off = u32x2{r.v[0], r.v[1]};
+    else *(lds_u4 *)(uintptr_t)off = u32x4{r.v[0], r.v[1], r.v[2], r.v[3]};
+}
+
+struct Blk {
+    uint4 h, c0, c1, c2, c3, c4, c5, c6;
+};
+
+__device__ __forceinline__ void blk_load(Blk &b, const uint4 *p)
+{
+    b.h = p[0]; b.c0 = p[1]; b.c1 = p[2]; b.c2 = p[3];
+    b.c3 = p[4]; b.c4 = p[5]; b.c5 = p[6]; b.c6 = p[7];
+}
+
+template <int W, bool SIGNED>
+__global__ __launch_bounds__(1024) void sweep_bytes_kernel(SweepArgs a)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    constexpr int NR = W / 4;
+    const int n = a.n;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int nt = blockDim.x;
+    const int blk = blockIdx.x;
+    const int r0 = blk * W;
+    const int grp = r0 >> 6;
+    const int sub = (r0 & 63) / W;
+
+    const BytesLds L = bytes_lds_layout(W, SIGNED ? 1 : 0, n, a.dmax);
+    uint64_t *T = reinterpret_cast<uint64_t *>(smem + L.thr);
+    int *Ed = reinterpret_cast<int *>(smem + L.edelta);
+    long long *misc = reinterpret_cast<long long *>(smem + L.misc);
+    int *Eblk = reinterpret_cast<int *>(misc + 4);
+    const uint32_t comp = (uint32_t)n * W;                        // complemented records
+    const uint32_t zrec = (uint32_t)(SIGNED ? 2 * n : n) * W;     // zero record
+    const uint32_t toff = (uint32_t)L.thr;
+
+    uint64_t *Xg = a.X + (size_t)grp * n;
+    for (int i = tid; i < n; i += nt) {
+        const uint64_t v = field_of<W>(Xg[i], sub);
+        Rec<NR> rc;
+#pragma unroll
+        for (int q = 0; q < NR; ++q) rc.v[q] = spread4((uint32_t)(v >> (4 * q)));
+        rec_store<NR>((uint32_t)i * W, rc);
+        if constexpr (SIGNED) {
+#pragma unroll
+            for (int q = 0; q < NR; ++q) rc.v[q] ^= 0x01010101u;
+            rec_store<NR>(comp + (uint32_t)i * W, rc);
+        }
+    }
+    if (tid < NR) *(lds_u32 *)(uintptr_t)(zrec + 4 * tid) = 0u;
+    const int level = a.as_state[0];
+    const uint64_t *trow = a.thr + ((size_t)a.k * a.lmax1 + level) * (size_t)(a.dmax + 1);
+    for (int m = tid; m <= a.dmax; m += nt) T[m] = m == 0 ? (1ull << 32) : trow[m];
+    if (tid < W) {
+        Eblk[tid] = (r0 + tid < a.R) ? a.E[r0 + tid] : 0;
+        Ed[tid] = 0;
+    }
+    if (tid == 0) {
+        misc[0] = a.best_E[0];
+        misc[1] = -1;  // no candidate (reads back as ~0ull)
+    }
+    // Bytes of real (non-padding) replicas, as 0x80 markers for the counters.
+    uint32_t real80[NR];
+#pragma unroll
+    for (int q = 0; q < NR; ++q) {
+        uint32_t m = 0;
+        for (int b = 0; b < 4; ++b)
+            if (r0 + 4 * q + b < a.R) m |= 0x80u << (8 * b);
+        real80[q] = m;
+    }
+    __syncthreads();
+
+    const uint32_t k = (uint32_t)a.k;
+    const uint4 *blocks = a.blocks;
+    const int bu4 = a.block_u4;
+    const int nrounds = a.n_rounds;
+    const int total_rounds = nrounds * a.S;
+    const int4 *rounds = a.rounds;      // {first slot, end slot, 1 if last round of its level, 0}
+    const uint32_t rgrp0 = (uint32_t)(r0 >> 2) | (a.inst << 16);
+
+    uint32_t YA[NR], ZA[NR];
+#pragma unroll
+    for (int q = 0; q < NR; ++q) { YA[q] = 0; ZA[q] = 0; }
+    unsigned int att = 0, acc = 0;
+    int since_flush = 0;
+
+    Blk bufA, bufB;
+    {
+        // Lanes without a node in a round take block n: all entries point at the zero record.
+        const int4 r0d = rounds[0];
+        const int t0 = r0d.x + tid;
+        blk_load(bufA, blocks + (size_t)(t0 < r0d.y ? t0 : n) * bu4);
+    }
+
+    // Flush the byte energy accumulators into the block's per-replica deltas.
+    auto flush = [&]() {
+#pragma unroll
+        for (int q = 0; q < NR; ++q) {
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const int y = (int)((YA[q] >> (8 * b)) & 0xFFu);
+                const int z = (int)((ZA[q] >> (8 * b)) & 0xFFu);
+                int v = 4 * y - 2 * z;     // sum of 2m over accepted flips
+#pragma unroll
+                for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+                if (lane == 0 && v != 0) atomicAdd(&Ed[4 * q + b], v);
+            }
+            YA[q] = 0;
+            ZA[q] = 0;
+        }
+    };
+
+    auto step = [&](int rg, Blk &cur, Blk &nxt) {
+        const int s = rg / nrounds;
+        const int rho = rg - s * nrounds;
+        const int4 rd = rounds[rho];
+        // Prefetch this lane's block of the next round (next sweep wraps to round 0).
+        if (rg + 1 < total_rounds) {
+            const int4 nd = rounds[rho + 1 < nrounds ? rho + 1 : 0];
+            const int tn = nd.x + tid;
+            blk_load(nxt, blocks + (size_t)(tn < nd.y ? tn : n) * bu4);
+        }
+        const int t = rd.x + tid;
+        const int wave_first = __builtin_amdgcn_readfirstlane(rd.x + (tid & ~63));
+        if (wave_first < rd.y) {            // some lane of this wave has a node
+            const bool active = t < rd.y;
+            const uint32_t noff = active ? cur.h.x : zrec;
+            const int d = active ? (int)cur.h.y : 0;
+            const uint32_t node = cur.h.z;
+            // Levels are sorted by decreasing degree: the wave's first lane has its largest degree.
+            const int md = __builtin_amdgcn_readfirstlane(d);
+            uint32_t C[NR];
+#pragma unroll
+            for (int q = 0; q < NR; ++q) C[q] = 0;
+#define PA_NB(off)                                              \
+    {                                                           \
+        const Rec<NR> nb = rec_load<NR>(off);                   \
+        _Pragma("unroll") for (int q = 0; q < NR; ++q) C[q] += nb.v[q]; \
+    }
+#define PA_CHUNK(v) PA_NB(v.x) PA_NB(v.y) PA_NB(v.z) PA_NB(v.w)
+            if (md > 0) {
+                PA_CHUNK(cur.c0)
+                if (md > 4) {
+                    PA_CHUNK(cur.c1)
+                    if (md > 8) {
+                        PA_CHUNK(cur.c2)
+                        if (md > 12) {
+                            PA_CHUNK(cur.c3)
+                            if (md > 16) {
+                                PA_CHUNK(cur.c4)
+                                if (md > 20) {
+                                    PA_CHUNK(cur.c5)
+                                    if (md > 24) {
+                                        PA_CHUNK(cur.c6)
+                                        if (md > kRegCols) {
+                                            const uint32_t *rest = reinterpret_cast<const uint32_t *>(
+                                                blocks + (size_t)(active ? t : rd.x) * bu4) + 4;
+                                            for (int kk = kRegCols; kk < md; ++kk) {
+                                                const uint32_t off = active ? rest[kk] : zrec;
+                                                PA_NB(off)
+                                            }
+                                        }
+                                    }
+                                }
+                            }
+                        }
+                    }
+                }
+            }
+#undef PA_CHUNK
+#undef PA_NB
+            if (active) {
+                const Rec<NR> X = rec_load<NR>(noff);
+                const uint32_t Dm = (uint32_t)d * 0x01010101u;
+                const uint32_t base8d = toff + 8u * (uint32_t)d;
+                Rec<NR> Xn;
+#pragma unroll
+                for (int q = 0; q < NR; ++q) {
+                    // u = x ? c : d - c  (edges with w_ij x_i x_j = +1), per byte
+                    const uint32_t msk = X.v[q] * 0xFFu;
+                    const uint32_t U = (C[q] & msk) | ((Dm - C[q]) & ~msk);
+                    const U4 o = philox10_wide(U4{node, (uint32_t)s, k, rgrp0 + (uint32_t)q},
+                                               a.seed_lo, a.seed_hi);
+                    const uint32_t dr[4] = {o.x, o.y, o.z, o.w};
+                    uint32_t A = 0;
+#pragma unroll
+                    for (int b = 0; b < 4; ++b) {
+                        // T[max(d - 2u, 0)]: T[0] = 2^32 accepts every downhill move
+                        const int ad = (int)(base8d - (((U >> (8 * b)) & 0xFFu) << 4));
+                        const uint32_t aoff = (uint32_t)(ad < (int)toff ? (int)toff : ad);
+                        const uint64_t th = *(lds_u64 *)(uintptr_t)aoff;
+                        A |= ((uint64_t)dr[b] < th ? 1u : 0u) << (8 * b);
+                    }
+                    Xn.v[q] = X.v[q] ^ A;
+                    // uphill (2u < d) markers: byte 0x80 + (d - 1) - 2u >= 0x80
+                    const uint32_t up = (0x80808080u + Dm - 0x01010101u - 2u * U) & real80[q];
+                    att += __builtin_popcount(up);
+                    acc += __builtin_popcount(up & (A << 7));
+                    const uint32_t Am = A * 0xFFu;
+                    YA[q] += (Dm - U) & Am;
+                    ZA[q] += A * (uint32_t)d;
+                }
+                rec_store<NR>(noff, Xn);
+                if constexpr (SIGNED) {
+                    Rec<NR> Xc;
+#pragma unroll
+                    for (int q = 0; q < NR; ++q) Xc.v[q] = Xn.v[q] ^ 0x01010101u;
+                    rec_store<NR>(comp + noff, Xc);
+                }
+            }
+        }
+        ++since_flush;
+        const bool sweep_end = rho == nrounds - 1;
+        if (sweep_end || since_flush >= a.flush_every) {
+            flush();
+            since_flush = 0;
+        }
+        if (rd.z || sweep_end) __syncthreads();
+        if (sweep_end) {
+            // Energies after sweep s and the block's best candidate.
+            if (tid < W) {
+                Eblk[tid] += Ed[tid];
+                Ed[tid] = 0;
+            }
+            __syncthreads();
+            if (tid == 0) {
+                long long be = misc[0];
+                int arg = -1;
+                for (int qq = 0; qq < W && r0 + qq < a.R; ++qq)
+                    if ((long long)Eblk[qq] < be) {
+                        be = Eblk[qq];
+                        arg = qq;
+                    }
+                misc[2] = arg;
+                if (arg >= 0) {
+                    misc[0] = be;
+                    misc[1] = (long long)((((unsigned long long)((uint32_t)be ^ 0x80000000u)) << 32) |
+                                          ((unsigned long long)s << 15) |
+                                          (unsigned long long)(r0 + arg));
+                }
+            }
+            __syncthreads();
+            const int sq = (int)misc[2];
+            if (sq >= 0) {
+                uint32_t *dst = a.snap + (size_t)blk * a.nw32;
+                const unsigned char *rb = smem;
+                for (int w = tid; w < a.nw32; w += nt) {
+                    uint32_t bits = 0;
+                    const int ib = w * 32;
+                    for (int b = 0; b < 32 && ib + b < n; ++b)
+                        bits |= (uint32_t)(rb[(size_t)(ib + b) * W + sq] & 1u) << b;
+                    dst[w] = bits;
+                }
+            }
+            __syncthreads();
+        }
+    };
+
+    for (int rg = 0; rg < total_rounds; rg += 2) {
+        step(rg, bufA, bufB);
+        if (rg + 1 < total_rounds) step(rg + 1, bufB, bufA);
+    }
+
+    for (int i = tid; i < n; i += nt) {
+        const Rec<NR> rc = rec_load<NR>((uint32_t)i * W);
+        uint64_t v = 0;
+#pragma unroll
+        for (int q = 0; q < NR; ++q) v |= (uint64_t)gather4(rc.v[q]) << (4 * q);
+        if constexpr (W == 16) reinterpret_cast<uint16_t *>(Xg + i)[sub] = (uint16_t)v;
+        else if constexpr (W == 8) reinterpret_cast<uint8_t *>(Xg + i)[sub] = (uint8_t)v;
+        else {
+            // 4-bit fields share a byte with the neighbouring block: merge atomically.
+            unsigned int *wp = reinterpret_cast<unsigned int *>(Xg + i) + (sub >> 3);
+            const int sh = 4 * (sub & 7);
+            atomicAnd(wp, ~(0xFu << sh));
+            atomicOr(wp, (unsigned)v << sh);
+        }
     }
     if (tid < W && r0 + tid < a.R) a.E[r0 + tid] = Eblk[tid];
     const long long at = wave_sum_ll((long long)att), ac = wave_sum_ll((long long)acc);
@@ -824,39 +1199,63 @@ int launch_energy(const InitArgs &a, void *stream)
     return check("energy_kernel");
 }
 
-template <int W, bool SG, bool PRE>
+template <int W, bool SG>
 static int launch_sweep_t(int threads, int nblk, const SweepArgs &a, void *stream)
 {
     const int lds = sweep_lds_bytes(W, SG ? 1 : 0, a.n, a.dmax, threads);
     static int configured = 0;
     if (configured < lds) {
-        if (hipFuncSetAttribute(reinterpret_cast<const void *>(&sweep_kernel<W, SG, PRE>),
+        if (hipFuncSetAttribute(reinterpret_cast<const void *>(&sweep_kernel<W, SG>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess)
             return check("hipFuncSetAttribute(sweep)");
         configured = lds;
     }
-    hipLaunchKernelGGL((sweep_kernel<W, SG, PRE>), dim3(nblk), dim3(threads), lds,
-                       (hipStream_t)stream, a);
+    hipLaunchKernelGGL((sweep_kernel<W, SG>), dim3(nblk), dim3(threads), lds, (hipStream_t)stream, a);
     return check("sweep_kernel");
 }
 
-template <int W>
-static int launch_sweep_w(int sgn, int pre, int threads, int nblk, const SweepArgs &a, void *stream)
-{
-    if (sgn) return pre ? launch_sweep_t<W, true, true>(threads, nblk, a, stream)
-                        : launch_sweep_t<W, true, false>(threads, nblk, a, stream);
-    return pre ? launch_sweep_t<W, false, true>(threads, nblk, a, stream)
-               : launch_sweep_t<W, false, false>(threads, nblk, a, stream);
-}
-
-int launch_sweep(int W, int sgn, int pre, int threads, int nblk, const SweepArgs &a, void *stream)
+int launch_sweep(int W, int sgn, int threads, int nblk, const SweepArgs &a, void *stream)
 {
     switch (W) {
-    case 16: return launch_sweep_w<16>(sgn, pre, threads, nblk, a, stream);
-    case 32: return launch_sweep_w<32>(sgn, pre, threads, nblk, a, stream);
-    case 64: return launch_sweep_w<64>(sgn, pre, threads, nblk, a, stream);
+    case 16: return sgn ? launch_sweep_t<16, true>(threads, nblk, a, stream)
+                        : launch_sweep_t<16, false>(threads, nblk, a, stream);
+    case 32: return sgn ? launch_sweep_t<32, true>(threads, nblk, a, stream)
+                        : launch_sweep_t<32, false>(threads, nblk, a, stream);
+    case 64: return sgn ? launch_sweep_t<64, true>(threads, nblk, a, stream)
+                        : launch_sweep_t<64, false>(threads, nblk, a, stream);
     default:
         snprintf(g_err, sizeof g_err, "unsupported tile width %d", W);
+        return -1;
+    }
+}
+
+template <int W, bool SG>
+static int launch_bytes_t(int threads, int nblk, const SweepArgs &a, void *stream)
+{
+    const int lds = sweep_bytes_lds(W, SG ? 1 : 0, a.n, a.dmax);
+    static int configured = 0;
+    if (configured < lds) {
+        if (hipFuncSetAttribute(reinterpret_cast<const void *>(&sweep_bytes_kernel<W, SG>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess)
+            return check("hipFuncSetAttribute(sweep_bytes)");
+        configured = lds;
+    }
+    hipLaunchKernelGGL((sweep_bytes_kernel<W, SG>), dim3(nblk), dim3(threads), lds,
+                       (hipStream_t)stream, a);
+    return check("sweep_bytes_kernel");
+}
+
+int launch_sweep_bytes(int W, int sgn, int threads, int nblk, const SweepArgs &a, void *stream)
+{
+    switch (W) {
+    case 4: return sgn ? launch_bytes_t<4, true>(threads, nblk, a, stream)
+                       : launch_bytes_t<4, false>(threads, nblk, a, stream);
+    case 8: return sgn ? launch_bytes_t<8, true>(threads, nblk, a, stream)
+                       : launch_bytes_t<8, false>(threads, nblk, a, stream);
+    case 16: return sgn ? launch_bytes_t<16, true>(threads, nblk, a, stream)
+                        : launch_bytes_t<16, false>(threads, nblk, a, stream);
+    default:
+        snprintf(g_err, sizeof g_err, "unsupported byte-tile width %d", W);
         return -1;
     }
 }

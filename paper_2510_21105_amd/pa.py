@@ -47,6 +47,7 @@ class Schedule(ctypes.Structure):
         ("as_frozen_inv", ctypes.c_int32),
         ("as_gamma", ctypes.c_double),
         ("nl_period", ctypes.c_int32),
+        ("sweep_kernel", ctypes.c_int32),
         ("tile_replicas", ctypes.c_int32),
         ("record", ctypes.c_int32),
     ]
@@ -116,6 +117,7 @@ class RunParams:
     as_frozen_inv: int = 256
     as_gamma: float = 0.8
     nl_period: int = 0
+    sweep_kernel: int = 0
     tile_replicas: int = 0
     record: int = 0
 
@@ -168,6 +170,7 @@ class Solver:
         sch.as_frozen_inv = p.as_frozen_inv
         sch.as_gamma = p.as_gamma
         sch.nl_period = p.nl_period
+        sch.sweep_kernel = p.sweep_kernel
         sch.tile_replicas = p.tile_replicas
         sch.record = p.record
         return sch, (betas, order)
@@ -242,9 +245,10 @@ class Solver:
         return out
 
     def launch_info(self):
-        out = np.zeros(6, dtype=np.int64)
+        out = np.zeros(8, dtype=np.int64)
         _check(lib().pa_get_launch_info(self._h, _p(out)))
-        keys = ("tile_replicas", "threads", "workgroups", "lds_bytes", "levels", "sweep_launches")
+        keys = ("sweep_kernel", "tile_replicas", "threads", "workgroups", "lds_bytes", "levels",
+                "rounds", "sweep_launches")
         return dict(zip(keys, (int(v) for v in out)))
 
     def set_timing(self, on: bool):
@@ -264,5 +268,6 @@ def params_from_workload(wl: dict, **over) -> RunParams:
                      inst=d.get("inst", 0), order=d.get("order"), as_enable=d["as_enable"],
                      as_stall_steps=d["as_stall_steps"], as_max_level=d["as_max_level"],
                      as_frozen_inv=d["as_frozen_inv"], as_gamma=d["as_gamma"],
-                     nl_period=d["nl_period"], tile_replicas=d.get("tile_replicas", 0),
+                     nl_period=d["nl_period"], sweep_kernel=d.get("sweep_kernel", 0),
+                     tile_replicas=d.get("tile_replicas", 0),
                      record=d.get("record", 0))

@@ -47,7 +47,8 @@ def _compare(pa, g, wl, over=None, record=3, check_pop=True):
     s = _device_run(pa, g, p)
     stats = s.step_stats()
     t1 = time.time()
-    ref = O.run_workload(wl, **{k: v for k, v in over.items() if k != "tile_replicas"},
+    ref = O.run_workload(wl, **{k: v for k, v in over.items()
+                                if k not in ("tile_replicas", "sweep_kernel")},
                          want_population=check_pop, want_counts=bool(record & 1))
     _say(f"  device {t1 - t0:.2f}s oracle {time.time() - t1:.2f}s launch={s.launch_info()}")
     assert np.array_equal(stats, ref.stats), _first_diff(stats, ref.stats)
@@ -87,12 +88,22 @@ def test_brute20_matches_oracle_and_exhaustive_search(pa):
     assert s.best_cut() == refs.brute_force_max_cut(wl["graph"])
 
 
-@pytest.mark.parametrize("tile", [16, 32, 64])
-def test_launch_shapes_give_identical_results(pa, tile):
-    """Results do not depend on replicas per workgroup (ragged R = 150)."""
+SHAPES = [(1, 4), (1, 8), (1, 16), (2, 16), (2, 32), (2, 64)]
+
+
+@pytest.mark.parametrize("kernel,tile", SHAPES)
+def test_launch_shapes_give_identical_results(pa, kernel, tile):
+    """Results do not depend on the sweep kernel or replicas per workgroup (ragged R = 150)."""
     wl = dict(W.workload("small800"), R=150, betas=W.linear_betas(0.1, 3.0, 12), sweeps=4)
-    _compare(pa, wl["graph"], wl, dict(tile_replicas=tile, as_enable=1, as_stall_steps=1,
-                                       as_frozen_inv=4, nl_period=3))
+    _compare(pa, wl["graph"], wl, dict(sweep_kernel=kernel, tile_replicas=tile, as_enable=1,
+                                       as_stall_steps=1, as_frozen_inv=4, nl_period=3))
+
+
+@pytest.mark.parametrize("kernel,tile", [(1, 4), (1, 8), (2, 32)])
+def test_signed_torus_launch_shapes(pa, kernel, tile):
+    wl = W.workload("torus100")
+    wl = dict(wl, R=100, betas=wl["betas"][:4], sweeps=3)
+    _compare(pa, wl["graph"], wl, dict(sweep_kernel=kernel, tile_replicas=tile))
 
 
 def test_g63_shape_truncated_with_as_and_nl(pa):

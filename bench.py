@@ -80,6 +80,7 @@ def main():
     ap.add_argument("--sweep-kernel", type=int, default=0,
                     help="0 automatic, 1 node-per-lane byte records, 2 replica-per-lane bit words")
     ap.add_argument("--tile", type=int, default=0, help="replicas per workgroup (0 automatic)")
+    ap.add_argument("--threads", type=int, default=0, help="threads per sweep workgroup (0 automatic)")
     ap.add_argument("--cpu-sample-steps", type=int, default=12)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -109,7 +110,8 @@ def main():
 
     wl = W.workload(args.workload)
     g = wl["graph"]
-    params = pa.params_from_workload(wl, sweep_kernel=args.sweep_kernel, tile_replicas=args.tile)
+    params = pa.params_from_workload(wl, sweep_kernel=args.sweep_kernel, tile_replicas=args.tile,
+                                     wg_threads=args.threads)
     solver = pa.Solver(g)
     K, S, R, N = len(params.betas), params.sweeps, params.R, g.n
     attempts = R * N * S * K

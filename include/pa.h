@@ -65,6 +65,8 @@ typedef struct {
     int32_t tile_replicas;    /* replicas per workgroup, 0 = automatic; kernel 1 takes
                                  4, 8 or 16, kernel 2 takes 16, 32 or 64. Results
                                  never depend on it.                              */
+    int32_t wg_threads;       /* threads per sweep workgroup, 0 = automatic, else a
+                                 multiple of 64 in [64, 1024]. Results never depend on it. */
     int32_t record;           /* bit 0: keep per-step copy counts; bit 1: keep the
                                  initial population (both for pa_get_* below)     */
 } pa_schedule;
@@ -105,7 +107,8 @@ pa_status pa_workspace_bytes(const pa_solver *s, const pa_schedule *sch, int32_t
  * (device memory of at least pa_workspace_bytes, 256-byte aligned). The
  * workspace holds the results and must stay untouched until the last
  * pa_best_* / pa_get_* call for this run. Every output is a pure function of
- * (graph, schedule except sweep_kernel and tile_replicas, R, seed, instance).
+ * (graph, schedule except sweep_kernel, tile_replicas and wg_threads, R, seed,
+ * instance).
  *
  * Per step k = 0..K-1 (all integer on the device):
  *   1. S sweeps over `order`; for node i of replica r:

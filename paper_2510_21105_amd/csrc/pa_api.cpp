@@ -215,6 +215,8 @@ static pa_status check_schedule(const pa_solver *s, const pa_schedule *sch, int 
         sch->tile_replicas != 16 && sch->tile_replicas != 32 && sch->tile_replicas != 64)
         return fail(PA_EINVAL, "tile_replicas must be 0, 4, 8, 16, 32 or 64");
     if (sch->record < 0 || sch->record > 3) return fail(PA_EINVAL, "record must be in [0, 3]");
+    if (sch->wg_threads != 0 && (sch->wg_threads < 64 || sch->wg_threads > 1024 || sch->wg_threads % 64))
+        return fail(PA_EINVAL, "wg_threads must be 0 or a multiple of 64 in [64, 1024]");
     if (sch->order) {
         std::vector<char> seen(s->n, 0);
         for (int t = 0; t < s->n; ++t) {
@@ -402,7 +404,7 @@ static pa_status build_plan(pa_solver *s, const pa_schedule *sch, int R, Plan &p
         (void)hipGetLastError();
         max_lds = 160 * 1024;
     }
-    p.threads = pa::kMaxThreads;
+    p.threads = sch->wg_threads ? sch->wg_threads : pa::kMaxThreads;
     p.sgn = s->has_neg;
     const int req = sch->sweep_kernel, tile = sch->tile_replicas;
     if (req < 0 || req > 2) return fail(PA_EINVAL, "sweep_kernel must be 0, 1 or 2");

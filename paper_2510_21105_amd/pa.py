@@ -49,6 +49,7 @@ class Schedule(ctypes.Structure):
         ("nl_period", ctypes.c_int32),
         ("sweep_kernel", ctypes.c_int32),
         ("tile_replicas", ctypes.c_int32),
+        ("wg_threads", ctypes.c_int32),
         ("record", ctypes.c_int32),
     ]
 
@@ -119,6 +120,7 @@ class RunParams:
     nl_period: int = 0
     sweep_kernel: int = 0
     tile_replicas: int = 0
+    wg_threads: int = 0
     record: int = 0
 
 
@@ -172,6 +174,7 @@ class Solver:
         sch.nl_period = p.nl_period
         sch.sweep_kernel = p.sweep_kernel
         sch.tile_replicas = p.tile_replicas
+        sch.wg_threads = p.wg_threads
         sch.record = p.record
         return sch, (betas, order)
 
@@ -269,5 +272,5 @@ def params_from_workload(wl: dict, **over) -> RunParams:
                      as_stall_steps=d["as_stall_steps"], as_max_level=d["as_max_level"],
                      as_frozen_inv=d["as_frozen_inv"], as_gamma=d["as_gamma"],
                      nl_period=d["nl_period"], sweep_kernel=d.get("sweep_kernel", 0),
-                     tile_replicas=d.get("tile_replicas", 0),
+                     tile_replicas=d.get("tile_replicas", 0), wg_threads=d.get("wg_threads", 0),
                      record=d.get("record", 0))

@@ -1,0 +1,186 @@
+"""Host-side checks of the C ABI (no GPU needed, no device compute).
+
+The library must load, export every function ``include/pa.h`` declares,
+lay out ``pa_schedule`` exactly as the Python binding does, and reject
+malformed graphs and schedules with the documented status codes before any
+device call.
+"""
+import ctypes
+import os
+import re
+import subprocess
+import tempfile
+
+import numpy as np
+import pytest
+
+from paper_2510_21105_amd import pa, workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pa.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(pa_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_function():
+    L = pa.lib()
+    names = declared_functions()
+    assert len(names) >= 15
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+    assert set(names) == set(pa.EXPORTS)
+
+
+def test_schedule_layout_matches_header():
+    fields = [f[0] for f in pa.Schedule._fields_]
+    prog = "#include <stdio.h>\n#include <stddef.h>\n#include \"pa.h\"\nint main(void){\n"
+    prog += 'printf("%zu\\n", sizeof(pa_schedule));\n'
+    for f in fields:
+        prog += f'printf("%zu\\n", offsetof(pa_schedule, {f}));\n'
+    prog += "return 0;}\n"
+    with tempfile.TemporaryDirectory() as d:
+        src = os.path.join(d, "layout.c")
+        exe = os.path.join(d, "layout")
+        open(src, "w").write(prog)
+        subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), src, "-o", exe])
+        vals = [int(v) for v in subprocess.check_output([exe]).split()]
+    assert vals[0] == ctypes.sizeof(pa.Schedule)
+    for f, off in zip(fields, vals[1:]):
+        assert getattr(pa.Schedule, f).offset == off, f
+
+
+def _create(n, row_ptr, col, w):
+    h = ctypes.c_void_p()
+    rp = np.ascontiguousarray(row_ptr, np.int32)
+    c = np.ascontiguousarray(col, np.int32)
+    ww = np.ascontiguousarray(w, np.int8)
+    st = pa.lib().pa_create(ctypes.byref(h), n, rp.ctypes.data, c.ctypes.data, ww.ctypes.data)
+    if st == 0:
+        pa.lib().pa_destroy(h)
+    return st
+
+
+def test_create_accepts_valid_graph_and_reports_facts():
+    g = W.torus(6, 3, signed=True)
+    s = pa.Solver(g)
+    info = s.info()
+    assert info["n"] == 36 and info["nnz"] == 144 and info["dmax"] == 4
+    assert info["w_tot"] == int(g.edges()[2].sum())
+
+
+@pytest.mark.parametrize("case", ["asym", "self", "dup", "w0", "w2", "col", "rowptr", "rowptr0"])
+def test_create_rejects_malformed_graph(case):
+    g = W.cycle(5)
+    rp, col, w = g.row_ptr.copy(), g.col.copy(), g.w.copy()
+    if case == "asym":
+        w[0] = -1
+    elif case == "self":
+        col[0] = 0
+    elif case == "dup":
+        col[1] = col[0]
+    elif case == "w0":
+        w[:] = 0
+    elif case == "w2":
+        w[3] = 2
+    elif case == "col":
+        col[2] = 99
+    elif case == "rowptr":
+        rp[2], rp[3] = rp[3], rp[2]
+    elif case == "rowptr0":
+        rp = rp + 1
+    assert _create(5, rp, col, w) == pa.PA_EINVAL
+
+
+def test_create_rejects_sizes():
+    assert _create(1, [0, 0], [], []) == pa.PA_ERANGE
+    assert _create(40000, np.zeros(40001, np.int32), [], []) == pa.PA_ERANGE
+
+
+def _bytes(s, p):
+    return s.workspace_bytes(p)
+
+
+def test_workspace_grows_with_population():
+    wl = W.workload("small800")
+    s = pa.Solver(wl["graph"])
+    a = _bytes(s, pa.params_from_workload(wl, R=64))
+    b = _bytes(s, pa.params_from_workload(wl, R=4096))
+    assert 0 < a < b
+
+
+@pytest.mark.parametrize("bad,status", [
+    (dict(betas=[0.5, 0.4]), pa.PA_EINVAL),
+    (dict(betas=[-0.1]), pa.PA_EINVAL),
+    (dict(betas=[float("nan")]), pa.PA_EINVAL),
+    (dict(betas=[float("inf")]), pa.PA_EINVAL),
+    (dict(sweeps=0), pa.PA_ERANGE),
+    (dict(sweeps=70000), pa.PA_ERANGE),
+    (dict(R=0), pa.PA_ERANGE),
+    (dict(R=40000), pa.PA_ERANGE),
+    (dict(R=7, nl_period=2), pa.PA_EINVAL),
+    (dict(tile_replicas=12), pa.PA_EINVAL),
+    (dict(sweep_kernel=3), pa.PA_EINVAL),
+    (dict(wg_threads=100), pa.PA_EINVAL),
+    (dict(wg_threads=2048), pa.PA_EINVAL),
+    (dict(as_enable=1, as_stall_steps=0), pa.PA_EINVAL),
+    (dict(as_enable=1, as_max_level=16), pa.PA_ERANGE),
+    (dict(as_enable=1, as_gamma=1.5), pa.PA_EINVAL),
+    (dict(as_enable=1, as_frozen_inv=0), pa.PA_EINVAL),
+    (dict(record=4), pa.PA_EINVAL),
+])
+def test_schedule_validation(bad, status):
+    wl = W.workload("small800")
+    s = pa.Solver(wl["graph"])
+    with pytest.raises(pa.PAError) as e:
+        _bytes(s, pa.params_from_workload(wl, **bad))
+    assert e.value.status == status
+
+
+def test_order_must_be_permutation():
+    wl = W.workload("small800")
+    s = pa.Solver(wl["graph"])
+    order = np.arange(800, dtype=np.int32)
+    order[5] = 6
+    with pytest.raises(pa.PAError) as e:
+        _bytes(s, pa.params_from_workload(wl, order=order))
+    assert e.value.status == pa.PA_EINVAL
+
+
+def test_run_rejects_missing_or_misaligned_workspace_without_device_calls():
+    wl = W.workload("small800")
+    s = pa.Solver(wl["graph"])
+    p = pa.params_from_workload(wl)
+    sch, keep = s._schedule(p)
+    L = pa.lib()
+    st = L.pa_run(s._h, ctypes.byref(sch), p.R, p.seed, p.inst, None, 1 << 20, None)
+    assert st == pa.PA_EWORKSPACE
+    st = L.pa_run(s._h, ctypes.byref(sch), p.R, p.seed, p.inst, ctypes.c_void_p(4096 + 8),
+                  1 << 20, None)
+    assert st == pa.PA_EWORKSPACE
+    st = L.pa_run(s._h, ctypes.byref(sch), p.R, p.seed, 70000, ctypes.c_void_p(4096), 1 << 20, None)
+    assert st == pa.PA_ERANGE
+
+
+def test_results_before_run_are_rejected():
+    s = pa.Solver(W.cycle(8))
+    for call in (s.best_cut, s.best_config, s.best_config_hex, s.population, s.step_stats,
+                 s.launch_info):
+        with pytest.raises(pa.PAError) as e:
+            call()
+        assert e.value.status == pa.PA_ESTATE
+    assert "no completed pa_run" in pa.lib().pa_last_error().decode()
+
+
+def test_auto_launch_choice_is_reported_in_workspace_plan():
+    """Kernel 1 refuses graphs whose degree exceeds its byte counters."""
+    g = W.complete(200)        # degree 199 > 127
+    s = pa.Solver(g)
+    wl = dict(W.workload("small800"), graph=g, order=None)
+    with pytest.raises(pa.PAError) as e:
+        _bytes(s, pa.params_from_workload(wl, sweep_kernel=1))
+    assert e.value.status == pa.PA_EINVAL
+    assert _bytes(s, pa.params_from_workload(wl)) > 0       # automatic choice falls back

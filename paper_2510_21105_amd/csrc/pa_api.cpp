@@ -417,8 +417,18 @@ static pa_status build_plan(pa_solver *s, const pa_schedule *sch, int R, Plan &p
     if (req != 2 && bytes_ok) {
         W = tile;
         if (W == 0) {
-            W = 16;
-            while (W > 4 && ((R + W - 1) / W < cus || !bytes_fit(W))) W >>= 1;
+            // Measured on MI355X: two resident workgroups of 512 threads per CU
+            // hide the per-level latency best. Take the widest tile whose LDS
+            // allows two per CU and that still gives two workgroups per CU;
+            // else the narrowest tile that fits (most workgroups).
+            for (int w = 16; w >= 4 && W == 0; w >>= 1)
+                if (2 * pa::sweep_bytes_lds(w, p.sgn, n, s->dmax) <= max_lds && (R + w - 1) / w >= 2 * cus)
+                    W = w;
+            for (int w = 4; w <= 16 && W == 0; w <<= 1)
+                if (bytes_fit(w)) W = w;
+            if (W == 0) W = 4;
+            if (sch->wg_threads == 0)
+                p.threads = 2 * pa::sweep_bytes_lds(W, p.sgn, n, s->dmax) <= max_lds ? 512 : 1024;
         }
         if (!bytes_fit(W)) {
             if (req == 1)

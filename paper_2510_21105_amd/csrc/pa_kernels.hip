@@ -247,7 +247,9 @@ __device__ __forceinline__ U4 philox10_wide(U4 c, uint32_t k0, uint32_t k1)
 }
 
 template <int W, bool SIGNED>
-__global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs a)
+__global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs a, const int2 *__restrict__ stream_all,
+                                                    const int *__restrict__ level_off,
+                                                    const uint4 *__restrict__ blocks)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int NS = 64 / W;      // node slots per wave
@@ -311,8 +313,10 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs a)
     __syncthreads();
 
     const uint32_t k = (uint32_t)a.k;
-    const int2 *stream = a.stream + (size_t)wave * a.qpad;
-    const uint4 *blocks = a.blocks;
+    // Read-only tables come in as separate restrict arguments so that their
+    // uniform reads become scalar loads, which do not wait on the vector
+    // prefetch of the adjacency blocks.
+    const int2 *stream = stream_all + (size_t)wave * a.qpad;
     const int bu4 = a.block_u4;
     const uint32_t rgrp = ((uint32_t)(r0 >> 2) + (uint32_t)((lane & 15) % GPS)) | (a.inst << 16);
     const int fill_slot = (lane & 15) / GPS;
@@ -331,18 +335,17 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs a)
             h = bp[0]; c0 = bp[1]; c1 = bp[2]; c2 = bp[3]; c3 = bp[4]; c4 = bp[5]; c5 = bp[6]; c6 = bp[7];
         }
         for (int lv = 0; lv < a.n_levels; ++lv) {
-            const int beg = a.level_off[lv], end = a.level_off[lv + 1];
+            const int beg = level_off[lv], end = level_off[lv + 1];
             const int Lsz = end - beg;
             const int npass = Lsz > wave * NS ? (Lsz - wave * NS + nwaves * NS - 1) / (nwaves * NS) : 0;
             for (int p = 0; p < npass; ++p, ++q) {
-                // Prefetch the next pass of this wave's stream (read-only graph data).
+                // Prefetch the next pass of this wave's stream (read-only graph
+                // data); past the end of the stream it reloads slot 0.
                 const int2 sn = stream[q + 1];
-                uint4 nh = h, n0 = c0, n1 = c1, n2 = c2, n3 = c3, n4 = c4, n5 = c5, n6 = c6;
-                if (sn.x >= 0) {
-                    const int tn = sn.x + slot_w < n ? sn.x + slot_w : sn.x;
-                    const uint4 *bp = blocks + (size_t)tn * bu4;
-                    nh = bp[0]; n0 = bp[1]; n1 = bp[2]; n2 = bp[3]; n3 = bp[4]; n4 = bp[5]; n5 = bp[6]; n6 = bp[7];
-                }
+                const int tn = sn.x < 0 ? 0 : (sn.x + slot_w < n ? sn.x + slot_w : sn.x);
+                const uint4 *bpn = blocks + (size_t)tn * bu4;
+                const uint4 nh = bpn[0], n0 = bpn[1], n1 = bpn[2], n2 = bpn[3], n3 = bpn[4], n4 = bpn[5],
+                            n5 = bpn[6], n6 = bpn[7];
                 if ((q & 3) == 0) {
                     // Draws for passes q..q+3: every lane computes one Philox call.
                     const int2 e = stream[q + fill_pass];
@@ -568,7 +571,8 @@ __device__ __forceinline__ void blk_load(Blk &b, const uint4 *p)
 }
 
 template <int W, bool SIGNED>
-__global__ __launch_bounds__(1024) void sweep_bytes_kernel(SweepArgs a)
+__global__ __launch_bounds__(1024) void sweep_bytes_kernel(SweepArgs a, const int4 *__restrict__ rounds,
+                                                          const uint4 *__restrict__ blocks)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int NR = W / 4;
@@ -627,11 +631,12 @@ __global__ __launch_bounds__(1024) void sweep_bytes_kernel(SweepArgs a)
     __syncthreads();
 
     const uint32_t k = (uint32_t)a.k;
-    const uint4 *blocks = a.blocks;
+    // rounds[] = {first slot, level end, 1 if last round of its level, 0}. The
+    // read-only tables are separate restrict arguments so that the uniform
+    // round reads become scalar loads and never wait on the block prefetch.
     const int bu4 = a.block_u4;
     const int nrounds = a.n_rounds;
     const int total_rounds = nrounds * a.S;
-    const int4 *rounds = a.rounds;      // {first slot, end slot, 1 if last round of its level, 0}
     const uint32_t rgrp0 = (uint32_t)(r0 >> 2) | (a.inst << 16);
 
     uint32_t YA[NR], ZA[NR];
@@ -670,8 +675,9 @@ __global__ __launch_bounds__(1024) void sweep_bytes_kernel(SweepArgs a)
         const int s = rg / nrounds;
         const int rho = rg - s * nrounds;
         const int4 rd = rounds[rho];
-        // Prefetch this lane's block of the next round (next sweep wraps to round 0).
-        if (rg + 1 < total_rounds) {
+        // Prefetch this lane's block of the next round (the next sweep wraps to
+        // round 0; after the last round this is a harmless reload).
+        {
             const int4 nd = rounds[rho + 1 < nrounds ? rho + 1 : 0];
             const int tn = nd.x + tid;
             blk_load(nxt, blocks + (size_t)(tn < nd.y ? tn : n) * bu4);
@@ -812,9 +818,11 @@ __global__ __launch_bounds__(1024) void sweep_bytes_kernel(SweepArgs a)
         }
     };
 
-    for (int rg = 0; rg < total_rounds; rg += 2) {
+    // One loop body: the next round's block is loaded into bufB while bufA is
+    // processed, and rotated in at the end of the round.
+    for (int rg = 0; rg < total_rounds; ++rg) {
         step(rg, bufA, bufB);
-        if (rg + 1 < total_rounds) step(rg + 1, bufB, bufA);
+        bufA = bufB;
     }
 
     for (int i = tid; i < n; i += nt) {
@@ -1210,7 +1218,8 @@ static int launch_sweep_t(int threads, int nblk, const SweepArgs &a, void *strea
             return check("hipFuncSetAttribute(sweep)");
         configured = lds;
     }
-    hipLaunchKernelGGL((sweep_kernel<W, SG>), dim3(nblk), dim3(threads), lds, (hipStream_t)stream, a);
+    hipLaunchKernelGGL((sweep_kernel<W, SG>), dim3(nblk), dim3(threads), lds, (hipStream_t)stream, a,
+                       a.stream, a.level_off, a.blocks);
     return check("sweep_kernel");
 }
 
@@ -1241,7 +1250,7 @@ static int launch_bytes_t(int threads, int nblk, const SweepArgs &a, void *strea
         configured = lds;
     }
     hipLaunchKernelGGL((sweep_bytes_kernel<W, SG>), dim3(nblk), dim3(threads), lds,
-                       (hipStream_t)stream, a);
+                       (hipStream_t)stream, a, a.rounds, a.blocks);
     return check("sweep_bytes_kernel");
 }
 

@@ -276,34 +276,35 @@ static void build_levels(const pa_solver *s, const int32_t *order, Plan &p)
 static void build_blocks(const pa_solver *s, Plan &p)
 {
     const int n = s->n;
-    const int cap = 4 * ((std::max(s->dmax, 1) + 3) / 4);
-    p.block_bytes = 16 + 4 * cap;
-    const int bw = p.block_bytes / 4;
     if (p.kind == 1) {
-        // Kernel 1: entries are LDS byte offsets of W-byte spin records;
-        // negative edges point at the complemented record (n + j). Block n is
-        // an all-padding block for lanes without a node in a round.
-        const uint32_t W = (uint32_t)p.W;
-        const uint32_t zero = (uint32_t)(p.sgn ? 2 * n : n) * W;
-        p.blocks.assign((size_t)(n + 1) * bw + 32, zero);
+        // Kernel 1: u16 {node, degree, neighbour record indices...}, padded
+        // with the zero record's index to 8m - 2 entries (a multiple of 16
+        // bytes with the header, at least the degree rounded up to 4).
+        // Negative edges name the complemented record n + j. Block n is an
+        // all-padding block for lanes without a node in a round.
+        const uint16_t zi = (uint16_t)(p.sgn ? 2 * n : n);
+        const int need = 4 * ((std::max(s->dmax, 1) + 3) / 4);
+        int capk = 6;
+        while (capk < need) capk += 8;
+        p.block_bytes = 2 * (2 + capk);
+        const int bw16 = p.block_bytes / 2;
+        std::vector<uint16_t> b16((size_t)(n + 1) * bw16 + 32, zi);
         for (int t = 0; t < n; ++t) {
             const int i = p.sched[t];
-            uint32_t *b = &p.blocks[(size_t)t * bw];
+            uint16_t *b = &b16[(size_t)t * bw16];
             const int e0 = s->row_ptr[i], e1 = s->row_ptr[i + 1];
-            b[0] = (uint32_t)i * W;
-            b[1] = (uint32_t)(e1 - e0);
-            b[2] = (uint32_t)i;
-            b[3] = 0;
+            b[0] = (uint16_t)i;
+            b[1] = (uint16_t)(e1 - e0);
             for (int e = e0; e < e1; ++e) {
                 const int j = s->col[e];
                 const bool neg = e >= e0 + s->npos[i];
-                b[4 + (e - e0)] = (uint32_t)(neg ? n + j : j) * W;
+                b[2 + (e - e0)] = (uint16_t)(neg ? n + j : j);
             }
         }
-        uint32_t *pad = &p.blocks[(size_t)n * bw];
-        pad[1] = 0;
-        pad[2] = 0;
-        pad[3] = 0;
+        b16[(size_t)n * bw16] = 0;
+        b16[(size_t)n * bw16 + 1] = 0;
+        p.blocks.assign((b16.size() + 1) / 2, 0u);
+        std::memcpy(p.blocks.data(), b16.data(), b16.size() * sizeof(uint16_t));
         // Rounds: a level is cut into chunks of one node per thread.
         p.rounds.clear();
         for (int l = 0; l < p.n_levels; ++l) {
@@ -319,6 +320,9 @@ static void build_blocks(const pa_solver *s, Plan &p)
         p.flush_every = std::max(1, 255 / std::max(s->dmax, 1));
         return;
     }
+    const int cap = 4 * ((std::max(s->dmax, 1) + 3) / 4);
+    p.block_bytes = 16 + 4 * cap;
+    const int bw = p.block_bytes / 4;
     const int NS = 64 / p.W, NW = p.threads / 64;
     const int sh = p.W == 16 ? 1 : (p.W == 32 ? 2 : 3);
     const uint32_t zero = (uint32_t)(p.sgn ? 2 * n : n) << sh;

@@ -560,14 +560,17 @@ __device__ __forceinline__ void rec_store(uint32_t off, const Rec<NR> &r)
     else *(lds_u4 *)(uintptr_t)off = u32x4{r.v[0], r.v[1], r.v[2], r.v[3]};
 }
 
+// Adjacency block head held in registers: u16 {node, degree, 30 neighbour
+// record indices} = 64 bytes; longer rows continue in global memory.
 struct Blk {
-    uint4 h, c0, c1, c2, c3, c4, c5, c6;
+    uint4 b0, b1, b2, b3;
 };
+
+constexpr int kBlkCols = 30;
 
 __device__ __forceinline__ void blk_load(Blk &b, const uint4 *p)
 {
-    b.h = p[0]; b.c0 = p[1]; b.c1 = p[2]; b.c2 = p[3];
-    b.c3 = p[4]; b.c4 = p[5]; b.c5 = p[6]; b.c6 = p[7];
+    b.b0 = p[0]; b.b1 = p[1]; b.b2 = p[2]; b.b3 = p[3];
 }
 
 template <int W, bool SIGNED>
@@ -644,13 +647,14 @@ __global__ __launch_bounds__(1024) void sweep_bytes_kernel(SweepArgs a, const in
     for (int q = 0; q < NR; ++q) { YA[q] = 0; ZA[q] = 0; }
     unsigned int att = 0, acc = 0;
     int since_flush = 0;
+    constexpr int SHW = W == 4 ? 2 : (W == 8 ? 3 : 4);   // record index -> LDS byte offset
 
     Blk bufA, bufB;
+    int4 rd = rounds[0];   // the current round, carried from one iteration to the next
     {
         // Lanes without a node in a round take block n: all entries point at the zero record.
-        const int4 r0d = rounds[0];
-        const int t0 = r0d.x + tid;
-        blk_load(bufA, blocks + (size_t)(t0 < r0d.y ? t0 : n) * bu4);
+        const int t0 = rd.x + tid;
+        blk_load(bufA, blocks + (size_t)(t0 < rd.y ? t0 : n) * bu4);
     }
 
     // Flush the byte energy accumulators into the block's per-replica deltas.
@@ -671,14 +675,13 @@ __global__ __launch_bounds__(1024) void sweep_bytes_kernel(SweepArgs a, const in
         }
     };
 
-    auto step = [&](int rg, Blk &cur, Blk &nxt) {
+    auto step = [&](int rg, Blk &cur, Blk &nxt, int4 &nd) {
         const int s = rg / nrounds;
         const int rho = rg - s * nrounds;
-        const int4 rd = rounds[rho];
         // Prefetch this lane's block of the next round (the next sweep wraps to
         // round 0; after the last round this is a harmless reload).
+        nd = rounds[rho + 1 < nrounds ? rho + 1 : 0];
         {
-            const int4 nd = rounds[rho + 1 < nrounds ? rho + 1 : 0];
             const int tn = nd.x + tid;
             blk_load(nxt, blocks + (size_t)(tn < nd.y ? tn : n) * bu4);
         }
@@ -686,9 +689,9 @@ __global__ __launch_bounds__(1024) void sweep_bytes_kernel(SweepArgs a, const in
         const int wave_first = __builtin_amdgcn_readfirstlane(rd.x + (tid & ~63));
         if (wave_first < rd.y) {            // some lane of this wave has a node
             const bool active = t < rd.y;
-            const uint32_t noff = active ? cur.h.x : zrec;
-            const int d = active ? (int)cur.h.y : 0;
-            const uint32_t node = cur.h.z;
+            const uint32_t node = cur.b0.x & 0xFFFFu;
+            const uint32_t noff = active ? node << SHW : zrec;
+            const int d = active ? (int)(cur.b0.x >> 16) : 0;
             // Levels are sorted by decreasing degree: the wave's first lane has its largest degree.
             const int md = __builtin_amdgcn_readfirstlane(d);
             uint32_t C[NR];
@@ -699,27 +702,30 @@ __global__ __launch_bounds__(1024) void sweep_bytes_kernel(SweepArgs a, const in
         const Rec<NR> nb = rec_load<NR>(off);                   \
         _Pragma("unroll") for (int q = 0; q < NR; ++q) C[q] += nb.v[q]; \
     }
-#define PA_CHUNK(v) PA_NB(v.x) PA_NB(v.y) PA_NB(v.z) PA_NB(v.w)
+#define PA_W(w) PA_NB(((w) & 0xFFFFu) << SHW) PA_NB(((w) >> 16) << SHW)
             if (md > 0) {
-                PA_CHUNK(cur.c0)
+                PA_W(cur.b0.y) PA_W(cur.b0.z)
                 if (md > 4) {
-                    PA_CHUNK(cur.c1)
+                    PA_W(cur.b0.w) PA_W(cur.b1.x)
                     if (md > 8) {
-                        PA_CHUNK(cur.c2)
+                        PA_W(cur.b1.y) PA_W(cur.b1.z)
                         if (md > 12) {
-                            PA_CHUNK(cur.c3)
+                            PA_W(cur.b1.w) PA_W(cur.b2.x)
                             if (md > 16) {
-                                PA_CHUNK(cur.c4)
+                                PA_W(cur.b2.y) PA_W(cur.b2.z)
                                 if (md > 20) {
-                                    PA_CHUNK(cur.c5)
+                                    PA_W(cur.b2.w) PA_W(cur.b3.x)
                                     if (md > 24) {
-                                        PA_CHUNK(cur.c6)
-                                        if (md > kRegCols) {
-                                            const uint32_t *rest = reinterpret_cast<const uint32_t *>(
-                                                blocks + (size_t)(active ? t : rd.x) * bu4) + 4;
-                                            for (int kk = kRegCols; kk < md; ++kk) {
-                                                const uint32_t off = active ? rest[kk] : zrec;
-                                                PA_NB(off)
+                                        PA_W(cur.b3.y) PA_W(cur.b3.z)
+                                        if (md > 28) {
+                                            PA_W(cur.b3.w)
+                                            if (md > kBlkCols) {
+                                                const uint16_t *rest = reinterpret_cast<const uint16_t *>(
+                                                    blocks + (size_t)(active ? t : rd.x) * bu4) + 2;
+                                                for (int kk = kBlkCols; kk < md; ++kk) {
+                                                    const uint32_t off = active ? (uint32_t)rest[kk] << SHW : zrec;
+                                                    PA_NB(off)
+                                                }
                                             }
                                         }
                                     }
@@ -729,7 +735,7 @@ __global__ __launch_bounds__(1024) void sweep_bytes_kernel(SweepArgs a, const in
                     }
                 }
             }
-#undef PA_CHUNK
+#undef PA_W
 #undef PA_NB
             if (active) {
                 const Rec<NR> X = rec_load<NR>(noff);
@@ -821,8 +827,10 @@ __global__ __launch_bounds__(1024) void sweep_bytes_kernel(SweepArgs a, const in
     // One loop body: the next round's block is loaded into bufB while bufA is
     // processed, and rotated in at the end of the round.
     for (int rg = 0; rg < total_rounds; ++rg) {
-        step(rg, bufA, bufB);
+        int4 nd;
+        step(rg, bufA, bufB, nd);
         bufA = bufB;
+        rd = nd;
     }
 
     for (int i = tid; i < n; i += nt) {

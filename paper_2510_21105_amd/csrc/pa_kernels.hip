@@ -598,16 +598,28 @@ __global__ __launch_bounds__(1024) void sweep_bytes_kernel(SweepArgs a, const in
     const uint32_t toff = (uint32_t)L.thr;
 
     uint64_t *Xg = a.X + (size_t)grp * n;
-    for (int i = tid; i < n; i += nt) {
-        const uint64_t v = field_of<W>(Xg[i], sub);
-        Rec<NR> rc;
+    // Expand the block's spin bits into byte records, 4 loads in flight per lane.
+    for (int base = 0; base < n; base += 4 * nt) {
+        uint64_t vv[4];
 #pragma unroll
-        for (int q = 0; q < NR; ++q) rc.v[q] = spread4((uint32_t)(v >> (4 * q)));
-        rec_store<NR>((uint32_t)i * W, rc);
-        if constexpr (SIGNED) {
+        for (int u = 0; u < 4; ++u) {
+            const int i = base + u * nt + tid;
+            vv[u] = i < n ? Xg[i] : 0ull;
+        }
 #pragma unroll
-            for (int q = 0; q < NR; ++q) rc.v[q] ^= 0x01010101u;
-            rec_store<NR>(comp + (uint32_t)i * W, rc);
+        for (int u = 0; u < 4; ++u) {
+            const int i = base + u * nt + tid;
+            if (i >= n) break;
+            const uint64_t v = field_of<W>(vv[u], sub);
+            Rec<NR> rc;
+#pragma unroll
+            for (int q = 0; q < NR; ++q) rc.v[q] = spread4((uint32_t)(v >> (4 * q)));
+            rec_store<NR>((uint32_t)i * W, rc);
+            if constexpr (SIGNED) {
+#pragma unroll
+                for (int q = 0; q < NR; ++q) rc.v[q] ^= 0x01010101u;
+                rec_store<NR>(comp + (uint32_t)i * W, rc);
+            }
         }
     }
     if (tid < NR) *(lds_u32 *)(uintptr_t)(zrec + 4 * tid) = 0u;
@@ -841,11 +853,13 @@ __global__ __launch_bounds__(1024) void sweep_bytes_kernel(SweepArgs a, const in
         if constexpr (W == 16) reinterpret_cast<uint16_t *>(Xg + i)[sub] = (uint16_t)v;
         else if constexpr (W == 8) reinterpret_cast<uint8_t *>(Xg + i)[sub] = (uint8_t)v;
         else {
-            // 4-bit fields share a byte with the neighbouring block: merge atomically.
+            // 4-bit fields share a byte with the neighbouring block: flip the
+            // changed bits atomically (only this block writes these 4 bits, so
+            // the word read here holds their value from the start of the step).
             unsigned int *wp = reinterpret_cast<unsigned int *>(Xg + i) + (sub >> 3);
             const int sh = 4 * (sub & 7);
-            atomicAnd(wp, ~(0xFu << sh));
-            atomicOr(wp, (unsigned)v << sh);
+            const unsigned delta = (((unsigned)v ^ (*wp >> sh)) & 0xFu) << sh;
+            if (delta) atomicXor(wp, delta);
         }
     }
     if (tid < W && r0 + tid < a.R) a.E[r0 + tid] = Eblk[tid];
@@ -1054,11 +1068,15 @@ __global__ __launch_bounds__(256) void gather_kernel(GatherArgs a)
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void icm_kernel(IcmArgs a)
 {
+    // LDS bitmaps (nw words each): A = spins of replica a, D = disagreement
+    // set, V = cluster, F / Nx = BFS frontiers; plus per-thread scan slots.
     extern __shared__ __align__(16) uint32_t bm[];
     __shared__ long long red_l[16];
+    __shared__ int scan_i[256];
+    __shared__ int seed_s;
     const int tid = threadIdx.x, lane = tid & 63, nt = blockDim.x;
     const int n = a.g.n, nw = a.nw32;
-    uint32_t *D = bm, *V = bm + nw, *F = bm + 2 * nw, *Nx = bm + 3 * nw;
+    uint32_t *A = bm, *D = bm + nw, *V = bm + 2 * nw, *F = bm + 3 * nw, *Nx = bm + 4 * nw;
     const int p = blockIdx.x, half = a.R / 2;
     const int ra = p, rb = p + half;
     const int ba = ra & 63, bb = rb & 63;
@@ -1066,34 +1084,59 @@ __global__ __launch_bounds__(256) void icm_kernel(IcmArgs a)
     const uint64_t *Xb = a.X + (size_t)(rb >> 6) * n;
 
     for (int w = tid; w < nw; w += nt) { V[w] = 0; F[w] = 0; Nx[w] = 0; }
-    long long cnt = 0;
-    for (int base = 0; base < nw * 32; base += nt) {
-        const int i = base + tid;
-        const int bit = i < n ? (int)(((Xa[i] >> ba) ^ (Xb[i] >> bb)) & 1ull) : 0;
-        const unsigned long long m = __ballot(bit);
-        const int w0 = (base + (tid & ~63)) >> 5;
-        if (lane == 0 && w0 < nw) D[w0] = (uint32_t)m;
-        if (lane == 32 && w0 + 1 < nw) D[w0 + 1] = (uint32_t)(m >> 32);
-        cnt += bit;
+    // Spins of a and of the disagreement set, 4 independent loads in flight per lane.
+    int cnt = 0;
+    for (int base = 0; base < nw * 32; base += 4 * nt) {
+        uint64_t va[4], vb[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int i = base + u * nt + tid;
+            va[u] = i < n ? Xa[i] : 0ull;
+            vb[u] = i < n ? Xb[i] : 0ull;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int i = base + u * nt + tid;
+            const int xa = (int)((va[u] >> ba) & 1ull);
+            const int dd = i < n ? xa ^ (int)((vb[u] >> bb) & 1ull) : 0;
+            const unsigned long long ma = __ballot(xa), md = __ballot(dd);
+            const int w0 = (base + u * nt + (tid & ~63)) >> 5;
+            if (lane == 0 && w0 < nw) { A[w0] = (uint32_t)ma; D[w0] = (uint32_t)md; }
+            if (lane == 32 && w0 + 1 < nw) { A[w0 + 1] = (uint32_t)(ma >> 32); D[w0 + 1] = (uint32_t)(md >> 32); }
+            cnt += dd;
+        }
     }
-    cnt = block_sum_ll(cnt, red_l);
-    if (cnt == 0) return;
-    // Seed node: the pick-th element of D in node order.
+    const long long total = block_sum_ll(cnt, red_l);
+    if (total == 0) return;
+    // Seed node: the pick-th element of D in node order (scan of per-thread word chunks).
     const uint32_t d = draw(a.seed_lo, a.seed_hi, a.inst, 3, 0, (uint32_t)a.k, 0u, (uint32_t)p);
-    const long long pick = (long long)(((uint64_t)d * (uint64_t)cnt) >> 32);
-    if (tid == 0) {
-        long long c = 0;
-        int w = 0;
-        for (; w < nw; ++w) {
+    const int pick = (int)(((uint64_t)d * (uint64_t)total) >> 32);
+    const int per = (nw + nt - 1) / nt;
+    const int w_lo = tid * per < nw ? tid * per : nw, w_hi = w_lo + per < nw ? w_lo + per : nw;
+    int mine = 0;
+    for (int w = w_lo; w < w_hi; ++w) mine += __popc(D[w]);
+    scan_i[tid] = mine;
+    __syncthreads();
+    for (int o = 1; o < nt; o <<= 1) {
+        const int v = tid >= o ? scan_i[tid - o] : 0;
+        __syncthreads();
+        scan_i[tid] += v;
+        __syncthreads();
+    }
+    const int before = scan_i[tid] - mine;
+    if (pick >= before && pick < before + mine) {
+        int c = before, w = w_lo;
+        for (; w < w_hi; ++w) {
             const int pc = __popc(D[w]);
             if (c + pc > pick) break;
             c += pc;
         }
         uint32_t bits = D[w];
-        for (long long t = c; t < pick; ++t) bits &= bits - 1;
+        for (int t = c; t < pick; ++t) bits &= bits - 1;
         const int s0 = w * 32 + __ffs(bits) - 1;
-        V[s0 >> 5] |= 1u << (s0 & 31);
-        F[s0 >> 5] |= 1u << (s0 & 31);
+        seed_s = s0;
+        V[s0 >> 5] = 1u << (s0 & 31);
+        F[s0 >> 5] = 1u << (s0 & 31);
     }
     __syncthreads();
     // Level-synchronous BFS inside D.
@@ -1124,7 +1167,7 @@ __global__ __launch_bounds__(256) void icm_kernel(IcmArgs a)
         for (int w = tid; w < nw; w += nt) Nx[w] = 0;
         __syncthreads();
     }
-    // Energy change of replica a: edges leaving the cluster change sign.
+    // Energy change of replica a: the edges leaving the cluster change sign.
     long long dEa = 0;
     for (int w = tid; w < nw; w += nt) {
         uint32_t c = V[w];
@@ -1132,12 +1175,12 @@ __global__ __launch_bounds__(256) void icm_kernel(IcmArgs a)
             const int b = __ffs(c) - 1;
             c &= c - 1;
             const int i = w * 32 + b;
-            const int bi = (int)((Xa[i] >> ba) & 1ull);
+            const int bi = (int)((A[w] >> b) & 1u);
             const int e0 = a.g.row_ptr[i], e1 = a.g.row_ptr[i + 1], em = e0 + a.g.npos[i];
             for (int e = e0; e < e1; ++e) {
                 const int j = a.g.col[e];
                 if (V[j >> 5] & (1u << (j & 31))) continue;
-                const int bj = (int)((Xa[j] >> ba) & 1ull);
+                const int bj = (int)((A[j >> 5] >> (j & 31)) & 1u);
                 const int neg = e >= em;
                 dEa += -2 * (1 - 2 * (bi ^ bj ^ neg));
             }
@@ -1161,6 +1204,7 @@ __global__ __launch_bounds__(256) void icm_kernel(IcmArgs a)
         a.E[ra] += (int)dEa;
         a.E[rb] -= (int)dEa;
     }
+    (void)seed_s;
 }
 
 __global__ void fill_u64_kernel(unsigned long long *p, unsigned long long v, long long count)
@@ -1293,7 +1337,7 @@ int launch_gather(const GatherArgs &a, void *stream)
 
 int launch_icm(const IcmArgs &a, void *stream)
 {
-    const int lds = 4 * a.nw32 * 4;
+    const int lds = 5 * a.nw32 * 4;
     hipLaunchKernelGGL(icm_kernel, dim3(a.R / 2), dim3(256), lds, (hipStream_t)stream, a);
     return check("icm_kernel");
 }

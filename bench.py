@@ -29,7 +29,7 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 SWEEP_SOURCE = os.path.join(ROOT, "paper_2510_21105_amd", "csrc", "pa_kernels.hip")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_kernel_hbm_traffic_g63like.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_kernel_hbm_traffic_{}.json")
 
 
 def kernel_source_hash() -> str:
@@ -44,11 +44,12 @@ def algorithmic_bytes_per_attempt(accept_rate: float, mean_degree: float, s_x=1,
     return (s_x + s_h) + accept_rate * (s_x + 2 * s_h * mean_degree)
 
 
-def measured_traffic_per_launch():
-    """HBM bytes per sweep launch from the committed rocprofv3 counter summary,
-    or None when it is absent or was taken on a different kernel source."""
+def measured_traffic_per_launch(workload: str):
+    """HBM bytes per sweep launch from the committed rocprofv3 counter summary
+    of this workload, or None when it is absent or was taken on a different
+    kernel source."""
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(TRAFFIC_FILE.format(workload)) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
@@ -143,11 +144,11 @@ def main():
     accepts = attempts - att_up + acc_up
     a = accepts / attempts
     dbar = 2.0 * g.n_edges / N
-    b_alg = algorithmic_bytes_per_attempt(a, dbar)
+    b_alg = algorithmic_bytes_per_attempt(a, dbar, s_h=wl.get("field_bytes", 2))
     per_launch_attempts = R * N * S
     avg_launch_s = sweep_ms / 1000.0 / max(sweep_launches, 1)
     achieved_gbs = b_alg * per_launch_attempts / avg_launch_s / 1e9
-    traffic = measured_traffic_per_launch()
+    traffic = measured_traffic_per_launch(args.workload)
     roof = {"bound": "hbm", "achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved_gbs / HBM_PEAK_GBS, 4), "traffic": traffic}
 
@@ -164,10 +165,7 @@ def main():
         "vs_baseline": None,
         "dtype": "int32",
         "data": "synthetic",
-        "config": {"workload": f"{args.workload}: random G(N={N}, M={g.n_edges}) seed 3 "
-                               f"(G63 shape), R={R}, K={K} linear beta 0.1->5.0, S={S}, "
-                               f"adaptive stochasticity + cluster moves every "
-                               f"{params.nl_period} steps",
+        "config": {"workload": f"{args.workload}: {wl['desc']}",
                    "nodes": N, "edges": g.n_edges, "replicas": R, "temperature_steps": K,
                    "sweeps_per_step": S, "attempts_per_solve": attempts},
         "roofline": roof,

@@ -183,24 +183,38 @@ def workload(name: str) -> dict:
       stochasticity and non-local moves on.
     * ``torus100``: 100 x 100 torus with +-1 weights, seed 4, R=16384,
       1000 steps 0.1 -> 4.0, 5 sweeps/step, checkerboard order.
+
+    ``desc`` names the workload in one line; ``field_bytes`` (default 2) is
+    the width of a local field in the sequential cost model that prices the
+    sweep's algorithmic bytes (int16 fields for the random graphs, int8 for
+    the degree-4 torus).
     """
     base = dict(seed=42, as_enable=0, as_stall_steps=20, as_max_level=4,
                 as_frozen_inv=256, as_gamma=0.8, nl_period=0)
     if name == "small800":
         g = random_graph(800, 4000, 1, "small800")
         return dict(base, graph=g, betas=linear_betas(0.1, 3.0, 50), sweeps=10,
-                    order=natural_order(g.n), R=128, inst=0)
+                    order=natural_order(g.n), R=128, inst=0,
+                    desc="random G(N=800, M=4000) seed 1, R=128, K=50 linear beta 0.1->3.0, "
+                         "S=10, natural order")
     if name == "brute20":
         g = random_graph(20, 60, 2, "brute20")
         return dict(base, graph=g, betas=linear_betas(0.1, 3.0, 50), sweeps=10,
-                    order=natural_order(g.n), R=128, inst=0)
+                    order=natural_order(g.n), R=128, inst=0,
+                    desc="random G(N=20, M=60) seed 2, R=128, K=50 linear beta 0.1->3.0, "
+                         "S=10, natural order")
     if name == "g63like":
         g = random_graph(7000, 41459, 3, "g63like")
         return dict(base, graph=g, betas=linear_betas(0.1, 5.0, 2000), sweeps=10,
                     order=natural_order(g.n), R=4096, inst=1,
-                    as_enable=1, nl_period=10)
+                    as_enable=1, nl_period=10,
+                    desc="random G(N=7000, M=41459) seed 3 (G63 shape), R=4096, K=2000 linear "
+                         "beta 0.1->5.0, S=10, natural order, adaptive stochasticity + "
+                         "cluster moves every 10 steps")
     if name == "torus100":
         g = torus(100, 4, True, "torus100")
         return dict(base, graph=g, betas=linear_betas(0.1, 4.0, 1000), sweeps=5,
-                    order=checkerboard_order(100), R=16384, inst=2)
+                    order=checkerboard_order(100), R=16384, inst=2, field_bytes=1,
+                    desc="100x100 torus, +-1 weights seed 4, R=16384, K=1000 linear beta "
+                         "0.1->4.0, S=5, checkerboard order")
     raise KeyError(name)

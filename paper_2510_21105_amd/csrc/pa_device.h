@@ -44,7 +44,7 @@ struct SweepArgs {
     int qpad;
     const int4 *rounds;         // [n_rounds] {first slot, level end, last round of level, 0}
     int n_rounds;
-    int flush_every;            // rounds between flushes of the byte energy accumulators
+    int flush_every;            // rounds between widenings of the byte energy accumulators
     const uint64_t *thr;        // [K][lmax1][dmax+1]
     const int *as_state;        // [0] level
     uint64_t *X;                // [G][n]

@@ -573,6 +573,19 @@ __device__ __forceinline__ void blk_load(Blk &b, const uint4 *p)
     b.b0 = p[0]; b.b1 = p[1]; b.b2 = p[2]; b.b3 = p[3];
 }
 
+// Sum over the 64 lanes of a wave with DPP row shifts and row broadcasts
+// (every lane active); the total is read from lane 63.
+__device__ __forceinline__ int wave_sum_dpp(int v)
+{
+    v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xF, 0xF, false);   // row_shr:1
+    v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xF, 0xF, false);   // row_shr:2
+    v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xF, 0xF, false);   // row_shr:4
+    v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xF, 0xF, false);   // row_shr:8
+    v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xA, 0xF, false);   // row_bcast:15
+    v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xC, 0xF, false);   // row_bcast:31
+    return __builtin_amdgcn_readlane(v, 63);
+}
+
 template <int W, bool SIGNED>
 __global__ __launch_bounds__(1024) void sweep_bytes_kernel(SweepArgs a, const int4 *__restrict__ rounds,
                                                           const uint4 *__restrict__ blocks)
@@ -651,7 +664,6 @@ __global__ __launch_bounds__(1024) void sweep_bytes_kernel(SweepArgs a, const in
     // round reads become scalar loads and never wait on the block prefetch.
     const int bu4 = a.block_u4;
     const int nrounds = a.n_rounds;
-    const int total_rounds = nrounds * a.S;
     const uint32_t rgrp0 = (uint32_t)(r0 >> 2) | (a.inst << 16);
 
     uint32_t YA[NR], ZA[NR];
@@ -662,37 +674,54 @@ __global__ __launch_bounds__(1024) void sweep_bytes_kernel(SweepArgs a, const in
     constexpr int SHW = W == 4 ? 2 : (W == 8 ? 3 : 4);   // record index -> LDS byte offset
 
     Blk bufA, bufB;
-    int4 rd = rounds[0];   // the current round, carried from one iteration to the next
+    int4 rd = rounds[0];                          // the current round
+    int4 nd = rounds[nrounds > 1 ? 1 : 0];        // the next round
     {
         // Lanes without a node in a round take block n: all entries point at the zero record.
         const int t0 = rd.x + tid;
         blk_load(bufA, blocks + (size_t)(t0 < rd.y ? t0 : n) * bu4);
     }
 
-    // Flush the byte energy accumulators into the block's per-replica deltas.
-    auto flush = [&]() {
+    // Per-replica energy changes of this lane: byte accumulators (YA: d - u,
+    // ZA: d, per accepted flip) are widened into E32 before a byte can
+    // overflow, and E32 is summed over the workgroup once per sweep.
+    int E32[W];
+#pragma unroll
+    for (int r = 0; r < W; ++r) E32[r] = 0;
+    auto widen = [&]() {
 #pragma unroll
         for (int q = 0; q < NR; ++q) {
 #pragma unroll
             for (int b = 0; b < 4; ++b) {
                 const int y = (int)((YA[q] >> (8 * b)) & 0xFFu);
                 const int z = (int)((ZA[q] >> (8 * b)) & 0xFFu);
-                int v = 4 * y - 2 * z;     // sum of 2m over accepted flips
-#pragma unroll
-                for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-                if (lane == 0 && v != 0) atomicAdd(&Ed[4 * q + b], v);
+                E32[4 * q + b] += 4 * y - 2 * z;     // sum of 2m over accepted flips
             }
             YA[q] = 0;
             ZA[q] = 0;
         }
     };
+    auto flush = [&]() {
+        widen();
+#pragma unroll
+        for (int r = 0; r < W; ++r) {
+            const int v = wave_sum_dpp(E32[r]);
+            if (lane == 0 && v != 0) atomicAdd(&Ed[r], v);
+            E32[r] = 0;
+        }
+    };
 
-    auto step = [&](int rg, Blk &cur, Blk &nxt, int4 &nd) {
-        const int s = rg / nrounds;
-        const int rho = rg - s * nrounds;
-        // Prefetch this lane's block of the next round (the next sweep wraps to
-        // round 0; after the last round this is a harmless reload).
-        nd = rounds[rho + 1 < nrounds ? rho + 1 : 0];
+    auto step = [&](int s, int rho, Blk &cur, Blk &nxt, int4 &n2) {
+        // The header of the round after next is loaded now and used one
+        // iteration later; this lane's block of the next round is prefetched
+        // (sweeps wrap to round 0; past the last round these are harmless
+        // reloads).
+        {
+            int r2 = rho + 2;
+            if (r2 >= nrounds) r2 -= nrounds;
+            if (r2 >= nrounds) r2 -= nrounds;
+            n2 = rounds[r2];
+        }
         {
             const int tn = nd.x + tid;
             blk_load(nxt, blocks + (size_t)(tn < nd.y ? tn : n) * bu4);
@@ -791,8 +820,11 @@ __global__ __launch_bounds__(1024) void sweep_bytes_kernel(SweepArgs a, const in
         }
         ++since_flush;
         const bool sweep_end = rho == nrounds - 1;
-        if (sweep_end || since_flush >= a.flush_every) {
+        if (sweep_end) {
             flush();
+            since_flush = 0;
+        } else if (since_flush >= a.flush_every) {
+            widen();
             since_flush = 0;
         }
         if (rd.z || sweep_end) __syncthreads();
@@ -838,11 +870,14 @@ __global__ __launch_bounds__(1024) void sweep_bytes_kernel(SweepArgs a, const in
 
     // One loop body: the next round's block is loaded into bufB while bufA is
     // processed, and rotated in at the end of the round.
-    for (int rg = 0; rg < total_rounds; ++rg) {
-        int4 nd;
-        step(rg, bufA, bufB, nd);
-        bufA = bufB;
-        rd = nd;
+    for (int s = 0; s < a.S; ++s) {
+        for (int rho = 0; rho < nrounds; ++rho) {
+            int4 n2;
+            step(s, rho, bufA, bufB, n2);
+            bufA = bufB;
+            rd = nd;
+            nd = n2;
+        }
     }
 
     for (int i = tid; i < n; i += nt) {

@@ -228,3 +228,38 @@ def test_g63_shape_full_run_properties(pa):
     assert np.all((st[:, 4] >= 0) & (st[:, 4] <= p.as_max_level))
     assert int(E.min()) >= s.best_info()["E"]
     assert cut > 26000   # G63-shaped graphs reach ~27,000 (paper: 27,047 on G63)
+
+
+def _hub_graph():
+    """Random graph plus one hub of degree > 30 (neighbours beyond the
+    register-held block columns are read from global memory)."""
+    base = W.random_graph(300, 900, 6)
+    i, j, w = base.edges()
+    hub = np.arange(1, 300, 7)                    # 43 neighbours of node 0
+    keep = (i != 0) & (j != 0)
+    ii = np.concatenate([i[keep], np.zeros(hub.size, np.int64)])
+    jj = np.concatenate([j[keep], hub])
+    sgn = np.where(W.splitmix64(11, ii.size) & np.uint64(1), -1, 1)
+    return W.from_edges(300, ii, jj, sgn, "hub300")
+
+
+BLOCK_CLASSES = {
+    "deg4": lambda: W.torus(10, 7, True, "torus10"),
+    "deg8": lambda: W.random_graph(400, 600, 2),
+    "deg13": lambda: W.random_graph(300, 900, 6),
+    "deg19": lambda: W.random_graph(1500, 6000, 21),
+    "deg27": lambda: W.random_graph(600, 4000, 5),
+    "hub": _hub_graph,
+}
+
+
+@pytest.mark.parametrize("cls", sorted(BLOCK_CLASSES))
+def test_every_adjacency_block_size(pa, cls):
+    """Maximum degrees in each adjacency-block size class (<= 4, <= 8, <= 16,
+    <= 24, <= 30, > 30) through the node-per-lane kernel."""
+    g = BLOCK_CLASSES[cls]()
+    _say(f"{cls}: n={g.n} dmax={g.degrees().max()}")
+    wl = dict(W.workload("small800"), graph=g, R=72, betas=W.linear_betas(0.2, 2.5, 5),
+              sweeps=2, order=W.natural_order(g.n), nl_period=2)
+    for tile in (4, 8):
+        _compare(pa, g, wl, dict(sweep_kernel=1, tile_replicas=tile))

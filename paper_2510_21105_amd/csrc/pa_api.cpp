@@ -72,6 +72,7 @@ struct Plan {
     std::vector<int> stream;        // kernel 2: [waves][qpad][2]
     std::vector<int> rounds;        // kernel 1: [n_rounds][4]
     std::vector<uint64_t> thr, wtab;
+    std::vector<uint32_t> thr32;   // kernel 1: [K][lmax1][dmax + 1] = T[1..dmax], saturation flag
     std::vector<int> wtab_off, wtab_len;
     Layout L{};
 };
@@ -280,9 +281,12 @@ static void build_blocks(const pa_solver *s, Plan &p)
         // Kernel 1: u16 {node, degree, neighbour record indices...}, padded
         // with the zero record's index to 8m - 2 entries (a multiple of 16
         // bytes with the header, at least the degree rounded up to 4).
-        // Negative edges name the complemented record n + j. Block n is an
-        // all-padding block for lanes without a node in a round.
-        const uint16_t zi = (uint16_t)(p.sgn ? 2 * n : n);
+        // Negative edges name the complemented record n + j. Record indices
+        // count from the start of LDS (the threshold table occupies the first
+        // rb records). Block n is an all-padding block for lanes without a
+        // node in a round.
+        const int rb = pa::kBytesRecBase / p.W;     // records start after the threshold table
+        const uint16_t zi = (uint16_t)((p.sgn ? 2 * n : n) + rb);
         const int need = 4 * ((std::max(s->dmax, 1) + 3) / 4);
         int capk = 6;
         while (capk < need) capk += 8;
@@ -298,7 +302,7 @@ static void build_blocks(const pa_solver *s, Plan &p)
             for (int e = e0; e < e1; ++e) {
                 const int j = s->col[e];
                 const bool neg = e >= e0 + s->npos[i];
-                b[2 + (e - e0)] = (uint16_t)(neg ? n + j : j);
+                b[2 + (e - e0)] = (uint16_t)((neg ? n + j : j) + rb);
             }
         }
         b16[(size_t)n * bw16] = 0;
@@ -415,7 +419,27 @@ static pa_status build_plan(pa_solver *s, const pa_schedule *sch, int R, Plan &p
     auto bytes_fit = [&](int W) { return pa::sweep_bytes_lds(W, p.sgn, n, s->dmax) <= max_lds; };
     auto words_fit = [&](int W) { return pa::sweep_lds_bytes(W, p.sgn, n, s->dmax, p.threads) <= max_lds; };
     int W = 0;
-    bool bytes_ok = s->dmax <= kMaxBytesDegree && (tile == 0 || tile <= 16);
+    // Kernel 1 compares draws with 32-bit thresholds. A row whose threshold
+    // is exactly 2^32 for some but not all uphill moves (beta * gamma^l nonzero
+    // but below about 6e-17, where exp rounds to 1) needs kernel 2.
+    bool partial_sat = false;
+    if (s->dmax >= 1)
+        for (int k = 0; k < p.K && !partial_sat; ++k) {
+            double g = 1.0;
+            for (int l = 0; l < p.lmax1; ++l) {
+                const double b = sch->beta[k] * g;
+                if (threshold_fixed(b, 1) == (1ull << 32) && threshold_fixed(b, s->dmax) != (1ull << 32))
+                    partial_sat = true;
+                g = g * sch->as_gamma;
+            }
+        }
+    if (req == 1 && partial_sat)
+        return fail(PA_ERANGE, "sweep kernel 1 cannot take an inverse temperature whose "
+                               "acceptance rounds to 1 for some uphill moves only");
+    // Record indices (complements and the zero record included, offset by the
+    // threshold table) are u16.
+    const bool idx_fit = (p.sgn ? 2 * n : n) + pa::kBytesRecBase / 4 <= 0xFFFF;
+    bool bytes_ok = s->dmax <= kMaxBytesDegree && (tile == 0 || tile <= 16) && !partial_sat && idx_fit;
     if (req == 1 && !bytes_ok)
         return fail(PA_EINVAL, "sweep kernel 1 needs max degree <= %d and tile 4, 8 or 16", kMaxBytesDegree);
     if (req != 2 && bytes_ok) {
@@ -485,7 +509,22 @@ static pa_status build_plan(pa_solver *s, const pa_schedule *sch, int R, Plan &p
         total = 1;
         if (tables) p.wtab.push_back(0);
     }
-    if (tables) {
+    if (tables && p.kind == 1) {
+        const int D = s->dmax + 1;
+        p.thr32.assign((size_t)p.K * p.lmax1 * D, 0);
+        for (int k = 0; k < p.K; ++k) {
+            double g = 1.0;
+            for (int l = 0; l < p.lmax1; ++l) {
+                const double b = sch->beta[k] * g;
+                uint32_t *row = &p.thr32[((size_t)k * p.lmax1 + l) * D];
+                for (int m = 1; m < D; ++m)
+                    row[m - 1] = (uint32_t)std::min<uint64_t>(threshold_fixed(b, m), 0xFFFFFFFFull);
+                // Every uphill move accepted (exp rounds to 1 up to the max degree).
+                row[D - 1] = s->dmax >= 1 && threshold_fixed(b, s->dmax) == (1ull << 32) ? 1u : 0u;
+                g = g * sch->as_gamma;
+            }
+        }
+    } else if (tables) {
         const int D = s->dmax + 1;
         p.thr.assign((size_t)p.K * p.lmax1 * D, 0);
         for (int k = 0; k < p.K; ++k) {
@@ -595,7 +634,12 @@ extern "C" pa_status pa_run(pa_solver *s, const pa_schedule *sch, int32_t R, uin
     else
         HIP_TRY(hipMemcpyAsync(ws + L.stream, P.stream.data(), sizeof(int) * P.stream.size(),
                                hipMemcpyHostToDevice, hs));
-    HIP_TRY(hipMemcpyAsync(ws + L.thr, P.thr.data(), sizeof(uint64_t) * P.thr.size(), hipMemcpyHostToDevice, hs));
+    if (P.kind == 1)
+        HIP_TRY(hipMemcpyAsync(ws + L.thr, P.thr32.data(), sizeof(uint32_t) * P.thr32.size(),
+                               hipMemcpyHostToDevice, hs));
+    else
+        HIP_TRY(hipMemcpyAsync(ws + L.thr, P.thr.data(), sizeof(uint64_t) * P.thr.size(),
+                               hipMemcpyHostToDevice, hs));
     HIP_TRY(hipMemcpyAsync(ws + L.wtab, P.wtab.data(), sizeof(uint64_t) * P.wtab.size(), hipMemcpyHostToDevice, hs));
     HIP_TRY(hipMemcpyAsync(ws + L.wtab_off, P.wtab_off.data(), sizeof(int) * P.K, hipMemcpyHostToDevice, hs));
     HIP_TRY(hipMemcpyAsync(ws + L.wtab_len, P.wtab_len.data(), sizeof(int) * P.K, hipMemcpyHostToDevice, hs));
@@ -691,6 +735,7 @@ extern "C" pa_status pa_run(pa_solver *s, const pa_schedule *sch, int32_t R, uin
     sa.sched = reinterpret_cast<const int *>(ws + L.sched);
     sa.level_off = reinterpret_cast<const int *>(ws + L.level_off);
     sa.thr = reinterpret_cast<const uint64_t *>(ws + L.thr);
+    sa.thr32 = reinterpret_cast<const uint32_t *>(ws + L.thr);
     sa.as_state = reinterpret_cast<const int *>(ws + L.as_state);
     sa.best_E = reinterpret_cast<const int *>(ws + L.best);
     sa.cand = U64(L.cand);

@@ -18,6 +18,8 @@ namespace pa {
 
 constexpr int kStatFields = 8;
 constexpr int kMaxThreads = 1024;
+// Kernel 1 LDS: the 128-entry u32 threshold table, then the byte records.
+constexpr int kBytesRecBase = 512;
 
 struct GraphDev {
     int n;
@@ -45,7 +47,8 @@ struct SweepArgs {
     const int4 *rounds;         // [n_rounds] {first slot, level end, last round of level, 0}
     int n_rounds;
     int flush_every;            // rounds between widenings of the byte energy accumulators
-    const uint64_t *thr;        // [K][lmax1][dmax+1]
+    const uint64_t *thr;        // kernel 2: [K][lmax1][dmax+1] T[m] (T[0] unused)
+    const uint32_t *thr32;      // kernel 1: [K][lmax1][dmax+1] T[1..dmax], all-accept flag
     const int *as_state;        // [0] level
     uint64_t *X;                // [G][n]
     int *E;                     // [Rp]

@@ -488,21 +488,25 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs a, const int2 *__
 // Adjacency blocks are read once per node and prefetched one round ahead
 // into the other of two register buffers.
 //
-// Bytewise arithmetic needs every count below 256, so this path serves
-// graphs with maximum degree <= 255; the per-replica energy changes are
-// gathered in byte accumulators that are flushed before they can overflow.
+// The tests work on the bytes 0x80 + (m - 1), m = d - 2u the half energy
+// change of a flip (u: edges the flip would break): bit 7 marks an uphill
+// move, and the low 7 bits index the 32-bit threshold table T[m] that sits at
+// LDS address 0 (for m >= 1 and beta > 0, T[m] < 2^32; a row where every
+// uphill threshold is 2^32 carries an accept-all flag instead). Bytewise
+// arithmetic keeps 0x7F + d inside a byte, so this path serves graphs with
+// maximum degree <= 127; the per-replica energy changes are gathered in byte
+// accumulators that are widened into registers before they can overflow.
 // ---------------------------------------------------------------------------
 struct BytesLds {
-    size_t rec, thr, edelta, misc, total;
+    size_t rec, edelta, misc, total;
 };
 
-__host__ __device__ inline BytesLds bytes_lds_layout(int W, int sgn, int n, int dmax)
+__host__ __device__ inline BytesLds bytes_lds_layout(int W, int sgn, int n, int /*dmax*/)
 {
     BytesLds L;
     const size_t recs = (size_t)(sgn ? 2 * n : n) + 1;
-    L.rec = 0;
-    L.thr = align16(recs * (size_t)W);
-    L.edelta = L.thr + align16((size_t)(dmax + 1) * 8);
+    L.rec = kBytesRecBase;                        // [0, 512): 128 u32 thresholds
+    L.edelta = L.rec + align16(recs * (size_t)W);
     L.misc = L.edelta + 64 * 4;
     L.total = L.misc + 16 * 8;
     return L;
@@ -602,13 +606,13 @@ __global__ __launch_bounds__(1024) void sweep_bytes_kernel(SweepArgs a, const in
     const int sub = (r0 & 63) / W;
 
     const BytesLds L = bytes_lds_layout(W, SIGNED ? 1 : 0, n, a.dmax);
-    uint64_t *T = reinterpret_cast<uint64_t *>(smem + L.thr);
+    uint32_t *T = reinterpret_cast<uint32_t *>(smem);               // T[m] at index m - 1
     int *Ed = reinterpret_cast<int *>(smem + L.edelta);
     long long *misc = reinterpret_cast<long long *>(smem + L.misc);
     int *Eblk = reinterpret_cast<int *>(misc + 4);
+    constexpr uint32_t RB = kBytesRecBase;                        // LDS address of record 0
     const uint32_t comp = (uint32_t)n * W;                        // complemented records
-    const uint32_t zrec = (uint32_t)(SIGNED ? 2 * n : n) * W;     // zero record
-    const uint32_t toff = (uint32_t)L.thr;
+    const uint32_t zrec = RB + (uint32_t)(SIGNED ? 2 * n : n) * W;  // zero record
 
     uint64_t *Xg = a.X + (size_t)grp * n;
     // Expand the block's spin bits into byte records, 4 loads in flight per lane.
@@ -627,18 +631,20 @@ __global__ __launch_bounds__(1024) void sweep_bytes_kernel(SweepArgs a, const in
             Rec<NR> rc;
 #pragma unroll
             for (int q = 0; q < NR; ++q) rc.v[q] = spread4((uint32_t)(v >> (4 * q)));
-            rec_store<NR>((uint32_t)i * W, rc);
+            rec_store<NR>(RB + (uint32_t)i * W, rc);
             if constexpr (SIGNED) {
 #pragma unroll
                 for (int q = 0; q < NR; ++q) rc.v[q] ^= 0x01010101u;
-                rec_store<NR>(comp + (uint32_t)i * W, rc);
+                rec_store<NR>(RB + comp + (uint32_t)i * W, rc);
             }
         }
     }
     if (tid < NR) *(lds_u32 *)(uintptr_t)(zrec + 4 * tid) = 0u;
     const int level = a.as_state[0];
-    const uint64_t *trow = a.thr + ((size_t)a.k * a.lmax1 + level) * (size_t)(a.dmax + 1);
-    for (int m = tid; m <= a.dmax; m += nt) T[m] = m == 0 ? (1ull << 32) : trow[m];
+    const uint32_t *trow = a.thr32 + ((size_t)a.k * a.lmax1 + level) * (size_t)(a.dmax + 1);
+    for (int m = tid; m < 128; m += nt) T[m] = m < a.dmax ? trow[m] : 0u;
+    // Accept-all row (exp(-beta * 2m) rounds to 1 for every uphill move).
+    const uint32_t allm = trow[a.dmax] ? 0x01010101u : 0u;
     if (tid < W) {
         Eblk[tid] = (r0 + tid < a.R) ? a.E[r0 + tid] : 0;
         Ed[tid] = 0;
@@ -683,8 +689,9 @@ __global__ __launch_bounds__(1024) void sweep_bytes_kernel(SweepArgs a, const in
     }
 
     // Per-replica energy changes of this lane: byte accumulators (YA: d - u,
-    // ZA: d, per accepted flip) are widened into E32 before a byte can
-    // overflow, and E32 is summed over the workgroup once per sweep.
+    // ZA: u, per accepted flip; the flip changes E by 2(d - 2u)) are widened
+    // into E32 before a byte can overflow, and E32 is summed over the
+    // workgroup once per sweep.
     int E32[W];
 #pragma unroll
     for (int r = 0; r < W; ++r) E32[r] = 0;
@@ -695,7 +702,7 @@ __global__ __launch_bounds__(1024) void sweep_bytes_kernel(SweepArgs a, const in
             for (int b = 0; b < 4; ++b) {
                 const int y = (int)((YA[q] >> (8 * b)) & 0xFFu);
                 const int z = (int)((ZA[q] >> (8 * b)) & 0xFFu);
-                E32[4 * q + b] += 4 * y - 2 * z;     // sum of 2m over accepted flips
+                E32[4 * q + b] += 2 * (y - z);       // sum of 2m over accepted flips
             }
             YA[q] = 0;
             ZA[q] = 0;
@@ -731,7 +738,7 @@ __global__ __launch_bounds__(1024) void sweep_bytes_kernel(SweepArgs a, const in
         if (wave_first < rd.y) {            // some lane of this wave has a node
             const bool active = t < rd.y;
             const uint32_t node = cur.b0.x & 0xFFFFu;
-            const uint32_t noff = active ? node << SHW : zrec;
+            const uint32_t noff = active ? RB + (node << SHW) : zrec;
             const int d = active ? (int)(cur.b0.x >> 16) : 0;
             // Levels are sorted by decreasing degree: the wave's first lane has its largest degree.
             const int md = __builtin_amdgcn_readfirstlane(d);
@@ -780,34 +787,31 @@ __global__ __launch_bounds__(1024) void sweep_bytes_kernel(SweepArgs a, const in
 #undef PA_NB
             if (active) {
                 const Rec<NR> X = rec_load<NR>(noff);
-                const uint32_t Dm = (uint32_t)d * 0x01010101u;
-                const uint32_t base8d = toff + 8u * (uint32_t)d;
+                const uint32_t Dm = __builtin_amdgcn_perm(0u, (uint32_t)d, 0u);   // d in every byte
                 Rec<NR> Xn;
 #pragma unroll
                 for (int q = 0; q < NR; ++q) {
                     // u = x ? c : d - c  (edges with w_ij x_i x_j = +1), per byte
-                    const uint32_t msk = X.v[q] * 0xFFu;
+                    const uint32_t msk = (X.v[q] << 8) - X.v[q];
                     const uint32_t U = (C[q] & msk) | ((Dm - C[q]) & ~msk);
                     const U4 o = philox10_wide(U4{node, (uint32_t)s, k, rgrp0 + (uint32_t)q},
                                                a.seed_lo, a.seed_hi);
                     const uint32_t dr[4] = {o.x, o.y, o.z, o.w};
-                    uint32_t A = 0;
+                    // w = 0x80 + (m - 1) per byte with m = d - 2u
+                    const uint32_t w = (0x7F7F7F7Fu + Dm) - 2u * U;
+                    uint32_t A = ((~w >> 7) & 0x01010101u) | allm;   // m <= 0 always accepts
 #pragma unroll
                     for (int b = 0; b < 4; ++b) {
-                        // T[max(d - 2u, 0)]: T[0] = 2^32 accepts every downhill move
-                        const int ad = (int)(base8d - (((U >> (8 * b)) & 0xFFu) << 4));
-                        const uint32_t aoff = (uint32_t)(ad < (int)toff ? (int)toff : ad);
-                        const uint64_t th = *(lds_u64 *)(uintptr_t)aoff;
-                        A |= ((uint64_t)dr[b] < th ? 1u : 0u) << (8 * b);
+                        const uint32_t th = T[(w >> (8 * b)) & 0x7Fu];
+                        A |= (dr[b] < th ? 1u : 0u) << (8 * b);
                     }
                     Xn.v[q] = X.v[q] ^ A;
-                    // uphill (2u < d) markers: byte 0x80 + (d - 1) - 2u >= 0x80
-                    const uint32_t up = (0x80808080u + Dm - 0x01010101u - 2u * U) & real80[q];
+                    const uint32_t up = w & real80[q];           // uphill markers
                     att += __builtin_popcount(up);
                     acc += __builtin_popcount(up & (A << 7));
-                    const uint32_t Am = A * 0xFFu;
-                    YA[q] += (Dm - U) & Am;
-                    ZA[q] += A * (uint32_t)d;
+                    const uint32_t Am = (A << 8) - A;
+                    YA[q] += (Dm - U) & Am;                      // d - u of accepted flips
+                    ZA[q] += U & Am;                             // u of accepted flips
                 }
                 rec_store<NR>(noff, Xn);
                 if constexpr (SIGNED) {
@@ -855,7 +859,7 @@ __global__ __launch_bounds__(1024) void sweep_bytes_kernel(SweepArgs a, const in
             const int sq = (int)misc[2];
             if (sq >= 0) {
                 uint32_t *dst = a.snap + (size_t)blk * a.nw32;
-                const unsigned char *rb = smem;
+                const unsigned char *rb = smem + RB;
                 for (int w = tid; w < a.nw32; w += nt) {
                     uint32_t bits = 0;
                     const int ib = w * 32;
@@ -881,7 +885,7 @@ __global__ __launch_bounds__(1024) void sweep_bytes_kernel(SweepArgs a, const in
     }
 
     for (int i = tid; i < n; i += nt) {
-        const Rec<NR> rc = rec_load<NR>((uint32_t)i * W);
+        const Rec<NR> rc = rec_load<NR>(RB + (uint32_t)i * W);
         uint64_t v = 0;
 #pragma unroll
         for (int q = 0; q < NR; ++q) v |= (uint64_t)gather4(rc.v[q]) << (4 * q);

@@ -184,3 +184,17 @@ def test_auto_launch_choice_is_reported_in_workspace_plan():
         _bytes(s, pa.params_from_workload(wl, sweep_kernel=1))
     assert e.value.status == pa.PA_EINVAL
     assert _bytes(s, pa.params_from_workload(wl)) > 0       # automatic choice falls back
+
+
+def test_partially_saturated_threshold_row_needs_the_word_kernel():
+    """beta = 1e-17: exp(-2 beta m) rounds to 1 for m = 1 but not for m = 20,
+    which the 32-bit thresholds of kernel 1 cannot express."""
+    wl = dict(W.workload("small800"), betas=[1e-17, 0.5])
+    s = pa.Solver(wl["graph"])
+    assert wl["graph"].degrees().max() == 20
+    with pytest.raises(pa.PAError) as e:
+        _bytes(s, pa.params_from_workload(wl, sweep_kernel=1))
+    assert e.value.status == pa.PA_ERANGE
+    assert _bytes(s, pa.params_from_workload(wl)) > 0          # automatic choice: kernel 2
+    # a fully saturated row (every uphill threshold 2^32) stays on kernel 1
+    assert _bytes(s, pa.params_from_workload(dict(wl, betas=[0.0, 1e-20, 0.5]), sweep_kernel=1)) > 0

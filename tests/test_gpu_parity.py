@@ -263,3 +263,14 @@ def test_every_adjacency_block_size(pa, cls):
               sweeps=2, order=W.natural_order(g.n), nl_period=2)
     for tile in (4, 8):
         _compare(pa, g, wl, dict(sweep_kernel=1, tile_replicas=tile))
+
+
+def test_tiny_inverse_temperatures(pa):
+    """beta = 0 and 1e-20 (every uphill move accepted), 1e-17 (exp rounds to 1
+    for the smallest moves only: served by the word kernel), then normal."""
+    g = W.random_graph(800, 4000, 1, "small800")
+    wl = dict(W.workload("small800"), R=70, betas=[0.0, 1e-20, 0.3], sweeps=2)
+    s, _ = _compare(pa, g, wl, dict(sweep_kernel=1))
+    assert s.launch_info()["sweep_kernel"] == 1
+    s, _ = _compare(pa, g, dict(wl, betas=[1e-20, 1e-17, 0.3]))
+    assert s.launch_info()["sweep_kernel"] == 2

@@ -742,17 +742,36 @@ __global__ __launch_bounds__(1024) void sweep_bytes_kernel(SweepArgs a, const in
             const int d = active ? (int)(cur.b0.x >> 16) : 0;
             // Levels are sorted by decreasing degree: the wave's first lane has its largest degree.
             const int md = __builtin_amdgcn_readfirstlane(d);
+            // The own record and the first four neighbours are read before the
+            // draws are computed, so that their LDS latency overlaps the Philox
+            // arithmetic (the scheduling barriers and the empty asm keep the
+            // compiler from moving the draws after the first use of the reads).
+            // Lanes past their degree read the zero record.
+            const Rec<NR> X = rec_load<NR>(noff);
+            const Rec<NR> g0 = rec_load<NR>((cur.b0.y & 0xFFFFu) << SHW);
+            const Rec<NR> g1 = rec_load<NR>((cur.b0.y >> 16) << SHW);
+            const Rec<NR> g2 = rec_load<NR>((cur.b0.z & 0xFFFFu) << SHW);
+            const Rec<NR> g3 = rec_load<NR>((cur.b0.z >> 16) << SHW);
+            __builtin_amdgcn_sched_barrier(0);
+            uint32_t dr[NR][4];
+#pragma unroll
+            for (int q = 0; q < NR; ++q) {
+                const U4 o = philox10_wide(U4{node, (uint32_t)s, k, rgrp0 + (uint32_t)q}, a.seed_lo,
+                                           a.seed_hi);
+                dr[q][0] = o.x; dr[q][1] = o.y; dr[q][2] = o.z; dr[q][3] = o.w;
+                asm volatile("" ::"v"(dr[q][0]), "v"(dr[q][1]), "v"(dr[q][2]), "v"(dr[q][3]));
+            }
+            __builtin_amdgcn_sched_barrier(0);
             uint32_t C[NR];
 #pragma unroll
-            for (int q = 0; q < NR; ++q) C[q] = 0;
+            for (int q = 0; q < NR; ++q) C[q] = (g0.v[q] + g1.v[q]) + (g2.v[q] + g3.v[q]);
 #define PA_NB(off)                                              \
     {                                                           \
         const Rec<NR> nb = rec_load<NR>(off);                   \
         _Pragma("unroll") for (int q = 0; q < NR; ++q) C[q] += nb.v[q]; \
     }
 #define PA_W(w) PA_NB(((w) & 0xFFFFu) << SHW) PA_NB(((w) >> 16) << SHW)
-            if (md > 0) {
-                PA_W(cur.b0.y) PA_W(cur.b0.z)
+            {
                 if (md > 4) {
                     PA_W(cur.b0.w) PA_W(cur.b1.x)
                     if (md > 8) {
@@ -786,7 +805,6 @@ __global__ __launch_bounds__(1024) void sweep_bytes_kernel(SweepArgs a, const in
 #undef PA_W
 #undef PA_NB
             if (active) {
-                const Rec<NR> X = rec_load<NR>(noff);
                 const uint32_t Dm = __builtin_amdgcn_perm(0u, (uint32_t)d, 0u);   // d in every byte
                 Rec<NR> Xn;
 #pragma unroll
@@ -794,16 +812,13 @@ __global__ __launch_bounds__(1024) void sweep_bytes_kernel(SweepArgs a, const in
                     // u = x ? c : d - c  (edges with w_ij x_i x_j = +1), per byte
                     const uint32_t msk = (X.v[q] << 8) - X.v[q];
                     const uint32_t U = (C[q] & msk) | ((Dm - C[q]) & ~msk);
-                    const U4 o = philox10_wide(U4{node, (uint32_t)s, k, rgrp0 + (uint32_t)q},
-                                               a.seed_lo, a.seed_hi);
-                    const uint32_t dr[4] = {o.x, o.y, o.z, o.w};
                     // w = 0x80 + (m - 1) per byte with m = d - 2u
                     const uint32_t w = (0x7F7F7F7Fu + Dm) - 2u * U;
                     uint32_t A = ((~w >> 7) & 0x01010101u) | allm;   // m <= 0 always accepts
 #pragma unroll
                     for (int b = 0; b < 4; ++b) {
                         const uint32_t th = T[(w >> (8 * b)) & 0x7Fu];
-                        A |= (dr[b] < th ? 1u : 0u) << (8 * b);
+                        A |= (dr[q][b] < th ? 1u : 0u) << (8 * b);
                     }
                     Xn.v[q] = X.v[q] ^ A;
                     const uint32_t up = w & real80[q];           // uphill markers
@@ -833,31 +848,37 @@ __global__ __launch_bounds__(1024) void sweep_bytes_kernel(SweepArgs a, const in
         }
         if (rd.z || sweep_end) __syncthreads();
         if (sweep_end) {
-            // Energies after sweep s and the block's best candidate.
-            if (tid < W) {
-                Eblk[tid] += Ed[tid];
-                Ed[tid] = 0;
-            }
-            __syncthreads();
-            if (tid == 0) {
-                long long be = misc[0];
-                int arg = -1;
-                for (int qq = 0; qq < W && r0 + qq < a.R; ++qq)
-                    if ((long long)Eblk[qq] < be) {
-                        be = Eblk[qq];
-                        arg = qq;
+            // Energies after sweep s and the block's best candidate, in wave 0
+            // (lowest energy, then lowest replica; strict improvement only).
+            if (tid < 64) {
+                unsigned long long key = ~0ull;
+                if (tid < W) {
+                    const int e = Eblk[tid] + Ed[tid];
+                    Eblk[tid] = e;
+                    Ed[tid] = 0;
+                    if (r0 + tid < a.R)
+                        key = ((unsigned long long)((uint32_t)e ^ 0x80000000u) << 32) | (unsigned)tid;
+                }
+                key = wave_min_u64(key);
+                if (tid == 0) {
+                    int arg = -1;
+                    if (key != ~0ull) {
+                        const long long be = (long long)(int)((uint32_t)(key >> 32) ^ 0x80000000u);
+                        if (be < misc[0]) {
+                            arg = (int)(key & 0xFFFFFFFFu);
+                            misc[0] = be;
+                            misc[1] = (long long)(((key >> 32) << 32) | ((unsigned long long)s << 15) |
+                                                  (unsigned long long)(r0 + arg));
+                        }
                     }
-                misc[2] = arg;
-                if (arg >= 0) {
-                    misc[0] = be;
-                    misc[1] = (long long)((((unsigned long long)((uint32_t)be ^ 0x80000000u)) << 32) |
-                                          ((unsigned long long)s << 15) |
-                                          (unsigned long long)(r0 + arg));
+                    misc[2] = arg;
                 }
             }
             __syncthreads();
             const int sq = (int)misc[2];
             if (sq >= 0) {
+                // Snapshot of the improving replica; the next round may only
+                // rewrite records after every lane has read them.
                 uint32_t *dst = a.snap + (size_t)blk * a.nw32;
                 const unsigned char *rb = smem + RB;
                 for (int w = tid; w < a.nw32; w += nt) {
@@ -867,8 +888,8 @@ __global__ __launch_bounds__(1024) void sweep_bytes_kernel(SweepArgs a, const in
                         bits |= (uint32_t)(rb[(size_t)(ib + b) * W + sq] & 1u) << b;
                     dst[w] = bits;
                 }
+                __syncthreads();
             }
-            __syncthreads();
         }
     };
 

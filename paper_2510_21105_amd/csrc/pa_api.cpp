@@ -58,7 +58,7 @@ constexpr size_t kAlign = 256;
 size_t align_up(size_t b, size_t a = kAlign) { return (b + a - 1) / a * a; }
 
 struct Layout {
-    size_t row_ptr, col, npos, sched, level_off, blocks, stream, thr, wtab, wtab_off, wtab_len;
+    size_t row_ptr, col, npos, edges, vout, sched, level_off, blocks, stream, thr, wtab, wtab_off, wtab_len;
     size_t X0, X1, E0, E1, cand, snap, counters, as_state, best, best_x, stats, parent;
     size_t counts, xinit, total;
 };
@@ -86,6 +86,7 @@ struct pa_solver {
     long long w_tot = 0;
     int has_neg = 0;
     std::vector<int> row_ptr, col, npos;
+    std::vector<uint32_t> edges;   // each edge once (i < j): i | j << 15 | negative << 30
     // last run
     bool has_run = false;
     Plan plan;
@@ -164,6 +165,11 @@ extern "C" pa_status pa_create(pa_solver **out, int32_t n, const int32_t *row_pt
         s->npos[i] = np;
     }
     s->row_ptr[n] = (int)e;
+    s->edges.reserve(nnz / 2);
+    for (int i = 0; i < n; ++i)
+        for (auto &jw : rows[i])
+            if (jw.first > i)
+                s->edges.push_back((uint32_t)i | ((uint32_t)jw.first << 15) | (jw.second < 0 ? 1u << 30 : 0u));
     *out = s;
     return PA_OK;
 }
@@ -416,6 +422,10 @@ static pa_status build_plan(pa_solver *s, const pa_schedule *sch, int R, Plan &p
     p.sgn = s->has_neg;
     const int req = sch->sweep_kernel, tile = sch->tile_replicas;
     if (req < 0 || req > 2) return fail(PA_EINVAL, "sweep_kernel must be 0, 1 or 2");
+    // The cluster move keeps n union-find parents and three n-bit bitmaps in LDS
+    // (plus 2.2 KB of fixed scratch).
+    if (sch->nl_period > 0 && pa::icm_lds_bytes(n, p.nw32) + 4096 > max_lds)
+        return fail(PA_ERANGE, "cluster moves on %d nodes exceed the LDS of a workgroup", n);
     auto bytes_fit = [&](int W) { return pa::sweep_bytes_lds(W, p.sgn, n, s->dmax) <= max_lds; };
     auto words_fit = [&](int W) { return pa::sweep_lds_bytes(W, p.sgn, n, s->dmax, p.threads) <= max_lds; };
     int W = 0;
@@ -549,6 +559,8 @@ static pa_status build_plan(pa_solver *s, const pa_schedule *sch, int R, Plan &p
     L.row_ptr = take(sizeof(int) * (n + 1));
     L.col = take(sizeof(int) * s->nnz);
     L.npos = take(sizeof(int) * n);
+    L.edges = take(sizeof(uint32_t) * s->edges.size());
+    L.vout = sch->nl_period > 0 ? take(sizeof(uint32_t) * (size_t)(R / 2) * p.nw32) : 0;
     L.sched = take(sizeof(int) * n);
     L.level_off = take(sizeof(int) * (p.n_levels + 1));
     L.blocks = take(sizeof(uint32_t) * p.blocks.size());
@@ -623,6 +635,9 @@ extern "C" pa_status pa_run(pa_solver *s, const pa_schedule *sch, int32_t R, uin
     if (s->nnz)
         HIP_TRY(hipMemcpyAsync(ws + L.col, s->col.data(), sizeof(int) * s->nnz, hipMemcpyHostToDevice, hs));
     HIP_TRY(hipMemcpyAsync(ws + L.npos, s->npos.data(), sizeof(int) * n, hipMemcpyHostToDevice, hs));
+    if (!s->edges.empty())
+        HIP_TRY(hipMemcpyAsync(ws + L.edges, s->edges.data(), sizeof(uint32_t) * s->edges.size(),
+                               hipMemcpyHostToDevice, hs));
     HIP_TRY(hipMemcpyAsync(ws + L.sched, P.sched.data(), sizeof(int) * n, hipMemcpyHostToDevice, hs));
     HIP_TRY(hipMemcpyAsync(ws + L.level_off, P.level_off.data(), sizeof(int) * (P.n_levels + 1),
                            hipMemcpyHostToDevice, hs));
@@ -657,6 +672,8 @@ extern "C" pa_status pa_run(pa_solver *s, const pa_schedule *sch, int32_t R, uin
     gd.row_ptr = reinterpret_cast<const int *>(ws + L.row_ptr);
     gd.col = reinterpret_cast<const int *>(ws + L.col);
     gd.npos = reinterpret_cast<const int *>(ws + L.npos);
+    gd.edges = reinterpret_cast<const uint32_t *>(ws + L.edges);
+    gd.ne = (int)s->edges.size();
     const uint32_t seed_lo = (uint32_t)seed, seed_hi = (uint32_t)(seed >> 32);
 
     size_t Xc = L.X0, Xn = L.X1, Ec = L.E0, En = L.E1;
@@ -776,6 +793,7 @@ extern "C" pa_status pa_run(pa_solver *s, const pa_schedule *sch, int32_t R, uin
             pa::IcmArgs ic;
             ic.g = gd;
             ic.R = R;
+            ic.G = P.G;
             ic.k = k;
             ic.nw32 = P.nw32;
             ic.seed_lo = seed_lo;
@@ -783,6 +801,7 @@ extern "C" pa_status pa_run(pa_solver *s, const pa_schedule *sch, int32_t R, uin
             ic.inst = instance;
             ic.X = reinterpret_cast<uint64_t *>(ws + Xc);
             ic.E = reinterpret_cast<int *>(ws + Ec);
+            ic.vout = reinterpret_cast<uint32_t *>(ws + L.vout);
             LAUNCH_TRY(pa::launch_icm(ic, hs));
             e.do_pop = 1;
             e.pop_step = k;

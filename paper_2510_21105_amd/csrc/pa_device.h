@@ -27,6 +27,8 @@ struct GraphDev {
     const int *row_ptr;
     const int *col;
     const int *npos;
+    const uint32_t *edges;      // [ne] each edge once, i < j: i | j << 15 | negative << 30
+    int ne;
 };
 
 struct SweepArgs {
@@ -92,10 +94,11 @@ struct GatherArgs {
 
 struct IcmArgs {
     GraphDev g;
-    int R, k, nw32;
+    int R, G, k, nw32;
     uint32_t seed_lo, seed_hi, inst;
     uint64_t *X;
     int *E;
+    uint32_t *vout;             // [R/2][nw32] cluster bitmap of each pair
 };
 
 struct InitArgs {
@@ -116,6 +119,7 @@ int launch_sweep_bytes(int W, int sgn, int threads, int nblk, const SweepArgs &a
 int launch_epilogue(const EpiArgs &a, void *stream);
 int launch_gather(const GatherArgs &a, void *stream);
 int launch_icm(const IcmArgs &a, void *stream);
+int icm_lds_bytes(int n, int nw32);
 int launch_fill_u64(unsigned long long *p, unsigned long long v, long long count, void *stream);
 const char *last_hip_error();
 

@@ -1099,52 +1099,110 @@ __global__ __launch_bounds__(1024) void epilogue_kernel(EpiArgs a)
 // parents of consecutive slots are non-decreasing, so a wave's 64 loads hit
 // one or two groups.
 // ---------------------------------------------------------------------------
-constexpr int kGatherNodesPerWave = 32;
+constexpr int kGatherNodesPerWave = 64;
 
 __global__ __launch_bounds__(256) void gather_kernel(GatherArgs a)
 {
     const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int g = blockIdx.y;
     const int q = g * 64 + lane;
     const int p = q < a.R ? a.parent[q] : -1;
     const int i0 = (blockIdx.x * 4 + wave) * kGatherNodesPerWave;
-    const uint64_t *src = p >= 0 ? a.Xin + (size_t)(p >> 6) * a.n : a.Xin;
     const int pb = p & 63;
-    for (int t = 0; t < kGatherNodesPerWave; ++t) {
-        const int i = i0 + t;
-        if (i >= a.n) break;
-        const int bit = p >= 0 ? (int)((src[i] >> pb) & 1ull) : 0;
-        const unsigned long long mask = __ballot(bit);
-        if (lane == 0) a.Xout[(size_t)g * a.n + i] = mask;
+    // Systematic resampling hands out slots in parent order, so the lanes of
+    // a wave usually read one or two parent words per node, which the memory
+    // pipeline merges into one or two cache-line requests.
+    const uint64_t *src = a.Xin + (size_t)(p >= 0 ? p >> 6 : 0) * a.n;
+    // Batches of 16 loads in flight; indices past the last node are clamped
+    // (their words are never stored).
+    uint64_t out = 0;
+    for (int t0 = 0; t0 < kGatherNodesPerWave; t0 += 16) {
+        uint64_t w[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int i = i0 + t0 + u;
+            w[u] = src[i < a.n ? i : a.n - 1];
+        }
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const unsigned long long mask = __ballot(p >= 0 && ((w[u] >> pb) & 1ull));
+            if (lane == t0 + u) out = mask;
+        }
     }
+    // Lane t holds the word of node i0 + t: one coalesced store per wave.
+    if (lane < kGatherNodesPerWave && i0 + lane < a.n) a.Xout[(size_t)g * a.n + i0 + lane] = out;
     if (blockIdx.x == 0 && wave == 0 && q < a.R) a.Eout[q] = a.Ein[p];
 }
 
 // ---------------------------------------------------------------------------
 // Non-local move: Houdayer cluster move on the pair (p, p + R/2). One
-// workgroup per pair; bitmaps of the disagreement set D, the cluster and the
-// BFS frontiers live in LDS.
+// workgroup per pair finds the connected component of the seed node inside
+// the disagreement set D with a union-find over the edge list (parents in
+// LDS), computes the energy change of replica a from the edges that cross
+// the cluster boundary, and writes the cluster bitmap; icm_apply_kernel then
+// flips the clusters of all pairs in the population words.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void icm_kernel(IcmArgs a)
+
+// Root of x with path halving. Roots are only ever hooked under smaller
+// roots and halving links x to an ancestor, so P[x] <= x always holds and
+// every step strictly decreases x: the walk ends within n steps.
+__device__ __forceinline__ uint32_t uf_find(volatile uint32_t *P, uint32_t x)
 {
-    // LDS bitmaps (nw words each): A = spins of replica a, D = disagreement
-    // set, V = cluster, F / Nx = BFS frontiers; plus per-thread scan slots.
-    extern __shared__ __align__(16) uint32_t bm[];
+    for (;;) {
+        const uint32_t px = P[x];
+        if (px >= x) return x;
+        const uint32_t ppx = P[px];
+        if (ppx != px) P[x] = ppx;
+        x = ppx;
+    }
+}
+
+// Merge the sets of x and y (lock-free: a failed hook means another lane
+// hooked that root, which happens at most once per root).
+__device__ __forceinline__ void uf_unite(volatile uint32_t *P, uint32_t x, uint32_t y)
+{
+    for (;;) {
+        x = uf_find(P, x);
+        y = uf_find(P, y);
+        if (x == y) return;
+        if (x > y) {
+            const uint32_t t = x;
+            x = y;
+            y = t;
+        }
+        if (atomicCAS(const_cast<uint32_t *>(&P[y]), y, x) == y) return;
+    }
+}
+
+constexpr int kIcmThreads = 512;
+
+int icm_lds_bytes(int n, int nw32)
+{
+    return (n + 3 * nw32) * 4;
+}
+
+__global__ __launch_bounds__(kIcmThreads) void icm_kernel(IcmArgs a)
+{
+    // LDS: P = union-find parents [n], bitmaps A = spins of replica a,
+    // D = disagreement set, V = cluster (nw words each).
+    extern __shared__ __align__(16) uint32_t lds[];
     __shared__ long long red_l[16];
-    __shared__ int scan_i[256];
-    __shared__ int seed_s;
+    __shared__ int scan_i[kIcmThreads];
+    __shared__ uint32_t root_s;
     const int tid = threadIdx.x, lane = tid & 63, nt = blockDim.x;
     const int n = a.g.n, nw = a.nw32;
-    uint32_t *A = bm, *D = bm + nw, *V = bm + 2 * nw, *F = bm + 3 * nw, *Nx = bm + 4 * nw;
+    volatile uint32_t *P = lds;
+    uint32_t *A = lds + n, *D = A + nw, *V = D + nw;
     const int p = blockIdx.x, half = a.R / 2;
     const int ra = p, rb = p + half;
     const int ba = ra & 63, bb = rb & 63;
     const uint64_t *Xa = a.X + (size_t)(ra >> 6) * n;
     const uint64_t *Xb = a.X + (size_t)(rb >> 6) * n;
+    uint32_t *Vout = a.vout + (size_t)p * nw;
 
-    for (int w = tid; w < nw; w += nt) { V[w] = 0; F[w] = 0; Nx[w] = 0; }
-    // Spins of a and of the disagreement set, 4 independent loads in flight per lane.
+    // Spins of a, the disagreement set and singleton parents; 4 independent
+    // loads per replica in flight per lane.
     int cnt = 0;
     for (int base = 0; base < nw * 32; base += 4 * nt) {
         uint64_t va[4], vb[4];
@@ -1157,6 +1215,7 @@ __global__ __launch_bounds__(256) void icm_kernel(IcmArgs a)
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const int i = base + u * nt + tid;
+            if (i < n) P[i] = (uint32_t)i;
             const int xa = (int)((va[u] >> ba) & 1ull);
             const int dd = i < n ? xa ^ (int)((vb[u] >> bb) & 1ull) : 0;
             const unsigned long long ma = __ballot(xa), md = __ballot(dd);
@@ -1167,7 +1226,27 @@ __global__ __launch_bounds__(256) void icm_kernel(IcmArgs a)
         }
     }
     const long long total = block_sum_ll(cnt, red_l);
-    if (total == 0) return;
+    if (total == 0) {
+        for (int w = tid; w < nw; w += nt) Vout[w] = 0u;
+        return;
+    }
+    auto inD = [&](uint32_t i) { return (D[i >> 5] >> (i & 31)) & 1u; };
+    // Components of the subgraph induced by D.
+    const uint32_t *edges = a.g.edges;
+    const int ne = a.g.ne;
+    for (int e0 = tid; e0 < ne; e0 += 8 * nt) {
+        uint32_t ev[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int idx = e0 + u * nt;
+            ev[u] = idx < ne ? edges[idx] : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const uint32_t i = ev[u] & 0x7FFFu, j = (ev[u] >> 15) & 0x7FFFu;
+            if (e0 + u * nt < ne && inD(i) && inD(j)) uf_unite(P, i, j);
+        }
+    }
     // Seed node: the pick-th element of D in node order (scan of per-thread word chunks).
     const uint32_t d = draw(a.seed_lo, a.seed_hi, a.inst, 3, 0, (uint32_t)a.k, 0u, (uint32_t)p);
     const int pick = (int)(((uint64_t)d * (uint64_t)total) >> 32);
@@ -1176,7 +1255,7 @@ __global__ __launch_bounds__(256) void icm_kernel(IcmArgs a)
     int mine = 0;
     for (int w = w_lo; w < w_hi; ++w) mine += __popc(D[w]);
     scan_i[tid] = mine;
-    __syncthreads();
+    __syncthreads();        // also completes the unions
     for (int o = 1; o < nt; o <<= 1) {
         const int v = tid >= o ? scan_i[tid - o] : 0;
         __syncthreads();
@@ -1193,78 +1272,68 @@ __global__ __launch_bounds__(256) void icm_kernel(IcmArgs a)
         }
         uint32_t bits = D[w];
         for (int t = c; t < pick; ++t) bits &= bits - 1;
-        const int s0 = w * 32 + __ffs(bits) - 1;
-        seed_s = s0;
-        V[s0 >> 5] = 1u << (s0 & 31);
-        F[s0 >> 5] = 1u << (s0 & 31);
+        root_s = uf_find(P, (uint32_t)(w * 32 + __ffs(bits) - 1));
     }
     __syncthreads();
-    // Level-synchronous BFS inside D.
-    for (;;) {
-        long long grew = 0;
-        for (int w = tid; w < nw; w += nt) {
-            uint32_t f = F[w];
-            while (f) {
-                const int b = __ffs(f) - 1;
-                f &= f - 1;
-                const int i = w * 32 + b;
-                for (int e = a.g.row_ptr[i]; e < a.g.row_ptr[i + 1]; ++e) {
-                    const int j = a.g.col[e];
-                    const uint32_t jb = 1u << (j & 31);
-                    if ((D[j >> 5] & jb) && !(V[j >> 5] & jb)) {
-                        const uint32_t old = atomicOr(&V[j >> 5], jb);
-                        if (!(old & jb)) {
-                            atomicOr(&Nx[j >> 5], jb);
-                            grew = 1;
-                        }
-                    }
-                }
-            }
-        }
-        grew = block_sum_ll(grew, red_l);
-        if (grew == 0) break;
-        uint32_t *t = F; F = Nx; Nx = t;
-        for (int w = tid; w < nw; w += nt) Nx[w] = 0;
-        __syncthreads();
+    const uint32_t root = root_s;
+    // Cluster = the seed's component.
+    for (int base = 0; base < nw * 32; base += nt) {
+        const int i = base + tid;
+        const bool in = i < n && inD((uint32_t)i) && uf_find(P, (uint32_t)i) == root;
+        const unsigned long long m = __ballot(in);
+        const int w0 = (base + (tid & ~63)) >> 5;
+        if (lane == 0 && w0 < nw) V[w0] = (uint32_t)m;
+        if (lane == 32 && w0 + 1 < nw) V[w0 + 1] = (uint32_t)(m >> 32);
     }
-    // Energy change of replica a: the edges leaving the cluster change sign.
+    __syncthreads();
+    // Energy change of replica a: the edges with one end in the cluster
+    // change sign (an edge from the cluster to D - cluster cannot exist).
     long long dEa = 0;
-    for (int w = tid; w < nw; w += nt) {
-        uint32_t c = V[w];
-        while (c) {
-            const int b = __ffs(c) - 1;
-            c &= c - 1;
-            const int i = w * 32 + b;
-            const int bi = (int)((A[w] >> b) & 1u);
-            const int e0 = a.g.row_ptr[i], e1 = a.g.row_ptr[i + 1], em = e0 + a.g.npos[i];
-            for (int e = e0; e < e1; ++e) {
-                const int j = a.g.col[e];
-                if (V[j >> 5] & (1u << (j & 31))) continue;
-                const int bj = (int)((A[j >> 5] >> (j & 31)) & 1u);
-                const int neg = e >= em;
+    for (int e0 = tid; e0 < ne; e0 += 8 * nt) {
+        uint32_t ev[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int idx = e0 + u * nt;
+            ev[u] = idx < ne ? edges[idx] : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const uint32_t i = ev[u] & 0x7FFFu, j = (ev[u] >> 15) & 0x7FFFu;
+            const uint32_t vi = (V[i >> 5] >> (i & 31)) & 1u, vj = (V[j >> 5] >> (j & 31)) & 1u;
+            if (e0 + u * nt < ne && vi != vj) {
+                const int bi = (int)((A[i >> 5] >> (i & 31)) & 1u), bj = (int)((A[j >> 5] >> (j & 31)) & 1u);
+                const int neg = (int)((ev[u] >> 30) & 1u);
                 dEa += -2 * (1 - 2 * (bi ^ bj ^ neg));
             }
         }
     }
     dEa = block_sum_ll(dEa, red_l);
-    // Flip the cluster in both replicas (other workgroups own other bits of
-    // the same words, hence the atomics).
-    unsigned long long *Xw = reinterpret_cast<unsigned long long *>(a.X);
-    for (int w = tid; w < nw; w += nt) {
-        uint32_t c = V[w];
-        while (c) {
-            const int b = __ffs(c) - 1;
-            c &= c - 1;
-            const int i = w * 32 + b;
-            atomicXor(&Xw[(size_t)(ra >> 6) * n + i], 1ull << ba);
-            atomicXor(&Xw[(size_t)(rb >> 6) * n + i], 1ull << bb);
-        }
-    }
+    for (int w = tid; w < nw; w += nt) Vout[w] = V[w];
     if (tid == 0) {
         a.E[ra] += (int)dEa;
         a.E[rb] -= (int)dEa;
     }
-    (void)seed_s;
+}
+
+// Flip every pair's cluster in both of its replicas: wave (word w, group g)
+// gathers the 64 replicas' bits of nodes 32w..32w+31 with ballots.
+__global__ __launch_bounds__(256) void icm_apply_kernel(IcmArgs a)
+{
+    const int lane = threadIdx.x & 63;
+    const int w = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int g = blockIdx.y;
+    if (w >= a.nw32) return;
+    const int q = g * 64 + lane, half = a.R / 2;
+    const int pr = q < a.R ? (q < half ? q : q - half) : -1;
+    const uint32_t v = pr >= 0 ? a.vout[(size_t)pr * a.nw32 + w] : 0u;
+    uint64_t out = 0;
+#pragma unroll
+    for (int b = 0; b < 32; ++b) {
+        const unsigned long long m = __ballot((v >> b) & 1u);
+        if (lane == b) out = m;
+    }
+    const int i = w * 32 + lane;
+    if (lane < 32 && i < a.g.n && out) a.X[(size_t)g * a.g.n + i] ^= out;
 }
 
 __global__ void fill_u64_kernel(unsigned long long *p, unsigned long long v, long long count)
@@ -1397,9 +1466,18 @@ int launch_gather(const GatherArgs &a, void *stream)
 
 int launch_icm(const IcmArgs &a, void *stream)
 {
-    const int lds = 5 * a.nw32 * 4;
-    hipLaunchKernelGGL(icm_kernel, dim3(a.R / 2), dim3(256), lds, (hipStream_t)stream, a);
-    return check("icm_kernel");
+    const int lds = icm_lds_bytes(a.g.n, a.nw32);
+    static int configured = 0;
+    if (configured < lds) {
+        if (hipFuncSetAttribute(reinterpret_cast<const void *>(&icm_kernel),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess)
+            return check("hipFuncSetAttribute(icm)");
+        configured = lds;
+    }
+    hipLaunchKernelGGL(icm_kernel, dim3(a.R / 2), dim3(kIcmThreads), lds, (hipStream_t)stream, a);
+    if (int st = check("icm_kernel")) return st;
+    hipLaunchKernelGGL(icm_apply_kernel, dim3((a.nw32 + 3) / 4, a.G), dim3(256), 0, (hipStream_t)stream, a);
+    return check("icm_apply_kernel");
 }
 
 }  // namespace pa

@@ -759,6 +759,9 @@ extern "C" pa_status pa_run(pa_solver *s, const pa_schedule *sch, int32_t R, uin
     sa.snap = reinterpret_cast<uint32_t *>(ws + L.snap);
     sa.counters = U64(L.counters);
     sa.nw32 = P.nw32;
+    sa.Xin = nullptr;
+    sa.Ein = nullptr;
+    sa.parent = nullptr;
 
     if (s->timing) {
         const size_t need = 2 * (size_t)P.K;
@@ -772,11 +775,23 @@ extern "C" pa_status pa_run(pa_solver *s, const pa_schedule *sch, int32_t R, uin
 
     for (int k = 0; k < P.K; ++k) {
         sa.k = k;
-        sa.X = reinterpret_cast<uint64_t *>(ws + Xc);
-        sa.E = reinterpret_cast<int *>(ws + Ec);
         if (s->timing) HIP_TRY(hipEventRecord(s->ev[2 * k], hs));
-        if (P.kind == 1) LAUNCH_TRY(pa::launch_sweep_bytes(P.W, P.sgn, P.threads, P.nblk, sa, hs));
-        else LAUNCH_TRY(pa::launch_sweep(P.W, P.sgn, P.threads, P.nblk, sa, hs));
+        if (P.kind == 1) {
+            // Kernel 1 reads the previous population through the resampling
+            // parents and writes the other buffer (no separate gather).
+            sa.Xin = reinterpret_cast<const uint64_t *>(ws + Xc);
+            sa.Ein = reinterpret_cast<const int *>(ws + Ec);
+            sa.X = reinterpret_cast<uint64_t *>(ws + Xn);
+            sa.E = reinterpret_cast<int *>(ws + En);
+            sa.parent = k > 0 ? reinterpret_cast<const int *>(ws + L.parent) : nullptr;
+            LAUNCH_TRY(pa::launch_sweep_bytes(P.W, P.sgn, P.threads, P.nblk, sa, hs));
+            std::swap(Xc, Xn);
+            std::swap(Ec, En);
+        } else {
+            sa.X = reinterpret_cast<uint64_t *>(ws + Xc);
+            sa.E = reinterpret_cast<int *>(ws + Ec);
+            LAUNCH_TRY(pa::launch_sweep(P.W, P.sgn, P.threads, P.nblk, sa, hs));
+        }
         if (s->timing) {
             HIP_TRY(hipEventRecord(s->ev[2 * k + 1], hs));
             s->ev_used = k + 1;
@@ -812,7 +827,7 @@ extern "C" pa_status pa_run(pa_solver *s, const pa_schedule *sch, int32_t R, uin
             e.do_rest = 1;
         }
         LAUNCH_TRY(pa::launch_epilogue(e, hs));
-        if (k + 1 < P.K) {
+        if (P.kind == 2 && k + 1 < P.K) {
             pa::GatherArgs ga;
             ga.n = n;
             ga.R = R;

@@ -52,8 +52,11 @@ struct SweepArgs {
     const uint64_t *thr;        // kernel 2: [K][lmax1][dmax+1] T[m] (T[0] unused)
     const uint32_t *thr32;      // kernel 1: [K][lmax1][dmax+1] T[1..dmax], all-accept flag
     const int *as_state;        // [0] level
-    uint64_t *X;                // [G][n]
+    uint64_t *X;                // [G][n] population written by the sweep (kernel 2: in place)
     int *E;                     // [Rp]
+    const uint64_t *Xin;        // kernel 1: population before resampling, read through parent
+    const int *Ein;             // kernel 1: its energies
+    const int *parent;          // kernel 1: [R] resampling parent of each slot, null = identity
     const int *best_E;          // global best so far
     unsigned long long *cand;   // [nblk] (E+2^31)<<32 | s<<15 | r, or ~0
     uint32_t *snap;             // [nblk][nw32]

@@ -614,20 +614,50 @@ __global__ __launch_bounds__(1024) void sweep_bytes_kernel(SweepArgs a, const in
     const uint32_t comp = (uint32_t)n * W;                        // complemented records
     const uint32_t zrec = RB + (uint32_t)(SIGNED ? 2 * n : n) * W;  // zero record
 
-    uint64_t *Xg = a.X + (size_t)grp * n;
+    uint64_t *Xg = a.X + (size_t)grp * n;            // output words of this block's group
+    // The block's replica slots take the spins of their resampling parents
+    // (identity before the first resampling). Systematic resampling hands
+    // out slots in parent order, so the parents of a block normally sit in
+    // one or two 64-replica words: those are read once per node.
+    const bool ident = a.parent == nullptr;
+    int pr[W];
+    int gA = 1 << 30, gB = -1;
+#pragma unroll
+    for (int b = 0; b < W; ++b) {
+        const int r = r0 + b < a.R ? r0 + b : r0;
+        pr[b] = ident ? r : a.parent[r];
+        gA = (pr[b] >> 6) < gA ? (pr[b] >> 6) : gA;
+        gB = (pr[b] >> 6) > gB ? (pr[b] >> 6) : gB;
+    }
+    const bool two = gB - gA <= 1;
+    const uint64_t *XA = a.Xin + (size_t)gA * n, *XB = a.Xin + (size_t)gB * n;
     // Expand the block's spin bits into byte records, 4 loads in flight per lane.
     for (int base = 0; base < n; base += 4 * nt) {
-        uint64_t vv[4];
+        uint64_t va[4], vb[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const int i = base + u * nt + tid;
-            vv[u] = i < n ? Xg[i] : 0ull;
+            va[u] = i < n ? XA[i] : 0ull;
+            vb[u] = i < n && !ident && two ? XB[i] : 0ull;
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const int i = base + u * nt + tid;
             if (i >= n) break;
-            const uint64_t v = field_of<W>(vv[u], sub);
+            uint64_t v = 0;
+            if (ident) {
+                v = field_of<W>(va[u], sub);
+            } else if (two) {
+#pragma unroll
+                for (int b = 0; b < W; ++b) {
+                    const uint64_t w = (pr[b] >> 6) == gA ? va[u] : vb[u];
+                    v |= ((w >> (pr[b] & 63)) & 1ull) << b;
+                }
+            } else {
+#pragma unroll
+                for (int b = 0; b < W; ++b)
+                    v |= ((a.Xin[(size_t)(pr[b] >> 6) * n + i] >> (pr[b] & 63)) & 1ull) << b;
+            }
             Rec<NR> rc;
 #pragma unroll
             for (int q = 0; q < NR; ++q) rc.v[q] = spread4((uint32_t)(v >> (4 * q)));
@@ -646,7 +676,7 @@ __global__ __launch_bounds__(1024) void sweep_bytes_kernel(SweepArgs a, const in
     // Accept-all row (exp(-beta * 2m) rounds to 1 for every uphill move).
     const uint32_t allm = trow[a.dmax] ? 0x01010101u : 0u;
     if (tid < W) {
-        Eblk[tid] = (r0 + tid < a.R) ? a.E[r0 + tid] : 0;
+        Eblk[tid] = (r0 + tid < a.R) ? a.Ein[ident ? r0 + tid : a.parent[r0 + tid]] : 0;
         Ed[tid] = 0;
     }
     if (tid == 0) {

@@ -170,6 +170,17 @@ extern "C" pa_status pa_create(pa_solver **out, int32_t n, const int32_t *row_pt
         for (auto &jw : rows[i])
             if (jw.first > i)
                 s->edges.push_back((uint32_t)i | ((uint32_t)jw.first << 15) | (jw.second < 0 ? 1u << 30 : 0u));
+    {
+        // Fixed pseudo-random order (xorshift64 Fisher-Yates): concurrent
+        // unions in the cluster move then rarely meet the same root.
+        uint64_t z = 0x9E3779B97F4A7C15ull;
+        for (size_t q = s->edges.size(); q > 1; --q) {
+            z ^= z << 13;
+            z ^= z >> 7;
+            z ^= z << 17;
+            std::swap(s->edges[q - 1], s->edges[z % q]);
+        }
+    }
     *out = s;
     return PA_OK;
 }
@@ -491,6 +502,22 @@ static pa_status build_plan(pa_solver *s, const pa_schedule *sch, int R, Plan &p
     p.nblk = (R + W - 1) / W;
 
     build_levels(s, sch->order, p);
+    if (p.kind == 1 && sch->wg_threads == 0 && p.threads == 512) {
+        // Measured on MI355X: when the dependency levels are small, fewer
+        // waves per workgroup wait less at the level barriers. Take the
+        // smallest multiple of 64 in [256, 512] whose number of rounds stays
+        // within 15% of the number of levels (the rounds a sweep cannot go
+        // below), else 512.
+        for (int T = 256; T < 512; T += 64) {
+            long long rounds = 0;
+            for (int l = 0; l < p.n_levels; ++l)
+                rounds += (p.level_off[l + 1] - p.level_off[l] + T - 1) / T;
+            if (rounds * 100 <= (long long)p.n_levels * 115) {
+                p.threads = T;
+                break;
+            }
+        }
+    }
     build_blocks(s, p);
 
     // Weight-table sizes (needed for the workspace size even without tables).

@@ -974,49 +974,88 @@ __device__ __forceinline__ uint64_t sys_f(uint64_t c, uint64_t R, uint64_t u, ui
 
 __global__ __launch_bounds__(1024) void epilogue_kernel(EpiArgs a)
 {
-    __shared__ unsigned long long red_u[16];
-    __shared__ long long red_l[16];
-    __shared__ unsigned long long scan[kMaxThreads];
-    __shared__ int sbest[5];
-    __shared__ int simp;
-    const int tid = threadIdx.x;
-    const int nt = blockDim.x;
-    if (tid < 5) sbest[tid] = a.best[tid];
-    if (tid == 0) simp = a.as_state[2];
-    __syncthreads();
-
-    if (a.do_cand) {
-        unsigned long long key = ~0ull;
-        for (int b = tid; b < a.nblk; b += nt) key = a.cand[b] < key ? a.cand[b] : key;
-        key = block_min_u64(key, red_u);
-        if (key != ~0ull) {
-            const int E = (int)((uint32_t)(key >> 32) ^ 0x80000000u);
-            if (!sbest[4] || E < sbest[0]) {
-                const int s = (int)((key >> 15) & 0xFFFFull);
-                const int r = (int)(key & 0x7FFFull);
-                const uint32_t *src = a.snap + (size_t)(r / a.W) * a.nw32;
-                for (int w = tid; w < a.nw32; w += nt) a.best_x[w] = src[w];
-                __syncthreads();
-                if (tid == 0) {
-                    sbest[0] = E; sbest[1] = a.k; sbest[2] = s; sbest[3] = r; sbest[4] = 1;
-                    simp = 1;
-                }
-            }
-        }
-        __syncthreads();
+    extern __shared__ int Esh[];       // [R] energies (when the population is read)
+    __shared__ unsigned long long w_cand[16], w_key[16], w_scan[16];
+    __shared__ long long w_sum[16];
+    __shared__ long long par_total;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int nt = blockDim.x, nwv = nt >> 6;
+    const int R = a.R;
+    // Thread tid owns the contiguous replicas [lo, hi) (the scan order).
+    const int per = (R + nt - 1) / nt;
+    const int lo = tid * per < R ? tid * per : R;
+    const int hi = lo + per < R ? lo + per : R;
+    const bool need_e = a.do_pop || a.do_rest;
+    // Best so far (uniform; thread 0 keeps the full record) and the improved flag.
+    int bE = a.best[0], bvalid = a.best[4];
+    int brec[5] = {0, 0, 0, 0, 0};
+    if (tid == 0)
+        for (int q = 0; q < 5; ++q) brec[q] = a.best[q];
+    int simp = a.as_state[2];
+    // Loads needed after the reductions, issued now.
+    const bool resample = a.do_rest && a.k < a.K - 1;
+    const int off = resample ? a.wtab_off[a.k] : 0, len = resample ? a.wtab_len[a.k] : 0;
+    int level_used = 0, stall0 = 0;
+    unsigned long long att = 0, acc = 0;
+    if (tid == 0 && a.do_rest) {
+        level_used = a.as_state[0];
+        stall0 = a.as_state[1];
+        att = a.counters[0];
+        acc = a.counters[1];
+        par_total = 0;
     }
 
-    if (a.do_pop) {
-        unsigned long long key = ~0ull;
-        for (int r = tid; r < a.R; r += nt) {
-            const unsigned long long kk =
-                ((unsigned long long)((uint32_t)a.E[r] ^ 0x80000000u) << 32) | (unsigned)r;
-            key = kk < key ? kk : key;
+    // One reduction for the block candidates, the population minimum
+    // (energy, then lowest replica) and the energy sum.
+    unsigned long long kc = ~0ull, ke = ~0ull;
+    long long es = 0;
+    if (a.do_cand)
+        for (int b = tid; b < a.nblk; b += nt) kc = a.cand[b] < kc ? a.cand[b] : kc;
+    if (need_e)
+        for (int r = tid; r < R; r += nt) {
+            const int v = a.E[r];
+            Esh[r] = v;
+            const unsigned long long kk = ((unsigned long long)((uint32_t)v ^ 0x80000000u) << 32) | (unsigned)r;
+            ke = kk < ke ? kk : ke;
+            es += v;
         }
-        key = block_min_u64(key, red_u);
-        const int E = (int)((uint32_t)(key >> 32) ^ 0x80000000u);
-        const int r = (int)(key & 0xFFFFFFFFull);
-        if (!sbest[4] || E < sbest[0]) {
+    kc = wave_min_u64(kc);
+    ke = wave_min_u64(ke);
+    es = wave_sum_ll(es);
+    if (lane == 0) {
+        w_cand[wv] = kc;
+        w_key[wv] = ke;
+        w_sum[wv] = es;
+    }
+    __syncthreads();
+    kc = ~0ull;
+    ke = ~0ull;
+    es = 0;
+    for (int v = 0; v < nwv; ++v) {
+        kc = w_cand[v] < kc ? w_cand[v] : kc;
+        ke = w_key[v] < ke ? w_key[v] : ke;
+        es += w_sum[v];
+    }
+
+    if (a.do_cand && kc != ~0ull) {
+        const int E = (int)((uint32_t)(kc >> 32) ^ 0x80000000u);
+        if (!bvalid || E < bE) {
+            const int sw = (int)((kc >> 15) & 0xFFFFull);
+            const int r = (int)(kc & 0x7FFFull);
+            const uint32_t *src = a.snap + (size_t)(r / a.W) * a.nw32;
+            for (int w = tid; w < a.nw32; w += nt) a.best_x[w] = src[w];
+            if (tid == 0) {
+                brec[0] = E; brec[1] = a.k; brec[2] = sw; brec[3] = r; brec[4] = 1;
+            }
+            bE = E;
+            bvalid = 1;
+            simp = 1;
+        }
+    }
+    if (a.do_pop) {
+        const int E = (int)((uint32_t)(ke >> 32) ^ 0x80000000u);
+        const int r = (int)(ke & 0xFFFFFFFFull);
+        if (!bvalid || E < bE) {
             const uint64_t *Xr = a.X + (size_t)(r >> 6) * a.n;
             const int b = r & 63;
             for (int w = tid; w < a.nw32; w += nt) {
@@ -1025,34 +1064,20 @@ __global__ __launch_bounds__(1024) void epilogue_kernel(EpiArgs a)
                     bits |= (uint32_t)((Xr[w * 32 + q] >> b) & 1ull) << q;
                 a.best_x[w] = bits;
             }
-            __syncthreads();
             if (tid == 0) {
-                sbest[0] = E; sbest[1] = a.pop_step; sbest[2] = a.pop_sweep; sbest[3] = r; sbest[4] = 1;
-                if (a.pop_step >= 0) simp = 1;
+                brec[0] = E; brec[1] = a.pop_step; brec[2] = a.pop_sweep; brec[3] = r; brec[4] = 1;
             }
+            bE = E;
+            bvalid = 1;
+            if (a.pop_step >= 0) simp = 1;
         }
-        __syncthreads();
     }
 
     if (a.do_rest) {
-        long long emin_l = 0x7FFFFFFFLL, esum = 0;
-        {
-            unsigned long long key = ~0ull;
-            for (int r = tid; r < a.R; r += nt) {
-                const unsigned long long kk = (unsigned long long)((uint32_t)a.E[r] ^ 0x80000000u);
-                key = kk < key ? kk : key;
-                esum += a.E[r];
-            }
-            key = block_min_u64(key, red_u);
-            emin_l = (long long)(int)((uint32_t)key ^ 0x80000000u);
-            esum = block_sum_ll(esum, red_l);
-        }
-        const int emin = (int)emin_l;
+        const int emin = (int)((uint32_t)(ke >> 32) ^ 0x80000000u);
         long long *st = a.stats + (size_t)a.k * kStatFields;
         if (tid == 0) {
-            const int level_used = a.as_state[0];
-            const unsigned long long att = a.counters[0], acc = a.counters[1];
-            int level = level_used, stall = a.as_state[1];
+            int level = level_used, stall = stall0;
             if (a.as_enable) {
                 if (simp) {
                     level = 0;
@@ -1068,35 +1093,35 @@ __global__ __launch_bounds__(1024) void epilogue_kernel(EpiArgs a)
             }
             a.as_state[0] = level;
             a.as_state[1] = stall;
-            a.as_state[2] = 0;
             a.counters[0] = 0;
             a.counters[1] = 0;
-            st[0] = emin; st[1] = esum; st[2] = (long long)att; st[3] = (long long)acc;
-            st[4] = level_used; st[5] = sbest[0];
+            st[0] = emin; st[1] = es; st[2] = (long long)att; st[3] = (long long)acc;
+            st[4] = level_used; st[5] = bE;
             st[6] = 0; st[7] = 0;
         }
-        if (a.k < a.K - 1) {
-            const int R = a.R;
-            const int per = (R + nt - 1) / nt;
-            const int lo = tid * per < R ? tid * per : R;
-            const int hi = lo + per < R ? lo + per : R;
-            const int off = a.wtab_off[a.k], len = a.wtab_len[a.k];
+        if (resample) {
             uint64_t ws = 0;
+#pragma unroll 4
             for (int r = lo; r < hi; ++r) {
-                const int nn = a.E[r] - emin;
+                const int nn = Esh[r] - emin;
                 ws += nn < len ? a.wtab[off + nn] : 0ull;
             }
-            scan[tid] = ws;
-            __syncthreads();
-            // Hillis-Steele inclusive scan over the per-thread sums.
-            for (int o = 1; o < nt; o <<= 1) {
-                const uint64_t v = tid >= o ? scan[tid - o] : 0ull;
-                __syncthreads();
-                scan[tid] += v;
-                __syncthreads();
+            // Exclusive scan of the per-thread sums: wave scan, then the wave totals.
+            uint64_t inc = ws;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const uint64_t t = __shfl_up(inc, o, 64);
+                if (lane >= o) inc += t;
             }
-            const uint64_t S = scan[nt - 1];
-            const uint64_t excl = scan[tid] - ws;
+            if (lane == 63) w_scan[wv] = inc;
+            __syncthreads();
+            uint64_t before = 0, S = 0;
+            for (int v = 0; v < nwv; ++v) {
+                const uint64_t x = w_scan[v];
+                before += v < wv ? x : 0ull;
+                S += x;
+            }
+            const uint64_t excl = before + inc - ws;
             const U4 o = philox10(U4{0u, 2u << 16, (uint32_t)a.k, a.inst << 16}, a.seed_lo, a.seed_hi);
             const uint64_t U = (uint64_t)o.x | ((uint64_t)o.y << 32);
             const uint64_t u = __umul64hi(U, S);
@@ -1104,7 +1129,7 @@ __global__ __launch_bounds__(1024) void epilogue_kernel(EpiArgs a)
             uint64_t fprev = sys_f(C, (uint64_t)R, u, S);
             long long parents = 0;
             for (int r = lo; r < hi; ++r) {
-                const int nn = a.E[r] - emin;
+                const int nn = Esh[r] - emin;
                 C += nn < len ? a.wtab[off + nn] : 0ull;
                 const uint64_t f = sys_f(C, (uint64_t)R, u, S);
                 for (uint64_t q = fprev; q < f; ++q) a.parent[q] = r;
@@ -1112,16 +1137,19 @@ __global__ __launch_bounds__(1024) void epilogue_kernel(EpiArgs a)
                 parents += f > fprev;
                 fprev = f;
             }
-            parents = block_sum_ll(parents, red_l);
+            parents = wave_sum_ll(parents);
+            if (lane == 0 && parents) atomicAdd((unsigned long long *)&par_total, (unsigned long long)parents);
+            __syncthreads();
             if (tid == 0) {
-                st[6] = parents;
+                st[6] = par_total;
                 st[7] = (long long)S;
             }
         }
     }
-    __syncthreads();
-    if (tid < 5) a.best[tid] = sbest[tid];
-    if (tid == 0) a.as_state[2] = a.do_rest ? 0 : simp;
+    if (tid == 0) {
+        for (int q = 0; q < 5; ++q) a.best[q] = brec[q];
+        a.as_state[2] = a.do_rest ? 0 : simp;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1177,7 +1205,15 @@ __global__ __launch_bounds__(256) void gather_kernel(GatherArgs a)
 // Root of x with path halving. Roots are only ever hooked under smaller
 // roots and halving links x to an ancestor, so P[x] <= x always holds and
 // every step strictly decreases x: the walk ends within n steps.
-__device__ __forceinline__ uint32_t uf_find(volatile uint32_t *P, uint32_t x)
+typedef volatile __attribute__((address_space(3))) uint32_t lds_vu32;
+
+// LDS compare-and-swap on an LDS-typed pointer (a generic pointer would become a FLAT atomic).
+__device__ __forceinline__ bool lds_cas(lds_vu32 *p, uint32_t expected, uint32_t desired)
+{
+    return __atomic_compare_exchange_n(p, &expected, desired, false, __ATOMIC_RELAXED, __ATOMIC_RELAXED);
+}
+
+__device__ __forceinline__ uint32_t uf_find(lds_vu32 *P, uint32_t x)
 {
     for (;;) {
         const uint32_t px = P[x];
@@ -1190,7 +1226,7 @@ __device__ __forceinline__ uint32_t uf_find(volatile uint32_t *P, uint32_t x)
 
 // Merge the sets of x and y (lock-free: a failed hook means another lane
 // hooked that root, which happens at most once per root).
-__device__ __forceinline__ void uf_unite(volatile uint32_t *P, uint32_t x, uint32_t y)
+__device__ __forceinline__ void uf_unite(lds_vu32 *P, uint32_t x, uint32_t y)
 {
     for (;;) {
         x = uf_find(P, x);
@@ -1201,7 +1237,7 @@ __device__ __forceinline__ void uf_unite(volatile uint32_t *P, uint32_t x, uint3
             x = y;
             y = t;
         }
-        if (atomicCAS(const_cast<uint32_t *>(&P[y]), y, x) == y) return;
+        if (lds_cas(&P[y], y, x)) return;
     }
 }
 
@@ -1222,7 +1258,7 @@ __global__ __launch_bounds__(kIcmThreads) void icm_kernel(IcmArgs a)
     __shared__ uint32_t root_s;
     const int tid = threadIdx.x, lane = tid & 63, nt = blockDim.x;
     const int n = a.g.n, nw = a.nw32;
-    volatile uint32_t *P = lds;
+    lds_vu32 *P = (lds_vu32 *)lds;
     uint32_t *A = lds + n, *D = A + nw, *V = D + nw;
     const int p = blockIdx.x, half = a.R / 2;
     const int ra = p, rb = p + half;
@@ -1261,7 +1297,8 @@ __global__ __launch_bounds__(kIcmThreads) void icm_kernel(IcmArgs a)
         return;
     }
     auto inD = [&](uint32_t i) { return (D[i >> 5] >> (i & 31)) & 1u; };
-    // Components of the subgraph induced by D.
+    // Components of the subgraph induced by D (the edge list is in shuffled
+    // order, so that the lanes of a wave seldom contend for one root).
     const uint32_t *edges = a.g.edges;
     const int ne = a.g.ne;
     for (int e0 = tid; e0 < ne; e0 += 8 * nt) {
@@ -1482,7 +1519,15 @@ int launch_sweep_bytes(int W, int sgn, int threads, int nblk, const SweepArgs &a
 
 int launch_epilogue(const EpiArgs &a, void *stream)
 {
-    hipLaunchKernelGGL(epilogue_kernel, dim3(1), dim3(kMaxThreads), 0, (hipStream_t)stream, a);
+    const int lds = a.R * 4;
+    static int configured = 0;
+    if (configured < lds) {
+        if (hipFuncSetAttribute(reinterpret_cast<const void *>(&epilogue_kernel),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess)
+            return check("hipFuncSetAttribute(epilogue)");
+        configured = lds;
+    }
+    hipLaunchKernelGGL(epilogue_kernel, dim3(1), dim3(kMaxThreads), lds, (hipStream_t)stream, a);
     return check("epilogue_kernel");
 }
 

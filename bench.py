@@ -82,7 +82,7 @@ def main():
                     help="0 automatic, 1 node-per-lane byte records, 2 replica-per-lane bit words")
     ap.add_argument("--tile", type=int, default=0, help="replicas per workgroup (0 automatic)")
     ap.add_argument("--threads", type=int, default=0, help="threads per sweep workgroup (0 automatic)")
-    ap.add_argument("--cpu-sample-steps", type=int, default=12)
+    ap.add_argument("--cpu-sample-steps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain int32 elementwise kernel of known size "

@@ -231,14 +231,18 @@ __device__ __forceinline__ uint64_t field_of(uint64_t v, int sub)
 
 constexpr int kRegCols = 28;   // neighbour entries held in registers (128-byte block head)
 
-// Philox4x32-10 written with 64-bit products (one v_mad_u64_u32 per product).
+// Philox4x32-10 written with 64-bit products (one v_mad_u64_u32 gives hi and
+// lo at once) and the two XORs of each output word as one 3-input bit
+// operation (0x96 = a ^ b ^ c).
 __device__ __forceinline__ U4 philox10_wide(U4 c, uint32_t k0, uint32_t k1)
 {
 #pragma unroll
     for (int round = 0; round < 10; ++round) {
         const uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c.x;
         const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c.z;
-        c = U4{(uint32_t)(p1 >> 32) ^ c.y ^ k0, (uint32_t)p1, (uint32_t)(p0 >> 32) ^ c.w ^ k1,
+        c = U4{(uint32_t)__builtin_amdgcn_bitop3_b32((uint32_t)(p1 >> 32), c.y, k0, 0x96),
+               (uint32_t)p1,
+               (uint32_t)__builtin_amdgcn_bitop3_b32((uint32_t)(p0 >> 32), c.w, k1, 0x96),
                (uint32_t)p0};
         k0 += 0x9E3779B9u;
         k1 += 0xBB67AE85u;
@@ -527,6 +531,13 @@ typedef __attribute__((address_space(3))) u32x4 lds_u4;
 __device__ __forceinline__ uint32_t spread4(uint32_t v)
 {
     return ((v & 0xFu) * 0x00204081u) & 0x01010101u;
+}
+
+// 0xFF in every byte that holds 1 (bytes hold 0 or 1): v_perm_b32 selector
+// 12 yields 0x00 and 13 yields 0xFF (a multiply by 0xFF would be quarter rate).
+__device__ __forceinline__ uint32_t byte_mask(uint32_t v)
+{
+    return __builtin_amdgcn_perm(0u, 0u, v + 0x0C0C0C0Cu);
 }
 
 // Gather bit 0 of 4 bytes into 4 bits (byte b -> bit b).
@@ -840,21 +851,22 @@ __global__ __launch_bounds__(1024) void sweep_bytes_kernel(SweepArgs a, const in
 #pragma unroll
                 for (int q = 0; q < NR; ++q) {
                     // u = x ? c : d - c  (edges with w_ij x_i x_j = +1), per byte
-                    const uint32_t msk = (X.v[q] << 8) - X.v[q];
+                    const uint32_t msk = byte_mask(X.v[q]);
                     const uint32_t U = (C[q] & msk) | ((Dm - C[q]) & ~msk);
                     // w = 0x80 + (m - 1) per byte with m = d - 2u
                     const uint32_t w = (0x7F7F7F7Fu + Dm) - 2u * U;
+                    const uint32_t idx = w & 0x7F7F7F7Fu;           // T[m] sits at LDS word m - 1
                     uint32_t A = ((~w >> 7) & 0x01010101u) | allm;   // m <= 0 always accepts
 #pragma unroll
                     for (int b = 0; b < 4; ++b) {
-                        const uint32_t th = T[(w >> (8 * b)) & 0x7Fu];
+                        const uint32_t th = *(lds_u32 *)(uintptr_t)(((idx >> (8 * b)) & 0xFFu) << 2);
                         A |= (dr[q][b] < th ? 1u : 0u) << (8 * b);
                     }
                     Xn.v[q] = X.v[q] ^ A;
                     const uint32_t up = w & real80[q];           // uphill markers
                     att += __builtin_popcount(up);
                     acc += __builtin_popcount(up & (A << 7));
-                    const uint32_t Am = (A << 8) - A;
+                    const uint32_t Am = byte_mask(A);
                     YA[q] += (Dm - U) & Am;                      // d - u of accepted flips
                     ZA[q] += U & Am;                             // u of accepted flips
                 }

@@ -72,12 +72,77 @@ def cpu_baseline(wl, sample_steps: int):
                       f"{dt:.1f} s on the host"}
 
 
+def batch_bench(args, count: int):
+    """Instances/s of a mix of uneven runs: one after another on one stream,
+    then as one batch over several streams (pa_run_batch)."""
+    import torch
+    from paper_2510_21105_amd import pa, workloads as W
+
+    wls = W.batch_workloads(count)
+    params = [pa.params_from_workload(w) for w in wls]
+    solvers = [pa.Solver(w["graph"]) for w in wls]
+    attempts = sum(p.R * w["graph"].n * p.sweeps * len(p.betas) for w, p in zip(wls, params))
+    streams = [torch.cuda.Stream() for _ in range(args.streams)]
+    print(f"[bench] {count} instances, {attempts:.3e} attempts per batch, {args.streams} streams",
+          file=sys.stderr, flush=True)
+    for w in range(args.warmup):
+        pa.run_batch(solvers, params, streams)
+        torch.cuda.synchronize()
+        print(f"[bench] warmup {w + 1}/{args.warmup} done", file=sys.stderr, flush=True)
+    seq, bat = [], []
+    for step in range(args.steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for s, p in zip(solvers, params):
+            s.run(p, stream=streams[0])
+        torch.cuda.synchronize()
+        seq.append(time.perf_counter() - t0)
+        cuts_seq = [s.best_cut() for s in solvers]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        pa.run_batch(solvers, params, streams)
+        torch.cuda.synchronize()
+        bat.append(time.perf_counter() - t0)
+        cuts_bat = [s.best_cut() for s in solvers]
+        if cuts_seq != cuts_bat:
+            raise RuntimeError("batched and sequential runs disagree")
+        print(f"[bench] timed batch {step + 1}/{args.steps}: sequential {seq[-1]:.2f} s, "
+              f"batched {bat[-1]:.2f} s", file=sys.stderr, flush=True)
+    t_seq, t_bat = sum(seq) / len(seq), sum(bat) / len(bat)
+    out = {
+        "metric": "instances/s",
+        "value": count / t_bat,
+        "unit": "instances/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": t_bat * 1000.0,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": f"batch{count}: {count} uneven instances (even: random "
+                               "G(N, N d/2), d ~ U[4,12]; odd: +-1 torus), N ~ U[800,7000], "
+                               "R ~ U[256,4096], K=500, plain population annealing",
+                   "instances": count, "streams": args.streams,
+                   "attempts_per_batch": attempts},
+        "sequential_instances_per_s": count / t_seq,
+        "speedup_vs_sequential": t_seq / t_bat,
+        "attempts_per_s": attempts / t_bat,
+        "best_cuts_first8": cuts_bat[:8],
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3, help="timed solves")
     ap.add_argument("--warmup", type=int, default=1, help="untimed solves")
-    ap.add_argument("--workload", default="g63like")
+    ap.add_argument("--workload", default="g63like",
+                    help="g63like, torus100, small800, or batchN (N uneven instances)")
+    ap.add_argument("--streams", type=int, default=8, help="streams for batchN (1..32)")
     ap.add_argument("--sweep-kernel", type=int, default=0,
                     help="0 automatic, 1 node-per-lane byte records, 2 replica-per-lane bit words")
     ap.add_argument("--tile", type=int, default=0, help="replicas per workgroup (0 automatic)")
@@ -92,6 +157,12 @@ def main():
         print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported",
               file=sys.stderr)
         sys.exit(2)
+
+    if args.workload.startswith("batch"):
+        # One hardware queue per stream (set before the HIP runtime starts).
+        args.streams = max(1, min(32, args.streams))
+        if int(os.environ.get("GPU_MAX_HW_QUEUES", "4")) < args.streams:
+            os.environ["GPU_MAX_HW_QUEUES"] = str(args.streams)
 
     import torch
     from paper_2510_21105_amd import pa, workloads as W
@@ -109,6 +180,9 @@ def main():
               f"{dst.numel() * 4} bytes written", file=sys.stderr, flush=True)
         del src, dst
 
+    if args.workload.startswith("batch"):
+        batch_bench(args, int(args.workload[5:] or 64))
+        return
     wl = W.workload(args.workload)
     g = wl["graph"]
     params = pa.params_from_workload(wl, sweep_kernel=args.sweep_kernel, tile_replicas=args.tile,

@@ -126,6 +126,32 @@ pa_status pa_workspace_bytes(const pa_solver *s, const pa_schedule *sch, int32_t
 pa_status pa_run(pa_solver *s, const pa_schedule *sch, int32_t R, uint64_t seed,
                  uint32_t instance, void *workspace, size_t workspace_bytes, void *stream);
 
+/* One run of a batch: the arguments of pa_run. */
+typedef struct {
+    pa_solver *solver;          /* distinct solver per run */
+    const pa_schedule *schedule;
+    int32_t R;
+    uint64_t seed;
+    uint32_t instance;
+    void *workspace;            /* as for pa_run: 256-byte aligned device memory */
+    size_t workspace_bytes;
+} pa_batch_run;
+
+/*
+ * Many independent runs sharing the device (for instance a mix of graphs and
+ * population sizes whose single runs leave compute units idle): run i is
+ * enqueued exactly as pa_run would on streams[i % n_streams], so runs on
+ * different streams overlap on the device while each keeps the results of
+ * the same run alone, bit for bit. Asynchronous like pa_run; the per-solver
+ * result calls synchronise the run's stream. Solvers must be distinct and
+ * each run needs its own workspace. Returns PA_OK, or the status of the
+ * first run that fails (its index is in pa_last_error); the runs before it
+ * stay enqueued and valid. PA_EINVAL for a null array, count < 1,
+ * n_streams < 1 or a solver used twice.
+ */
+pa_status pa_run_batch(const pa_batch_run *runs, int32_t count, void *const *streams,
+                       int32_t n_streams);
+
 /* Best cut found by the last run: cut = (W_tot - E) / 2 (eq. (1)) and its
  * Ising energy E. Synchronises the run's stream. PA_ESTATE before a run. */
 pa_status pa_best_cut(pa_solver *s, int64_t *cut, int32_t *energy);

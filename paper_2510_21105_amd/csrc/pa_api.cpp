@@ -896,6 +896,34 @@ extern "C" pa_status pa_best_info(pa_solver *s, int64_t out[4])
     return PA_OK;
 }
 
+extern "C" pa_status pa_run_batch(const pa_batch_run *runs, int32_t count, void *const *streams,
+                                  int32_t n_streams)
+{
+    g_error[0] = 0;
+    if (!runs || !streams || count < 1 || n_streams < 1)
+        return fail(PA_EINVAL, "pa_run_batch: null array, count < 1 or n_streams < 1");
+    std::vector<const pa_solver *> seen;
+    seen.reserve(count);
+    for (int i = 0; i < count; ++i) {
+        if (!runs[i].solver) return fail(PA_EINVAL, "pa_run_batch: run %d has no solver", i);
+        seen.push_back(runs[i].solver);
+    }
+    std::sort(seen.begin(), seen.end());
+    if (std::adjacent_find(seen.begin(), seen.end()) != seen.end())
+        return fail(PA_EINVAL, "pa_run_batch: a solver appears in two runs");
+    for (int i = 0; i < count; ++i) {
+        const pa_batch_run &r = runs[i];
+        const pa_status st = pa_run(r.solver, r.schedule, r.R, r.seed, r.instance, r.workspace,
+                                    r.workspace_bytes, streams[i % n_streams]);
+        if (st != PA_OK) {
+            char msg[sizeof g_error];
+            std::snprintf(msg, sizeof msg, "%s", g_error);
+            return fail(st, "pa_run_batch: run %d: %s", i, msg);
+        }
+    }
+    return PA_OK;
+}
+
 extern "C" pa_status pa_best_cut(pa_solver *s, int64_t *cut, int32_t *energy)
 {
     int64_t info[4];

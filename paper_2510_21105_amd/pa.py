@@ -24,7 +24,7 @@ _STATUS = {PA_EINVAL: "PA_EINVAL", PA_ERANGE: "PA_ERANGE", PA_EWORKSPACE: "PA_EW
            PA_EDEVICE: "PA_EDEVICE", PA_ESTATE: "PA_ESTATE"}
 
 EXPORTS = ("pa_last_error", "pa_create", "pa_destroy", "pa_graph_info", "pa_workspace_bytes",
-           "pa_run", "pa_best_cut", "pa_best_info", "pa_best_config", "pa_best_config_hex",
+           "pa_run", "pa_run_batch", "pa_best_cut", "pa_best_info", "pa_best_config", "pa_best_config_hex",
            "pa_get_population", "pa_get_initial_population", "pa_get_step_stats",
            "pa_get_counts", "pa_get_launch_info", "pa_set_timing", "pa_get_sweep_time")
 
@@ -54,6 +54,18 @@ class Schedule(ctypes.Structure):
     ]
 
 
+class BatchRun(ctypes.Structure):
+    _fields_ = [
+        ("solver", ctypes.c_void_p),
+        ("schedule", ctypes.POINTER(Schedule)),
+        ("R", ctypes.c_int32),
+        ("seed", ctypes.c_uint64),
+        ("instance", ctypes.c_uint32),
+        ("workspace", ctypes.c_void_p),
+        ("workspace_bytes", ctypes.c_size_t),
+    ]
+
+
 _lib = None
 
 
@@ -75,6 +87,7 @@ def lib():
             "pa_graph_info": [P, P],
             "pa_workspace_bytes": [P, ctypes.POINTER(Schedule), i32, ctypes.POINTER(ctypes.c_size_t)],
             "pa_run": [P, ctypes.POINTER(Schedule), i32, u64, u32, P, ctypes.c_size_t, P],
+            "pa_run_batch": [ctypes.POINTER(BatchRun), i32, ctypes.POINTER(P), i32],
             "pa_best_cut": [P, ctypes.POINTER(i64), ctypes.POINTER(i32)],
             "pa_best_info": [P, P],
             "pa_best_config": [P, P],
@@ -184,8 +197,8 @@ class Solver:
         _check(lib().pa_workspace_bytes(self._h, ctypes.byref(sch), p.R, ctypes.byref(b)))
         return int(b.value)
 
-    def run(self, p: RunParams, stream=None, workspace=None):
-        """Enqueue a run on ``stream`` (torch.cuda stream; current one by default)."""
+    def _prepare(self, p: RunParams, workspace=None):
+        """Schedule struct (with the arrays it points to) and an aligned workspace."""
         import torch
         sch, keep = self._schedule(p)
         need = self.workspace_bytes(p)
@@ -196,12 +209,21 @@ class Solver:
         base = workspace.data_ptr()
         aligned = (base + 255) // 256 * 256
         avail = workspace.numel() - (aligned - base)
+        return sch, keep, workspace, aligned, avail
+
+    def _started(self, p: RunParams, sch, keep, workspace):
+        self._keep = (keep, workspace, sch)
+        self._R = p.R
+        self._K = int(sch.n_steps)
+
+    def run(self, p: RunParams, stream=None, workspace=None):
+        """Enqueue a run on ``stream`` (torch.cuda stream; current one by default)."""
+        import torch
+        sch, keep, workspace, aligned, avail = self._prepare(p, workspace)
         st = torch.cuda.current_stream() if stream is None else stream
         _check(lib().pa_run(self._h, ctypes.byref(sch), p.R, p.seed, p.inst,
                             ctypes.c_void_p(aligned), avail, ctypes.c_void_p(st.cuda_stream)))
-        self._keep = (keep, workspace)
-        self._R = p.R
-        self._K = int(sch.n_steps)
+        self._started(p, sch, keep, workspace)
         return self
 
     # ---- results (each synchronises the run's stream) ----
@@ -262,6 +284,26 @@ class Solver:
         n = ctypes.c_int64()
         _check(lib().pa_get_sweep_time(self._h, ctypes.byref(ms), ctypes.byref(n)))
         return float(ms.value), int(n.value)
+
+
+def run_batch(solvers, params, streams):
+    """Enqueue independent runs (one per distinct solver) through pa_run_batch,
+    run i on ``streams[i % len(streams)]`` (torch.cuda streams)."""
+    if len(solvers) != len(params):
+        raise ValueError("one RunParams per solver")
+    runs = (BatchRun * len(solvers))()
+    held = []
+    for i, (s, p) in enumerate(zip(solvers, params)):
+        sch, keep, workspace, aligned, avail = s._prepare(p)
+        held.append((s, p, sch, keep, workspace))
+        runs[i] = BatchRun(s._h.value, ctypes.pointer(sch), p.R, p.seed, p.inst, aligned, avail)
+    hs = (ctypes.c_void_p * len(streams))(*[st.cuda_stream for st in streams])
+    st = lib().pa_run_batch(runs, len(solvers), hs, len(streams))
+    # Keep every workspace alive: runs before a failing one stay enqueued.
+    for s, p, sch, keep, workspace in held:
+        s._started(p, sch, keep, workspace)
+    _check(st)
+    return solvers
 
 
 def params_from_workload(wl: dict, **over) -> RunParams:

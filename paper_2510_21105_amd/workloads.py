@@ -218,3 +218,35 @@ def workload(name: str) -> dict:
                     desc="100x100 torus, +-1 weights seed 4, R=16384, K=1000 linear beta "
                          "0.1->4.0, S=5, checkerboard order")
     raise KeyError(name)
+
+
+def batch_workloads(count: int = 64, meta_seed: int = 5, steps: int = 500) -> list:
+    """A mix of uneven instances for batched runs, drawn from one SplitMix64
+    stream (meta_seed): instance j is a random graph G(N, round(N d / 2)) with
+    d ~ U[4, 12] for even j and an L x L torus with +-1 weights, L = round(sqrt N),
+    for odd j; N ~ U[800, 7000], R ~ U[256, 4096]; K = ``steps`` linear steps,
+    beta 0.1 -> 5.0 and 10 sweeps per step on random graphs (natural order),
+    0.1 -> 4.0 and 5 sweeps on tori (checkerboard order). Plain population
+    annealing (no noise levels, no cluster moves), run seed 42, instance id j.
+    """
+    u = splitmix64(meta_seed, 4 * count).astype(np.float64) / 2.0 ** 64
+    out = []
+    for j in range(count):
+        N = 800 + int(u[4 * j] * 6201)
+        R = 256 + int(u[4 * j + 1] * 3841)
+        gseed = 1000 + j
+        if j % 2 == 0:
+            d = 4.0 + 8.0 * u[4 * j + 2]
+            M = int(round(N * d / 2))
+            g = random_graph(N, M, gseed, f"batch{j}-G({N},{M})")
+            wl = dict(graph=g, betas=linear_betas(0.1, 5.0, steps), sweeps=10,
+                      order=natural_order(g.n))
+        else:
+            L = int(round(np.sqrt(N)))
+            g = torus(L, gseed, True, f"batch{j}-torus{L}")
+            wl = dict(graph=g, betas=linear_betas(0.1, 4.0, steps), sweeps=5,
+                      order=checkerboard_order(L))
+        out.append(dict(wl, R=R, seed=42, inst=j, as_enable=0, as_stall_steps=20, as_max_level=4,
+                        as_frozen_inv=256, as_gamma=0.8, nl_period=0,
+                        desc=f"{g.name}, R={R}"))
+    return out

@@ -198,3 +198,35 @@ def test_partially_saturated_threshold_row_needs_the_word_kernel():
     assert _bytes(s, pa.params_from_workload(wl)) > 0          # automatic choice: kernel 2
     # a fully saturated row (every uphill threshold 2^32) stays on kernel 1
     assert _bytes(s, pa.params_from_workload(dict(wl, betas=[0.0, 1e-20, 0.5]), sweep_kernel=1)) > 0
+
+
+def test_run_batch_rejects_bad_arguments_without_device_calls():
+    L = pa.lib()
+    s = pa.Solver(W.cycle(8))
+    p = pa.params_from_workload(dict(W.workload("small800"), graph=s.graph, order=None))
+    sch, keep = s._schedule(p)
+    runs = (pa.BatchRun * 2)()
+    runs[0] = pa.BatchRun(s._h.value, ctypes.pointer(sch), p.R, p.seed, 0, 4096, 1 << 20)
+    runs[1] = pa.BatchRun(s._h.value, ctypes.pointer(sch), p.R, p.seed, 1, 8192, 1 << 20)
+    streams = (ctypes.c_void_p * 1)(None)
+    assert L.pa_run_batch(None, 1, streams, 1) == pa.PA_EINVAL
+    assert L.pa_run_batch(runs, 0, streams, 1) == pa.PA_EINVAL
+    assert L.pa_run_batch(runs, 1, streams, 0) == pa.PA_EINVAL
+    assert L.pa_run_batch(runs, 2, streams, 1) == pa.PA_EINVAL          # same solver twice
+    assert "two runs" in L.pa_last_error().decode()
+    runs[0].workspace = 4096 + 8                                          # misaligned
+    assert L.pa_run_batch(runs, 1, streams, 1) == pa.PA_EWORKSPACE
+    assert "run 0" in L.pa_last_error().decode()
+
+
+def test_batch_instance_mix_is_deterministic_and_in_range():
+    a, b = W.batch_workloads(8), W.batch_workloads(8)
+    for x, y in zip(a, b):
+        assert x["graph"].n == y["graph"].n and x["R"] == y["R"]
+        assert np.array_equal(x["graph"].col, y["graph"].col)
+    for j, w in enumerate(a):
+        assert 256 <= w["R"] <= 4096 and w["inst"] == j and len(w["betas"]) == 500
+        if j % 2:
+            assert w["graph"].degrees().max() == 4 and w["sweeps"] == 5
+        else:
+            assert 800 <= w["graph"].n <= 7000 and w["sweeps"] == 10

@@ -274,3 +274,29 @@ def test_tiny_inverse_temperatures(pa):
     assert s.launch_info()["sweep_kernel"] == 1
     s, _ = _compare(pa, g, dict(wl, betas=[1e-20, 1e-17, 0.3]))
     assert s.launch_info()["sweep_kernel"] == 2
+
+
+def test_batched_runs_equal_solo_runs(pa):
+    """Runs enqueued together on two streams give exactly the results of
+    the same runs alone (uneven random graphs and tori, K = 12)."""
+    import torch
+    wls = W.batch_workloads(6, steps=12)
+    params = [pa.params_from_workload(w, R=min(w["R"], 700)) for w in wls]
+    solvers = [pa.Solver(w["graph"]) for w in wls]
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    pa.run_batch(solvers, params, streams)
+    for w, p, s in zip(wls, params, solvers):
+        solo = pa.Solver(w["graph"]).run(p)
+        _say(f"batch vs solo {w['desc']} cut {s.best_cut()}")
+        assert s.best_cut() == solo.best_cut()
+        assert s.best_info() == solo.best_info()
+        assert np.array_equal(s.best_config(), solo.best_config())
+        assert np.array_equal(s.step_stats(), solo.step_stats())
+        x1, E1 = s.population()
+        x2, E2 = solo.population()
+        assert np.array_equal(E1, E2) and np.array_equal(x1, x2)
+    # the first instance also matches the oracle
+    w, p = wls[0], params[0]
+    ref = O.run_workload(dict(w, R=p.R), want_counts=False)
+    assert solvers[0].best_cut() == ref.best_cut
+    assert np.array_equal(solvers[0].step_stats(), ref.stats)

@@ -159,6 +159,23 @@ def natural_order(n: int) -> np.ndarray:
     return np.arange(n, dtype=np.int32)
 
 
+def coloring_order(g: Graph) -> np.ndarray:
+    """Sweep order by colour classes of a first-fit greedy colouring in node
+    order (node i takes the smallest colour none of its smaller neighbours
+    has), nodes ascending within a class. Every class is an independent set,
+    so a sweep in this order has as many dependency levels as colours."""
+    n = g.n
+    color = np.full(n, -1, dtype=np.int64)
+    for i in range(n):
+        nb = g.col[g.row_ptr[i]:g.row_ptr[i + 1]]
+        used = set(int(c) for c in color[nb] if c >= 0)
+        c = 0
+        while c in used:
+            c += 1
+        color[i] = c
+    return np.lexsort((np.arange(n), color)).astype(np.int32)
+
+
 def checkerboard_order(L: int) -> np.ndarray:
     """Sites with (r + c) even in row-major order, then the odd sites."""
     r, c = np.divmod(np.arange(L * L), L)
@@ -181,6 +198,7 @@ def workload(name: str) -> dict:
     * ``g63like``: random G(7000, 41459) seed 3 (the G63 shape), R=4096,
       2000 steps 0.1 -> 5.0, 10 sweeps/step, natural order, adaptive
       stochasticity and non-local moves on.
+    * ``g63color``: ``g63like`` swept in greedy-colouring order.
     * ``torus100``: 100 x 100 torus with +-1 weights, seed 4, R=16384,
       1000 steps 0.1 -> 4.0, 5 sweeps/step, checkerboard order.
 
@@ -210,6 +228,13 @@ def workload(name: str) -> dict:
                     as_enable=1, nl_period=10,
                     desc="random G(N=7000, M=41459) seed 3 (G63 shape), R=4096, K=2000 linear "
                          "beta 0.1->5.0, S=10, natural order, adaptive stochasticity + "
+                         "cluster moves every 10 steps")
+    if name == "g63color":
+        wl = workload("g63like")
+        g = wl["graph"]
+        return dict(wl, order=coloring_order(g),
+                    desc="random G(N=7000, M=41459) seed 3 (G63 shape), R=4096, K=2000 linear "
+                         "beta 0.1->5.0, S=10, greedy-colouring order, adaptive stochasticity + "
                          "cluster moves every 10 steps")
     if name == "torus100":
         g = torus(100, 4, True, "torus100")

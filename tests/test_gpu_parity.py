@@ -300,3 +300,14 @@ def test_batched_runs_equal_solo_runs(pa):
     ref = O.run_workload(dict(w, R=p.R), want_counts=False)
     assert solvers[0].best_cut() == ref.best_cut
     assert np.array_equal(solvers[0].step_stats(), ref.stats)
+
+
+def test_greedy_coloring_order(pa):
+    """Colour-class order (few dependency levels) on a signed and an unsigned graph."""
+    g = W.random_graph(800, 4000, 1, "small800")
+    wl = dict(W.workload("small800"), R=96, betas=W.linear_betas(0.1, 3.0, 10), sweeps=4,
+              order=W.coloring_order(g), as_enable=1, as_stall_steps=1, as_frozen_inv=4, nl_period=3)
+    s, _ = _compare(pa, g, wl)
+    assert s.launch_info()["levels"] <= 12
+    t = W.torus(20, 5, True, "torus20")
+    _compare(pa, t, dict(wl, graph=t, order=W.coloring_order(t)))

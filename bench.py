@@ -135,14 +135,84 @@ def batch_bench(args, count: int):
     print(json.dumps(out), flush=True)
 
 
+def serve_bench(args, count: int):
+    """Serving: capacity with every request present, then Poisson arrivals at
+    0.5x and 0.9x that capacity (p50/p99 latency), and FIFO on one stream."""
+    import torch
+    from paper_2510_21105_amd import pa, serve as S, workloads as W
+
+    reqs = W.serve_requests(count)
+    span = reqs[-1]["arrival"]
+
+    def requests(rate):
+        return [S.Request(j, r["graph"], pa.params_from_workload(r),
+                          0.0 if rate is None else r["arrival"] / rate * (count / span))
+                for j, r in enumerate(reqs)]
+
+    budget = int(args.hbm_budget_gb * (1 << 30))
+
+    def run(rate, streams):
+        srv = S.Server(budget, n_streams=streams)
+        t0 = time.perf_counter()
+        res = srv.serve(requests(rate), realtime=rate is not None)
+        torch.cuda.synchronize()
+        span_s = time.perf_counter() - t0
+        lat = [r.latency for r in res]
+        cuts = {r.rid: r.best_cut for r in res}
+        return dict(requests_per_s=count / span_s, p50_s=S.percentile(lat, 50),
+                    p99_s=S.percentile(lat, 99), makespan_s=span_s), cuts
+
+    print(f"[bench] serving {count} requests, {args.streams} streams", file=sys.stderr, flush=True)
+    run(None, args.streams)                                   # warm-up (allocator, tables)
+    cap, cuts0 = run(None, args.streams)
+    print(f"[bench] capacity {cap['requests_per_s']:.2f} requests/s", file=sys.stderr, flush=True)
+    out_loads = {}
+    for f in (0.5, 0.9):
+        m, cuts = run(f * cap["requests_per_s"], args.streams)
+        if cuts != cuts0:
+            raise RuntimeError("served results depend on the mix")
+        out_loads[f"{f:.1f}x"] = m
+        print(f"[bench] offered {f:.1f}x: {m}", file=sys.stderr, flush=True)
+    fifo, cuts = run(0.5 * cap["requests_per_s"], 1)
+    if cuts != cuts0:
+        raise RuntimeError("served results depend on the mix")
+    print(f"[bench] FIFO one stream at 0.5x: {fifo}", file=sys.stderr, flush=True)
+    out = {
+        "metric": "requests/s",
+        "value": cap["requests_per_s"],
+        "unit": "requests/s",
+        "n_gpus": 1,
+        "steps": 1,
+        "warmup": 1,
+        "ms_per_step": cap["makespan_s"] * 1000.0,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": f"serve{count}: N log-uniform [800, 20000] (half random "
+                               "G(N, N d/2) with d ~ U[2,12], half +-1 tori), R log-uniform "
+                               "[512, 8192], K=500, S=5, Poisson arrivals",
+                   "requests": count, "streams": args.streams,
+                   "hbm_budget_gb": args.hbm_budget_gb},
+        "capacity": cap,
+        "offered": out_loads,
+        "fifo_one_stream_0.5x": fifo,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3, help="timed solves")
     ap.add_argument("--warmup", type=int, default=1, help="untimed solves")
     ap.add_argument("--workload", default="g63like",
-                    help="g63like, torus100, small800, or batchN (N uneven instances)")
-    ap.add_argument("--streams", type=int, default=8, help="streams for batchN (1..32)")
+                    help="g63like, g63color, torus100, small800, batchN (N uneven "
+                         "instances) or serveN (N served requests)")
+    ap.add_argument("--streams", type=int, default=8, help="streams for batchN / serveN (1..32)")
+    ap.add_argument("--hbm-budget-gb", type=float, default=32.0,
+                    help="workspace budget of concurrent runs for serveN")
     ap.add_argument("--sweep-kernel", type=int, default=0,
                     help="0 automatic, 1 node-per-lane byte records, 2 replica-per-lane bit words")
     ap.add_argument("--tile", type=int, default=0, help="replicas per workgroup (0 automatic)")
@@ -158,7 +228,7 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
-    if args.workload.startswith("batch"):
+    if args.workload.startswith(("batch", "serve")):
         # One hardware queue per stream (set before the HIP runtime starts).
         args.streams = max(1, min(32, args.streams))
         if int(os.environ.get("GPU_MAX_HW_QUEUES", "4")) < args.streams:
@@ -182,6 +252,9 @@ def main():
 
     if args.workload.startswith("batch"):
         batch_bench(args, int(args.workload[5:] or 64))
+        return
+    if args.workload.startswith("serve"):
+        serve_bench(args, int(args.workload[5:] or 128))
         return
     wl = W.workload(args.workload)
     g = wl["graph"]

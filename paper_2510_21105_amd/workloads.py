@@ -275,3 +275,35 @@ def batch_workloads(count: int = 64, meta_seed: int = 5, steps: int = 500) -> li
                         as_frozen_inv=256, as_gamma=0.8, nl_period=0,
                         desc=f"{g.name}, R={R}"))
     return out
+
+
+def serve_requests(count: int = 256, meta_seed: int = 6, steps: int = 500) -> list:
+    """A request stream for the serving loop, from one SplitMix64 stream
+    (meta_seed): N log-uniform in [800, 20000]; half random graphs
+    G(N, round(N d / 2)) with d ~ U[2, 12], half L x L tori with +-1 weights,
+    L = round(sqrt N); R log-uniform in [512, 8192]; K = ``steps`` linear steps,
+    5 sweeps per step, beta 0.1 -> 5.0 (random) or 0.1 -> 4.0 (torus); plain
+    population annealing. Each request carries a unit-rate Poisson arrival
+    time (exponential gaps with mean 1 s), to be divided by the offered rate.
+    """
+    u = splitmix64(meta_seed, 5 * count).astype(np.float64) / 2.0 ** 64
+    t = 0.0
+    out = []
+    for j in range(count):
+        N = int(round(np.exp(np.log(800) + u[5 * j] * (np.log(20000) - np.log(800)))))
+        R = int(round(np.exp(np.log(512) + u[5 * j + 1] * (np.log(8192) - np.log(512)))))
+        t += -np.log1p(-u[5 * j + 4])
+        gseed = 5000 + j
+        if u[5 * j + 2] < 0.5:
+            d = 2.0 + 10.0 * u[5 * j + 3]
+            M = int(round(N * d / 2))
+            g = random_graph(N, M, gseed, f"req{j}-G({N},{M})")
+            wl = dict(graph=g, betas=linear_betas(0.1, 5.0, steps), order=natural_order(g.n))
+        else:
+            L = int(round(np.sqrt(N)))
+            g = torus(L, gseed, True, f"req{j}-torus{L}")
+            wl = dict(graph=g, betas=linear_betas(0.1, 4.0, steps), order=checkerboard_order(L))
+        out.append(dict(wl, sweeps=5, R=R, seed=42, inst=j, as_enable=0, as_stall_steps=20,
+                        as_max_level=4, as_frozen_inv=256, as_gamma=0.8, nl_period=0,
+                        arrival=t, desc=f"{g.name}, R={R}"))
+    return out

@@ -311,3 +311,22 @@ def test_greedy_coloring_order(pa):
     assert s.launch_info()["levels"] <= 12
     t = W.torus(20, 5, True, "torus20")
     _compare(pa, t, dict(wl, graph=t, order=W.coloring_order(t)))
+
+
+def test_served_requests_equal_solo_runs(pa):
+    """Requests served concurrently under a workspace budget that forces
+    queueing give the results of the same runs alone."""
+    from paper_2510_21105_amd import serve as S
+    reqs = W.serve_requests(6, steps=6)
+    items = []
+    for j, r in enumerate(reqs):
+        g = W.random_graph(min(r["graph"].n, 1500), min(r["graph"].n_edges, 4000), 300 + j)
+        items.append((g, pa.params_from_workload(dict(r, graph=g, order=None), R=min(r["R"], 600))))
+    needs = [pa.Solver(g).workspace_bytes(p) + 256 for g, p in items]
+    srv = S.Server(hbm_budget=int(2.5 * max(needs)), n_streams=3)
+    res = srv.serve([S.Request(j, g, p, 0.0) for j, (g, p) in enumerate(items)], realtime=False)
+    assert sorted(r.rid for r in res) == list(range(len(items)))
+    for r in res:
+        g, p = items[r.rid]
+        solo = pa.Solver(g).run(p)
+        assert r.best_cut == solo.best_cut() and r.best_E == solo.best_info()["E"]

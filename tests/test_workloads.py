@@ -32,3 +32,19 @@ def test_coloring_order_of_g63_shape_has_few_levels():
     g = W.workload("g63color")["graph"]
     lev = _levels(g, W.workload("g63color")["order"])
     assert lev.max() + 1 <= 10
+
+
+def test_batch_and_request_streams_are_reproducible():
+    a, b = W.serve_requests(12), W.serve_requests(12)
+    assert [x["R"] for x in a] == [x["R"] for x in b]
+    assert all(np.array_equal(x["graph"].col, y["graph"].col) for x, y in zip(a, b))
+    arr = [x["arrival"] for x in a]
+    assert all(t2 > t1 for t1, t2 in zip(arr, arr[1:]))
+    for x in a:
+        assert 800 * 0.9 <= x["graph"].n <= 20000 * 1.1 and 512 <= x["R"] <= 8192
+
+
+def test_percentile():
+    from paper_2510_21105_amd.serve import percentile
+    assert percentile([3, 1, 2], 50) == 2
+    assert percentile(list(range(101)), 99) == 99

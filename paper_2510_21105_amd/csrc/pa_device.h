@@ -18,8 +18,9 @@ namespace pa {
 
 constexpr int kStatFields = 8;
 constexpr int kMaxThreads = 1024;
-// Kernel 1 LDS: the 128-entry u32 threshold table, then the byte records.
-constexpr int kBytesRecBase = 512;
+// Kernel 1 LDS: the 256-entry u32 threshold table (indexed by a move byte),
+// then the byte records.
+constexpr int kBytesRecBase = 1024;
 
 struct GraphDev {
     int n;

@@ -494,9 +494,10 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs a, const int2 *__
 //
 // The tests work on the bytes 0x80 + (m - 1), m = d - 2u the half energy
 // change of a flip (u: edges the flip would break): bit 7 marks an uphill
-// move, and the low 7 bits index the 32-bit threshold table T[m] that sits at
-// LDS address 0 (for m >= 1 and beta > 0, T[m] < 2^32; a row where every
-// uphill threshold is 2^32 carries an accept-all flag instead). Bytewise
+// move, and the byte itself indexes the 256-entry 32-bit threshold table that
+// sits at LDS address 0, T[m] at entry 0x80 + m - 1 (for m >= 1 and beta > 0,
+// T[m] < 2^32; a row where every uphill threshold is 2^32 carries an
+// accept-all flag instead). Bytewise
 // arithmetic keeps 0x7F + d inside a byte, so this path serves graphs with
 // maximum degree <= 127; the per-replica energy changes are gathered in byte
 // accumulators that are widened into registers before they can overflow.
@@ -509,7 +510,7 @@ __host__ __device__ inline BytesLds bytes_lds_layout(int W, int sgn, int n, int 
 {
     BytesLds L;
     const size_t recs = (size_t)(sgn ? 2 * n : n) + 1;
-    L.rec = kBytesRecBase;                        // [0, 512): 128 u32 thresholds
+    L.rec = kBytesRecBase;                        // [0, 1024): 256 u32 thresholds
     L.edelta = L.rec + align16(recs * (size_t)W);
     L.misc = L.edelta + 64 * 4;
     L.total = L.misc + 16 * 8;
@@ -611,13 +612,23 @@ __global__ __launch_bounds__(1024) void sweep_bytes_kernel(SweepArgs a, const in
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int nt = blockDim.x;
-    const int blk = blockIdx.x;
+    // Workgroups are dispatched round-robin over the 8 XCDs. For 8- and
+    // 16-replica tiles (plain byte stores) each XCD takes a contiguous range
+    // of tiles, so tiles sharing a 64-replica word share an L2; 4-replica
+    // tiles keep the plain order (their nibble stores are atomic XORs, which
+    // would then contend within one XCD).
+    const int blk = [] {
+        const int b = blockIdx.x;
+        if constexpr (W < 8) return b;
+        const int nb = gridDim.x, x = b & 7, q = nb >> 3, rem = nb & 7;
+        return x * q + (x < rem ? x : rem) + (b >> 3);
+    }();
     const int r0 = blk * W;
     const int grp = r0 >> 6;
     const int sub = (r0 & 63) / W;
 
     const BytesLds L = bytes_lds_layout(W, SIGNED ? 1 : 0, n, a.dmax);
-    uint32_t *T = reinterpret_cast<uint32_t *>(smem);               // T[m] at index m - 1
+    uint32_t *T = reinterpret_cast<uint32_t *>(smem);               // T[m] at index 0x80 + m - 1
     int *Ed = reinterpret_cast<int *>(smem + L.edelta);
     long long *misc = reinterpret_cast<long long *>(smem + L.misc);
     int *Eblk = reinterpret_cast<int *>(misc + 4);
@@ -683,7 +694,9 @@ __global__ __launch_bounds__(1024) void sweep_bytes_kernel(SweepArgs a, const in
     if (tid < NR) *(lds_u32 *)(uintptr_t)(zrec + 4 * tid) = 0u;
     const int level = a.as_state[0];
     const uint32_t *trow = a.thr32 + ((size_t)a.k * a.lmax1 + level) * (size_t)(a.dmax + 1);
-    for (int m = tid; m < 128; m += nt) T[m] = m < a.dmax ? trow[m] : 0u;
+    // Move byte 0x80 + (m - 1) of an uphill move indexes T[m]; the lower half
+    // (downhill moves, accepted by mask) stays zero.
+    for (int m = tid; m < 256; m += nt) T[m] = m >= 128 && m - 128 < a.dmax ? trow[m - 128] : 0u;
     // Accept-all row (exp(-beta * 2m) rounds to 1 for every uphill move).
     const uint32_t allm = trow[a.dmax] ? 0x01010101u : 0u;
     if (tid < W) {
@@ -855,11 +868,11 @@ __global__ __launch_bounds__(1024) void sweep_bytes_kernel(SweepArgs a, const in
                     const uint32_t U = (C[q] & msk) | ((Dm - C[q]) & ~msk);
                     // w = 0x80 + (m - 1) per byte with m = d - 2u
                     const uint32_t w = (0x7F7F7F7Fu + Dm) - 2u * U;
-                    const uint32_t idx = w & 0x7F7F7F7Fu;           // T[m] sits at LDS word m - 1
                     uint32_t A = ((~w >> 7) & 0x01010101u) | allm;   // m <= 0 always accepts
 #pragma unroll
                     for (int b = 0; b < 4; ++b) {
-                        const uint32_t th = *(lds_u32 *)(uintptr_t)(((idx >> (8 * b)) & 0xFFu) << 2);
+                        // T[m] sits at LDS word 0x80 + (m - 1): the move byte itself.
+                        const uint32_t th = *(lds_u32 *)(uintptr_t)(((w >> (8 * b)) & 0xFFu) << 2);
                         A |= (dr[q][b] < th ? 1u : 0u) << (8 * b);
                     }
                     Xn.v[q] = X.v[q] ^ A;

@@ -1322,21 +1322,38 @@ __global__ __launch_bounds__(kIcmThreads) void icm_kernel(IcmArgs a)
         return;
     }
     auto inD = [&](uint32_t i) { return (D[i >> 5] >> (i & 31)) & 1u; };
-    // Components of the subgraph induced by D (the edge list is in shuffled
-    // order, so that the lanes of a wave seldom contend for one root).
+    // Components of the subgraph induced by D. A small D (at most n/16 nodes)
+    // walks the adjacency rows of its own nodes; otherwise all edges are
+    // scanned (the edge list is in shuffled order, so that the lanes of a
+    // wave seldom contend for one root). Both give the same components.
     const uint32_t *edges = a.g.edges;
     const int ne = a.g.ne;
-    for (int e0 = tid; e0 < ne; e0 += 8 * nt) {
-        uint32_t ev[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int idx = e0 + u * nt;
-            ev[u] = idx < ne ? edges[idx] : 0u;
+    const bool sparse = total * 16 <= n;
+    if (sparse) {
+        for (int w = tid; w < nw; w += nt) {
+            uint32_t bits = D[w];
+            while (bits) {
+                const uint32_t i = (uint32_t)(w * 32 + __ffs(bits) - 1);
+                bits &= bits - 1;
+                for (int e = a.g.row_ptr[i]; e < a.g.row_ptr[i + 1]; ++e) {
+                    const uint32_t j = (uint32_t)a.g.col[e];
+                    if (j > i && inD(j)) uf_unite(P, i, j);
+                }
+            }
         }
+    } else {
+        for (int e0 = tid; e0 < ne; e0 += 8 * nt) {
+            uint32_t ev[8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const uint32_t i = ev[u] & 0x7FFFu, j = (ev[u] >> 15) & 0x7FFFu;
-            if (e0 + u * nt < ne && inD(i) && inD(j)) uf_unite(P, i, j);
+            for (int u = 0; u < 8; ++u) {
+                const int idx = e0 + u * nt;
+                ev[u] = idx < ne ? edges[idx] : 0u;
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const uint32_t i = ev[u] & 0x7FFFu, j = (ev[u] >> 15) & 0x7FFFu;
+                if (e0 + u * nt < ne && inD(i) && inD(j)) uf_unite(P, i, j);
+            }
         }
     }
     // Seed node: the pick-th element of D in node order (scan of per-thread word chunks).
@@ -1381,7 +1398,23 @@ __global__ __launch_bounds__(kIcmThreads) void icm_kernel(IcmArgs a)
     // Energy change of replica a: the edges with one end in the cluster
     // change sign (an edge from the cluster to D - cluster cannot exist).
     long long dEa = 0;
-    for (int e0 = tid; e0 < ne; e0 += 8 * nt) {
+    auto bitA = [&](uint32_t i) { return (int)((A[i >> 5] >> (i & 31)) & 1u); };
+    if (sparse) {
+        for (int w = tid; w < nw; w += nt) {
+            uint32_t bits = V[w];
+            while (bits) {
+                const uint32_t i = (uint32_t)(w * 32 + __ffs(bits) - 1);
+                bits &= bits - 1;
+                const int e0 = a.g.row_ptr[i], e1 = a.g.row_ptr[i + 1], em = e0 + a.g.npos[i];
+                for (int e = e0; e < e1; ++e) {
+                    const uint32_t j = (uint32_t)a.g.col[e];
+                    if ((V[j >> 5] >> (j & 31)) & 1u) continue;
+                    dEa += -2 * (1 - 2 * (bitA(i) ^ bitA(j) ^ (e >= em ? 1 : 0)));
+                }
+            }
+        }
+    }
+    for (int e0 = tid; e0 < (sparse ? 0 : ne); e0 += 8 * nt) {
         uint32_t ev[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) {

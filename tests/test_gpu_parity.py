@@ -330,3 +330,15 @@ def test_served_requests_equal_solo_runs(pa):
         g, p = items[r.rid]
         solo = pa.Solver(g).run(p)
         assert r.best_cut == solo.best_cut() and r.best_E == solo.best_info()["E"]
+
+
+def test_cluster_moves_on_a_collapsing_population(pa):
+    """Cold schedule with strong resampling: replica pairs soon differ in few
+    spins, so the cluster move runs on small disagreement sets (adjacency-row
+    path) as well as large ones (edge-list path)."""
+    wl = dict(W.workload("small800"), R=64, betas=W.linear_betas(1.5, 6.0, 24), sweeps=2,
+              nl_period=1)
+    _compare(pa, wl["graph"], wl)
+    wl2 = dict(W.workload("g63like"), R=48, betas=W.linear_betas(2.0, 6.0, 16), sweeps=1,
+               nl_period=1, as_enable=0)
+    _compare(pa, wl2["graph"], wl2)

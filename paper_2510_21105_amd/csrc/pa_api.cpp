@@ -67,6 +67,7 @@ struct Plan {
     int K = 0, S = 0, R = 0, G = 0, Rp = 0, W = 0, threads = 0, nblk = 0, nw32 = 0;
     int lmax1 = 1, n_levels = 0, record = 0;
     int kind = 2, sgn = 0, block_bytes = 0, qpad = 0, n_rounds = 0, flush_every = 1;
+    int direct = 0;   // kernel 1: block entries are LDS byte offsets (else record indices)
     std::vector<int> sched, level_off;
     std::vector<uint32_t> blocks;   // [n][block_bytes / 4] + 128 B
     std::vector<int> stream;        // kernel 2: [waves][qpad][2]
@@ -303,7 +304,14 @@ static void build_blocks(const pa_solver *s, Plan &p)
         // rb records). Block n is an all-padding block for lanes without a
         // node in a round.
         const int rb = pa::kBytesRecBase / p.W;     // records start after the threshold table
-        const uint16_t zi = (uint16_t)((p.sgn ? 2 * n : n) + rb);
+        const int zrec = p.sgn ? 2 * n : n;         // index of the zero record
+        // Entries are LDS byte offsets when every record's offset fits in 16
+        // bits (one instruction to decode), else record indices.
+        p.direct = pa::kBytesRecBase + zrec * p.W <= 0xFFFF;
+        auto enc = [&](int rec) {
+            return (uint16_t)(p.direct ? pa::kBytesRecBase + rec * p.W : rec + rb);
+        };
+        const uint16_t zi = enc(zrec);
         const int need = 4 * ((std::max(s->dmax, 1) + 3) / 4);
         int capk = 6;
         while (capk < need) capk += 8;
@@ -319,7 +327,7 @@ static void build_blocks(const pa_solver *s, Plan &p)
             for (int e = e0; e < e1; ++e) {
                 const int j = s->col[e];
                 const bool neg = e >= e0 + s->npos[i];
-                b[2 + (e - e0)] = (uint16_t)((neg ? n + j : j) + rb);
+                b[2 + (e - e0)] = enc(neg ? n + j : j);
             }
         }
         b16[(size_t)n * bw16] = 0;
@@ -769,6 +777,7 @@ extern "C" pa_status pa_run(pa_solver *s, const pa_schedule *sch, int32_t R, uin
     sa.rounds = reinterpret_cast<const int4 *>(ws + L.stream);
     sa.n_rounds = P.n_rounds;
     sa.flush_every = P.flush_every;
+    sa.direct = P.direct;
     sa.R = R;
     sa.S = P.S;
     sa.lmax1 = P.lmax1;

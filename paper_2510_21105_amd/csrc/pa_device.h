@@ -50,6 +50,7 @@ struct SweepArgs {
     const int4 *rounds;         // [n_rounds] {first slot, level end, last round of level, 0}
     int n_rounds;
     int flush_every;            // rounds between widenings of the byte energy accumulators
+    int direct;                 // kernel 1: block entries are LDS byte offsets
     const uint64_t *thr;        // kernel 2: [K][lmax1][dmax+1] T[m] (T[0] unused)
     const uint32_t *thr32;      // kernel 1: [K][lmax1][dmax+1] T[1..dmax], all-accept flag
     const int *as_state;        // [0] level

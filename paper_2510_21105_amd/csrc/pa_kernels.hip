@@ -602,7 +602,7 @@ __device__ __forceinline__ int wave_sum_dpp(int v)
     return __builtin_amdgcn_readlane(v, 63);
 }
 
-template <int W, bool SIGNED>
+template <int W, bool SIGNED, bool DIRECT>
 __global__ __launch_bounds__(1024) void sweep_bytes_kernel(SweepArgs a, const int4 *__restrict__ rounds,
                                                           const uint4 *__restrict__ blocks)
 {
@@ -732,6 +732,7 @@ __global__ __launch_bounds__(1024) void sweep_bytes_kernel(SweepArgs a, const in
     unsigned int att = 0, acc = 0;
     int since_flush = 0;
     constexpr int SHW = W == 4 ? 2 : (W == 8 ? 3 : 4);   // record index -> LDS byte offset
+    constexpr int SHC = DIRECT ? 0 : SHW;                // block entry -> LDS byte offset
 
     Blk bufA, bufB;
     int4 rd = rounds[0];                          // the current round
@@ -739,7 +740,7 @@ __global__ __launch_bounds__(1024) void sweep_bytes_kernel(SweepArgs a, const in
     {
         // Lanes without a node in a round take block n: all entries point at the zero record.
         const int t0 = rd.x + tid;
-        blk_load(bufA, blocks + (size_t)(t0 < rd.y ? t0 : n) * bu4);
+        blk_load(bufA, blocks + __umul24((uint32_t)(t0 < rd.y ? t0 : n), (uint32_t)bu4));
     }
 
     // Per-replica energy changes of this lane: byte accumulators (YA: d - u,
@@ -785,7 +786,7 @@ __global__ __launch_bounds__(1024) void sweep_bytes_kernel(SweepArgs a, const in
         }
         {
             const int tn = nd.x + tid;
-            blk_load(nxt, blocks + (size_t)(tn < nd.y ? tn : n) * bu4);
+            blk_load(nxt, blocks + __umul24((uint32_t)(tn < nd.y ? tn : n), (uint32_t)bu4));
         }
         const int t = rd.x + tid;
         const int wave_first = __builtin_amdgcn_readfirstlane(rd.x + (tid & ~63));
@@ -802,10 +803,10 @@ __global__ __launch_bounds__(1024) void sweep_bytes_kernel(SweepArgs a, const in
             // compiler from moving the draws after the first use of the reads).
             // Lanes past their degree read the zero record.
             const Rec<NR> X = rec_load<NR>(noff);
-            const Rec<NR> g0 = rec_load<NR>((cur.b0.y & 0xFFFFu) << SHW);
-            const Rec<NR> g1 = rec_load<NR>((cur.b0.y >> 16) << SHW);
-            const Rec<NR> g2 = rec_load<NR>((cur.b0.z & 0xFFFFu) << SHW);
-            const Rec<NR> g3 = rec_load<NR>((cur.b0.z >> 16) << SHW);
+            const Rec<NR> g0 = rec_load<NR>((cur.b0.y & 0xFFFFu) << SHC);
+            const Rec<NR> g1 = rec_load<NR>((cur.b0.y >> 16) << SHC);
+            const Rec<NR> g2 = rec_load<NR>((cur.b0.z & 0xFFFFu) << SHC);
+            const Rec<NR> g3 = rec_load<NR>((cur.b0.z >> 16) << SHC);
             __builtin_amdgcn_sched_barrier(0);
             uint32_t dr[NR][4];
 #pragma unroll
@@ -824,7 +825,7 @@ __global__ __launch_bounds__(1024) void sweep_bytes_kernel(SweepArgs a, const in
         const Rec<NR> nb = rec_load<NR>(off);                   \
         _Pragma("unroll") for (int q = 0; q < NR; ++q) C[q] += nb.v[q]; \
     }
-#define PA_W(w) PA_NB(((w) & 0xFFFFu) << SHW) PA_NB(((w) >> 16) << SHW)
+#define PA_W(w) PA_NB(((w) & 0xFFFFu) << SHC) PA_NB(((w) >> 16) << SHC)
             {
                 if (md > 4) {
                     PA_W(cur.b0.w) PA_W(cur.b1.x)
@@ -844,7 +845,7 @@ __global__ __launch_bounds__(1024) void sweep_bytes_kernel(SweepArgs a, const in
                                                 const uint16_t *rest = reinterpret_cast<const uint16_t *>(
                                                     blocks + (size_t)(active ? t : rd.x) * bu4) + 2;
                                                 for (int kk = kBlkCols; kk < md; ++kk) {
-                                                    const uint32_t off = active ? (uint32_t)rest[kk] << SHW : zrec;
+                                                    const uint32_t off = active ? (uint32_t)rest[kk] << SHC : zrec;
                                                     PA_NB(off)
                                                 }
                                             }
@@ -1544,31 +1545,37 @@ int launch_sweep(int W, int sgn, int threads, int nblk, const SweepArgs &a, void
     }
 }
 
-template <int W, bool SG>
+template <int W, bool SG, bool D>
 static int launch_bytes_t(int threads, int nblk, const SweepArgs &a, void *stream)
 {
     const int lds = sweep_bytes_lds(W, SG ? 1 : 0, a.n, a.dmax);
     static int configured = 0;
     if (configured < lds) {
-        if (hipFuncSetAttribute(reinterpret_cast<const void *>(&sweep_bytes_kernel<W, SG>),
+        if (hipFuncSetAttribute(reinterpret_cast<const void *>(&sweep_bytes_kernel<W, SG, D>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess)
             return check("hipFuncSetAttribute(sweep_bytes)");
         configured = lds;
     }
-    hipLaunchKernelGGL((sweep_bytes_kernel<W, SG>), dim3(nblk), dim3(threads), lds,
+    hipLaunchKernelGGL((sweep_bytes_kernel<W, SG, D>), dim3(nblk), dim3(threads), lds,
                        (hipStream_t)stream, a, a.rounds, a.blocks);
     return check("sweep_bytes_kernel");
+}
+
+template <int W>
+static int launch_bytes_w(int sgn, int threads, int nblk, const SweepArgs &a, void *stream)
+{
+    if (sgn) return a.direct ? launch_bytes_t<W, true, true>(threads, nblk, a, stream)
+                             : launch_bytes_t<W, true, false>(threads, nblk, a, stream);
+    return a.direct ? launch_bytes_t<W, false, true>(threads, nblk, a, stream)
+                    : launch_bytes_t<W, false, false>(threads, nblk, a, stream);
 }
 
 int launch_sweep_bytes(int W, int sgn, int threads, int nblk, const SweepArgs &a, void *stream)
 {
     switch (W) {
-    case 4: return sgn ? launch_bytes_t<4, true>(threads, nblk, a, stream)
-                       : launch_bytes_t<4, false>(threads, nblk, a, stream);
-    case 8: return sgn ? launch_bytes_t<8, true>(threads, nblk, a, stream)
-                       : launch_bytes_t<8, false>(threads, nblk, a, stream);
-    case 16: return sgn ? launch_bytes_t<16, true>(threads, nblk, a, stream)
-                        : launch_bytes_t<16, false>(threads, nblk, a, stream);
+    case 4: return launch_bytes_w<4>(sgn, threads, nblk, a, stream);
+    case 8: return launch_bytes_w<8>(sgn, threads, nblk, a, stream);
+    case 16: return launch_bytes_w<16>(sgn, threads, nblk, a, stream);
     default:
         snprintf(g_err, sizeof g_err, "unsupported byte-tile width %d", W);
         return -1;

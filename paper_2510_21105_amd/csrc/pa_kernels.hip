@@ -653,17 +653,17 @@ __global__ __launch_bounds__(1024) void sweep_bytes_kernel(SweepArgs a, const in
     }
     const bool two = gB - gA <= 1;
     const uint64_t *XA = a.Xin + (size_t)gA * n, *XB = a.Xin + (size_t)gB * n;
-    // Expand the block's spin bits into byte records, 4 loads in flight per lane.
-    for (int base = 0; base < n; base += 4 * nt) {
-        uint64_t va[4], vb[4];
+    // Expand the block's spin bits into byte records, 8 loads in flight per lane.
+    for (int base = 0; base < n; base += 8 * nt) {
+        uint64_t va[8], vb[8];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < 8; ++u) {
             const int i = base + u * nt + tid;
             va[u] = i < n ? XA[i] : 0ull;
             vb[u] = i < n && !ident && two ? XB[i] : 0ull;
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < 8; ++u) {
             const int i = base + u * nt + tid;
             if (i >= n) break;
             uint64_t v = 0;
@@ -961,21 +961,38 @@ __global__ __launch_bounds__(1024) void sweep_bytes_kernel(SweepArgs a, const in
         }
     }
 
-    for (int i = tid; i < n; i += nt) {
+    auto field = [&](int i) {
         const Rec<NR> rc = rec_load<NR>(RB + (uint32_t)i * W);
         uint64_t v = 0;
 #pragma unroll
         for (int q = 0; q < NR; ++q) v |= (uint64_t)gather4(rc.v[q]) << (4 * q);
-        if constexpr (W == 16) reinterpret_cast<uint16_t *>(Xg + i)[sub] = (uint16_t)v;
-        else if constexpr (W == 8) reinterpret_cast<uint8_t *>(Xg + i)[sub] = (uint8_t)v;
-        else {
-            // 4-bit fields share a byte with the neighbouring block: flip the
-            // changed bits atomically (only this block writes these 4 bits, so
-            // the word read here holds their value from the start of the step).
-            unsigned int *wp = reinterpret_cast<unsigned int *>(Xg + i) + (sub >> 3);
-            const int sh = 4 * (sub & 7);
-            const unsigned delta = (((unsigned)v ^ (*wp >> sh)) & 0xFu) << sh;
-            if (delta) atomicXor(wp, delta);
+        return v;
+    };
+    if constexpr (W >= 8) {
+        for (int i = tid; i < n; i += nt) {
+            const uint64_t v = field(i);
+            if constexpr (W == 16) reinterpret_cast<uint16_t *>(Xg + i)[sub] = (uint16_t)v;
+            else reinterpret_cast<uint8_t *>(Xg + i)[sub] = (uint8_t)v;
+        }
+    } else {
+        // 4-bit fields share a byte with the neighbouring block: flip the
+        // changed bits atomically. Only this block writes these 4 bits during
+        // the launch, so the words can be read first, 8 per lane in flight.
+        const int sh = 4 * (sub & 7);
+        for (int base = 0; base < n; base += 8 * nt) {
+            uint32_t old[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int i = base + u * nt + tid;
+                old[u] = i < n ? reinterpret_cast<const unsigned int *>(Xg + i)[sub >> 3] : 0u;
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int i = base + u * nt + tid;
+                if (i >= n) break;
+                const unsigned delta = (((unsigned)field(i) ^ (old[u] >> sh)) & 0xFu) << sh;
+                if (delta) atomicXor(reinterpret_cast<unsigned int *>(Xg + i) + (sub >> 3), delta);
+            }
         }
     }
     if (tid < W && r0 + tid < a.R) a.E[r0 + tid] = Eblk[tid];

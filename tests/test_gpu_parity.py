@@ -342,3 +342,45 @@ def test_cluster_moves_on_a_collapsing_population(pa):
     wl2 = dict(W.workload("g63like"), R=48, betas=W.linear_betas(2.0, 6.0, 16), sweeps=1,
                nl_period=1, as_enable=0)
     _compare(pa, wl2["graph"], wl2)
+
+
+def test_torus_full_run_properties(pa):
+    """The whole 1,000-step signed-torus run (R = 16,384, checkerboard order) in
+    the benchmark's launch shape, checked by size-independent properties."""
+    wl = W.workload("torus100")
+    g = wl["graph"]
+    p = pa.params_from_workload(wl)
+    s = _device_run(pa, g, p)
+    cut = s.best_cut()
+    _say(f"torus100 full run best cut {cut} launch={s.launch_info()}")
+    x, E = s.population()
+    i, j, w = g.edges()
+    for a in range(0, p.R, 2048):
+        xb = x[a:a + 2048].astype(np.int64)
+        assert np.array_equal((xb[:, i] * xb[:, j] * w[None, :]).sum(axis=1), E[a:a + 2048])
+    assert refs.cut_eq1(g, s.best_config()) == cut
+    st = s.step_stats()
+    assert np.all(np.diff(st[:, 5]) <= 0) and st[-1, 5] == s.best_info()["E"]
+    assert np.all(st[:-1, 6] >= 1) and np.all(st[:-1, 6] <= p.R)
+    assert int(E.min()) >= s.best_info()["E"]
+    # The +-1 square-lattice spin glass has a ground-state energy of about
+    # -1.40 per spin; a 1,000-step anneal gets within about 1.5 % of it.
+    e_best = s.best_info()["E"] / g.n
+    _say(f"torus100 best energy per spin {e_best:.4f}")
+    assert -1.45 < e_best < -1.38
+
+
+def test_repeated_runs_are_identical(pa):
+    """Two runs of one solver with the same inputs agree exactly; another seed differs."""
+    wl = dict(W.workload("g63like"), R=256, betas=W.workload("g63like")["betas"][:20], nl_period=5)
+    g = wl["graph"]
+    s = pa.Solver(g)
+    p = pa.params_from_workload(wl)
+    s.run(p)
+    a_stats, (a_x, a_E) = s.step_stats(), s.population()
+    s.run(p)
+    assert np.array_equal(s.step_stats(), a_stats)
+    b_x, b_E = s.population()
+    assert np.array_equal(a_x, b_x) and np.array_equal(a_E, b_E)
+    s.run(pa.params_from_workload(wl, seed=43))
+    assert not np.array_equal(s.population()[1], a_E)

@@ -65,11 +65,19 @@ def cpu_baseline(wl, sample_steps: int):
     O.run_workload(wl, betas=betas, want_population=False, want_counts=False)
     dt = time.perf_counter() - t0
     attempts = wl["R"] * wl["graph"].n * wl["sweeps"] * len(betas)
+    # One host thread on a shorter sample (the first steps, a quarter of the replicas).
+    one = dict(wl, R=max(1, wl["R"] // 4), betas=wl["betas"][:2], nthreads=1)
+    t1 = time.perf_counter()
+    O.run_workload(one, want_population=False, want_counts=False)
+    dt1 = time.perf_counter() - t1
+    attempts1 = one["R"] * wl["graph"].n * wl["sweeps"] * 2
     return {"value": attempts / dt, "unit": "attempts/s", "cores": O.num_threads(),
             "kind": "oracle",
             "sample": f"first {len(betas)} of {len(wl['betas'])} temperature steps of the same "
                       f"workload (R={wl['R']}, N={wl['graph'].n}, S={wl['sweeps']}), "
-                      f"{dt:.1f} s on the host"}
+                      f"{dt:.1f} s on the host",
+            "value_1thread": attempts1 / dt1,
+            "sample_1thread": f"first 2 steps with R={one['R']} on one thread, {dt1:.1f} s"}
 
 
 def batch_bench(args, count: int):

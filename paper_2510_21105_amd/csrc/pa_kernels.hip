@@ -6,16 +6,24 @@
 // FP64 Metropolis thresholds and resampling weights arrive as fixed-point
 // tables built on the host.
 //
-// Design (MI355X): the population lives bit-packed, 64 replicas per 64-bit
-// word per node. One workgroup owns W replicas (W = 16, 32 or 64) for a whole
-// temperature step: it loads their N*W bits into LDS, runs all S sweeps there
-// and writes them back once, so the hot loop never touches HBM. Local fields
-// are recomputed from the neighbours' spin bits (one LDS read per neighbour,
-// no stored field array), which keeps W replicas of a 20,000-node graph inside
-// 160 KB of LDS. Lanes are replicas; a wave handles 64/W nodes at a time, and
-// the workgroup's waves cover all nodes of one dependency level of the sweep
-// order in parallel (those nodes are pairwise non-adjacent), with a barrier
-// between levels -- the same result as the sequential sweep.
+// Design (MI355X): the population lives bit-packed in HBM, 64 replicas per
+// 64-bit word per node. A sweep kernel workgroup owns W replicas for a whole
+// temperature step: it loads their spins into LDS, runs all S sweeps there and
+// writes them back once, so the sweeps never touch HBM. Local fields are
+// recomputed from the neighbours' spins (one LDS read per neighbour, no stored
+// field array). The workgroup's lanes cover the nodes of one dependency level
+// of the sweep order at a time (those nodes are pairwise non-adjacent), with a
+// barrier between levels -- the same result as the sequential sweep.
+//
+//   sweep_bytes_kernel (kernel 1, default): one lane = one node for all W = 4,
+//     8 or 16 replicas, spins as byte records, bytewise neighbour counts.
+//   sweep_kernel (kernel 2): one lane = one replica, W = 16, 32 or 64 replicas
+//     as bit words; for degrees above 127 and as an independent check.
+//   epilogue_kernel: best tracking, noise level, reweighting and systematic
+//     resampling of a step (one workgroup).
+//   icm_kernel / icm_apply_kernel: the cluster move on replica pairs.
+//   gather_kernel: resampling copies for kernel 2 (kernel 1 reads through the
+//     parent list itself).
 #include <hip/hip_runtime.h>
 
 #include "pa_device.h"

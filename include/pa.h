@@ -152,6 +152,21 @@ typedef struct {
 pa_status pa_run_batch(const pa_batch_run *runs, int32_t count, void *const *streams,
                        int32_t n_streams);
 
+/*
+ * Test hook: the fixed-point tables a run with this schedule uses, dense, as
+ * little-endian u64 into caller memory `out` (NULL: only *bytes is set):
+ *   thresholds [K][L][d_max + 1], L = as_max_level + 1 with adaptive
+ *     stochasticity else 1: entry m = floor(2^32 exp(-(beta_k gamma^l * 2m)))
+ *     for m >= 1 (gamma^l as l successive FP64 products) and 2^32 for m = 0;
+ *   weights [K - 1][e_span + 1]: entry n = floor(2^32 exp(-(beta_{k+1} -
+ *     beta_k) n)).
+ * *bytes = 8 (K L (d_max + 1) + (K - 1)(e_span + 1)). PA_EINVAL for a bad
+ * schedule (as for pa_run) or negative sizes, PA_ERANGE when
+ * d_max > 4096, e_span > 2^26 or *bytes is too small for a non-NULL `out`.
+ */
+pa_status pa_build_tables(const pa_schedule *sch, int32_t d_max, int32_t e_span, void *out,
+                          size_t *bytes);
+
 /* Best cut found by the last run: cut = (W_tot - E) / 2 (eq. (1)) and its
  * Ising energy E. Synchronises the run's stream. PA_ESTATE before a run. */
 pa_status pa_best_cut(pa_solver *s, int64_t *cut, int32_t *energy);

@@ -905,6 +905,51 @@ extern "C" pa_status pa_best_info(pa_solver *s, int64_t out[4])
     return PA_OK;
 }
 
+extern "C" pa_status pa_build_tables(const pa_schedule *sch, int32_t d_max, int32_t e_span,
+                                     void *out, size_t *bytes)
+{
+    g_error[0] = 0;
+    if (!sch || !bytes || !sch->beta) return fail(PA_EINVAL, "pa_build_tables: null argument");
+    if (sch->n_steps < 1) return fail(PA_EINVAL, "pa_build_tables: n_steps must be >= 1");
+    if (d_max < 0 || e_span < 0) return fail(PA_EINVAL, "pa_build_tables: negative size");
+    if (d_max > kMaxDegree || e_span > (1 << 26))
+        return fail(PA_ERANGE, "pa_build_tables: d_max or e_span too large");
+    for (int k = 0; k < sch->n_steps; ++k) {
+        const double b = sch->beta[k];
+        if (!std::isfinite(b) || b < 0 || (k > 0 && b < sch->beta[k - 1]))
+            return fail(PA_EINVAL, "pa_build_tables: beta must be finite, >= 0 and non-decreasing");
+    }
+    if (sch->as_enable && (sch->as_max_level < 0 || sch->as_max_level > 15 || !(sch->as_gamma > 0) ||
+                           sch->as_gamma > 1))
+        return fail(PA_EINVAL, "pa_build_tables: noise levels need 0 <= as_max_level <= 15, 0 < gamma <= 1");
+    const int K = sch->n_steps, Lv = sch->as_enable ? sch->as_max_level + 1 : 1, D = d_max + 1;
+    const size_t n_thr = (size_t)K * Lv * D, n_w = (size_t)(K - 1) * (size_t)(e_span + 1);
+    const size_t need = 8 * (n_thr + n_w);
+    if (!out) {
+        *bytes = need;
+        return PA_OK;
+    }
+    if (*bytes < need) return fail(PA_ERANGE, "pa_build_tables: %zu bytes < %zu needed", *bytes, need);
+    *bytes = need;
+    uint64_t *o = static_cast<uint64_t *>(out);
+    for (int k = 0; k < K; ++k) {
+        double g = 1.0;
+        for (int l = 0; l < Lv; ++l) {
+            const double b = sch->beta[k] * g;
+            uint64_t *row = o + ((size_t)k * Lv + l) * D;
+            row[0] = 1ull << 32;
+            for (int m = 1; m < D; ++m) row[m] = threshold_fixed(b, m);
+            g = g * sch->as_gamma;
+        }
+    }
+    uint64_t *wt = o + n_thr;
+    for (int k = 0; k + 1 < K; ++k) {
+        const double db = sch->beta[k + 1] - sch->beta[k];
+        for (int m = 0; m <= e_span; ++m) wt[(size_t)k * (e_span + 1) + m] = weight_fixed(db, m);
+    }
+    return PA_OK;
+}
+
 extern "C" pa_status pa_run_batch(const pa_batch_run *runs, int32_t count, void *const *streams,
                                   int32_t n_streams)
 {

@@ -24,7 +24,7 @@ _STATUS = {PA_EINVAL: "PA_EINVAL", PA_ERANGE: "PA_ERANGE", PA_EWORKSPACE: "PA_EW
            PA_EDEVICE: "PA_EDEVICE", PA_ESTATE: "PA_ESTATE"}
 
 EXPORTS = ("pa_last_error", "pa_create", "pa_destroy", "pa_graph_info", "pa_workspace_bytes",
-           "pa_run", "pa_run_batch", "pa_best_cut", "pa_best_info", "pa_best_config", "pa_best_config_hex",
+           "pa_run", "pa_run_batch", "pa_build_tables", "pa_best_cut", "pa_best_info", "pa_best_config", "pa_best_config_hex",
            "pa_get_population", "pa_get_initial_population", "pa_get_step_stats",
            "pa_get_counts", "pa_get_launch_info", "pa_set_timing", "pa_get_sweep_time")
 
@@ -88,6 +88,7 @@ def lib():
             "pa_workspace_bytes": [P, ctypes.POINTER(Schedule), i32, ctypes.POINTER(ctypes.c_size_t)],
             "pa_run": [P, ctypes.POINTER(Schedule), i32, u64, u32, P, ctypes.c_size_t, P],
             "pa_run_batch": [ctypes.POINTER(BatchRun), i32, ctypes.POINTER(P), i32],
+            "pa_build_tables": [ctypes.POINTER(Schedule), i32, i32, P, ctypes.POINTER(ctypes.c_size_t)],
             "pa_best_cut": [P, ctypes.POINTER(i64), ctypes.POINTER(i32)],
             "pa_best_info": [P, P],
             "pa_best_config": [P, P],
@@ -170,7 +171,8 @@ class Solver:
         _check(lib().pa_graph_info(self._h, _p(out)))
         return dict(n=int(out[0]), nnz=int(out[1]), w_tot=int(out[2]), dmax=int(out[3]))
 
-    def _schedule(self, p: RunParams):
+    @staticmethod
+    def _schedule(p: RunParams):
         betas = np.ascontiguousarray(p.betas, dtype=np.float64)
         order = None if p.order is None else np.ascontiguousarray(p.order, dtype=np.int32)
         sch = Schedule()
@@ -284,6 +286,20 @@ class Solver:
         n = ctypes.c_int64()
         _check(lib().pa_get_sweep_time(self._h, ctypes.byref(ms), ctypes.byref(n)))
         return float(ms.value), int(n.value)
+
+
+def build_tables(p: RunParams, d_max: int, e_span: int):
+    """The run's fixed-point tables (pa_build_tables): thresholds
+    [K][levels][d_max + 1] and weights [K - 1][e_span + 1], as uint64 arrays."""
+    sch, keep = Solver._schedule(p)
+    n = ctypes.c_size_t()
+    _check(lib().pa_build_tables(ctypes.byref(sch), d_max, e_span, None, ctypes.byref(n)))
+    buf = np.zeros(n.value // 8, dtype=np.uint64)
+    _check(lib().pa_build_tables(ctypes.byref(sch), d_max, e_span, _p(buf), ctypes.byref(n)))
+    K = len(p.betas)
+    L = p.as_max_level + 1 if p.as_enable else 1
+    nt = K * L * (d_max + 1)
+    return buf[:nt].reshape(K, L, d_max + 1), buf[nt:].reshape(K - 1, e_span + 1)
 
 
 def run_batch(solvers, params, streams):

@@ -230,3 +230,38 @@ def test_batch_instance_mix_is_deterministic_and_in_range():
             assert w["graph"].degrees().max() == 4 and w["sweeps"] == 5
         else:
             assert 800 <= w["graph"].n <= 7000 and w["sweeps"] == 10
+
+
+@pytest.mark.parametrize("name,over", [
+    ("small800", {}),
+    ("g63like", dict(betas=W.workload("g63like")["betas"][::50])),          # AS levels on
+    ("torus100", dict(betas=np.array([0.0, 1e-20, 1e-17, 0.05, 2.0, 4.0]))),  # saturated rows
+])
+def test_run_tables_equal_oracle_tables(name, over):
+    """The fixed-point tables a run uses (pa_build_tables) equal the oracle's,
+    entry by entry: thresholds for every step and noise level, and weights."""
+    from oracle import oracle as O
+    wl = dict(W.workload(name), **over)
+    p = pa.params_from_workload(wl)
+    dmax, span = int(wl["graph"].degrees().max()), 400
+    thr, wts = pa.build_tables(p, dmax, span)
+    levels = p.as_max_level + 1 if p.as_enable else 1
+    assert thr.shape == (len(p.betas), levels, dmax + 1) and wts.shape == (len(p.betas) - 1, span + 1)
+    for k, b in enumerate(p.betas):
+        for lv in range(levels):
+            bl = O.level_beta(float(b), p.as_gamma, lv)
+            assert int(thr[k, lv, 0]) == 1 << 32
+            assert [int(v) for v in thr[k, lv, 1:]] == [O.threshold(bl, m) for m in range(1, dmax + 1)]
+    for k in range(len(p.betas) - 1):
+        db = float(p.betas[k + 1]) - float(p.betas[k])
+        assert [int(v) for v in wts[k]] == [O.weight(db, n) for n in range(span + 1)]
+
+
+def test_build_tables_rejects_bad_input():
+    wl = W.workload("small800")
+    with pytest.raises(pa.PAError) as e:
+        pa.build_tables(pa.params_from_workload(wl, betas=[0.5, 0.1]), 4, 10)
+    assert e.value.status == pa.PA_EINVAL
+    with pytest.raises(pa.PAError) as e:
+        pa.build_tables(pa.params_from_workload(wl), 5000, 10)
+    assert e.value.status == pa.PA_ERANGE

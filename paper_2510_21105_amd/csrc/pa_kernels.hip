@@ -1375,10 +1375,21 @@ __global__ __launch_bounds__(kIcmThreads) void icm_kernel(IcmArgs a)
                 const int idx = e0 + u * nt;
                 ev[u] = idx < ne ? edges[idx] : 0u;
             }
+            // Only the edges inside D: the wave then runs as many unions as
+            // its busiest lane has, not one per edge slot.
+            uint32_t pend = 0;
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
                 const uint32_t i = ev[u] & 0x7FFFu, j = (ev[u] >> 15) & 0x7FFFu;
-                if (e0 + u * nt < ne && inD(i) && inD(j)) uf_unite(P, i, j);
+                if (e0 + u * nt < ne && inD(i) && inD(j)) pend |= 1u << u;
+            }
+            while (pend) {
+                const int u = __ffs(pend) - 1;
+                pend &= pend - 1;
+                uint32_t e = ev[0];
+#pragma unroll
+                for (int v = 1; v < 8; ++v) e = u == v ? ev[v] : e;
+                uf_unite(P, e & 0x7FFFu, (e >> 15) & 0x7FFFu);
             }
         }
     }

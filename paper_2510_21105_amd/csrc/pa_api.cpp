@@ -346,7 +346,9 @@ static void build_blocks(const pa_solver *s, Plan &p)
             }
         }
         p.n_rounds = (int)p.rounds.size() / 4;
-        p.flush_every = std::max(1, 255 / std::max(s->dmax, 1));
+        // A byte accumulator gains at most d_max per round; the kernel runs
+        // rounds in pairs, so the count is even (d_max <= 127 keeps it >= 2).
+        p.flush_every = std::max(2, (255 / std::max(s->dmax, 1)) & ~1);
         return;
     }
     const int cap = 4 * ((std::max(s->dmax, 1) + 3) / 4);

@@ -738,7 +738,6 @@ __global__ __launch_bounds__(1024) void sweep_bytes_kernel(SweepArgs a, const in
 #pragma unroll
     for (int q = 0; q < NR; ++q) { YA[q] = 0; ZA[q] = 0; }
     unsigned int att = 0, acc = 0;
-    int since_flush = 0;
     constexpr int SHW = W == 4 ? 2 : (W == 8 ? 3 : 4);   // record index -> LDS byte offset
     constexpr int SHC = DIRECT ? 0 : SHW;                // block entry -> LDS byte offset
 
@@ -901,17 +900,17 @@ __global__ __launch_bounds__(1024) void sweep_bytes_kernel(SweepArgs a, const in
                 }
             }
         }
-        ++since_flush;
-        const bool sweep_end = rho == nrounds - 1;
-        if (sweep_end) {
-            flush();
-            since_flush = 0;
-        } else if (since_flush >= a.flush_every) {
-            widen();
-            since_flush = 0;
-        }
-        if (rd.z || sweep_end) __syncthreads();
-        if (sweep_end) {
+        // Level ends need a barrier; the sweep's last one is taken after the
+        // energy flush (sweep_done).
+        if (rd.z && rho != nrounds - 1) __syncthreads();
+    };
+
+    // End of sweep s: the energy changes are summed over the workgroup, then
+    // the block's best candidate is taken.
+    auto sweep_done = [&](int s) {
+        flush();
+        __syncthreads();
+        {
             // Energies after sweep s and the block's best candidate, in wave 0
             // (lowest energy, then lowest replica; strict improvement only).
             if (tid < 64) {
@@ -957,15 +956,32 @@ __global__ __launch_bounds__(1024) void sweep_bytes_kernel(SweepArgs a, const in
         }
     };
 
-    // One loop body: the next round's block is loaded into bufB while bufA is
-    // processed, and rotated in at the end of the round.
+    // The next round's block is loaded into one buffer while the other is
+    // processed; rounds go in pairs with the two buffers' roles swapped, so no
+    // registers are copied between rounds. The byte accumulators are widened
+    // after every chunk of flush_every rounds (an even count, at most
+    // 255 / d_max, so no byte can overflow) and at the end of each sweep.
+    auto round = [&](int s, int rho, Blk &cur, Blk &nxt) {
+        int4 n2;
+        step(s, rho, cur, nxt, n2);
+        rd = nd;
+        nd = n2;
+    };
     for (int s = 0; s < a.S; ++s) {
-        for (int rho = 0; rho < nrounds; ++rho) {
-            int4 n2;
-            step(s, rho, bufA, bufB, n2);
-            bufA = bufB;
-            rd = nd;
-            nd = n2;
+        for (int rho = 0; rho < nrounds;) {
+            const int cnt = min(a.flush_every, nrounds - rho);
+            int j = 0;
+            for (; j + 2 <= cnt; j += 2) {
+                round(s, rho + j, bufA, bufB);
+                round(s, rho + j + 1, bufB, bufA);
+            }
+            if (j < cnt) {                          // odd tail at the end of a sweep
+                round(s, rho + j, bufA, bufB);
+                bufA = bufB;
+            }
+            rho += cnt;
+            if (rho < nrounds) widen();
+            else sweep_done(s);
         }
     }
 

@@ -301,8 +301,9 @@ static void build_blocks(const pa_solver *s, Plan &p)
         // bytes with the header, at least the degree rounded up to 4).
         // Negative edges name the complemented record n + j. Record indices
         // count from the start of LDS (the threshold table occupies the first
-        // rb records). Block n is an all-padding block for lanes without a
-        // node in a round.
+        // rb records). Blocks n .. n + threads - 1 are all-padding blocks:
+        // a lane reads the block of slot (first slot of its round + lane),
+        // which may lie past the last node.
         const int rb = pa::kBytesRecBase / p.W;     // records start after the threshold table
         const int zrec = p.sgn ? 2 * n : n;         // index of the zero record
         // Entries are LDS byte offsets when every record's offset fits in 16
@@ -317,7 +318,7 @@ static void build_blocks(const pa_solver *s, Plan &p)
         while (capk < need) capk += 8;
         p.block_bytes = 2 * (2 + capk);
         const int bw16 = p.block_bytes / 2;
-        std::vector<uint16_t> b16((size_t)(n + 1) * bw16 + 32, zi);
+        std::vector<uint16_t> b16((size_t)(n + p.threads) * bw16 + 32, zi);
         for (int t = 0; t < n; ++t) {
             const int i = p.sched[t];
             uint16_t *b = &b16[(size_t)t * bw16];
@@ -330,8 +331,10 @@ static void build_blocks(const pa_solver *s, Plan &p)
                 b[2 + (e - e0)] = enc(neg ? n + j : j);
             }
         }
-        b16[(size_t)n * bw16] = 0;
-        b16[(size_t)n * bw16 + 1] = 0;
+        for (int t = n; t < n + p.threads; ++t) {
+            b16[(size_t)t * bw16] = 0;
+            b16[(size_t)t * bw16 + 1] = 0;
+        }
         p.blocks.assign((b16.size() + 1) / 2, 0u);
         std::memcpy(p.blocks.data(), b16.data(), b16.size() * sizeof(uint16_t));
         // Rounds: a level is cut into chunks of one node per thread.

@@ -744,11 +744,17 @@ __global__ __launch_bounds__(1024) void sweep_bytes_kernel(SweepArgs a, const in
     Blk bufA, bufB;
     int4 rd = rounds[0];                          // the current round
     int4 nd = rounds[nrounds > 1 ? 1 : 0];        // the next round
-    {
-        // Lanes without a node in a round take block n: all entries point at the zero record.
-        const int t0 = rd.x + tid;
-        blk_load(bufA, blocks + __umul24((uint32_t)(t0 < rd.y ? t0 : n), (uint32_t)bu4));
-    }
+    // Lane tid reads the block of slot (first slot of the round + tid): a
+    // uniform base plus a per-lane constant offset. Slots past a level's end
+    // belong to later levels or to the padding blocks after the last node;
+    // those lanes only read.
+    const uint32_t lane_off = (uint32_t)tid * (uint32_t)bu4 * 16u;
+    auto blk_at = [&](int first) {
+        return reinterpret_cast<const uint4 *>(reinterpret_cast<const unsigned char *>(blocks) +
+                                               (size_t)(uint32_t)first * (uint32_t)(bu4 * 16) + lane_off);
+    };
+    const int wbase = __builtin_amdgcn_readfirstlane(tid & ~63);   // first thread of this wave
+    blk_load(bufA, blk_at(rd.x));
 
     // Per-replica energy changes of this lane: byte accumulators (YA: d - u,
     // ZA: u, per accepted flip; the flip changes E by 2(d - 2u)) are widened
@@ -791,14 +797,10 @@ __global__ __launch_bounds__(1024) void sweep_bytes_kernel(SweepArgs a, const in
             if (r2 >= nrounds) r2 -= nrounds;
             n2 = rounds[r2];
         }
-        {
-            const int tn = nd.x + tid;
-            blk_load(nxt, blocks + __umul24((uint32_t)(tn < nd.y ? tn : n), (uint32_t)bu4));
-        }
+        blk_load(nxt, blk_at(nd.x));
         const int t = rd.x + tid;
-        const int wave_first = __builtin_amdgcn_readfirstlane(rd.x + (tid & ~63));
-        if (wave_first < rd.y) {            // some lane of this wave has a node
-            const bool active = t < rd.y;
+        if (rd.x + wbase < rd.y) {          // some lane of this wave has a node
+            const bool active = tid < rd.y - rd.x;
             const uint32_t node = cur.b0.x & 0xFFFFu;
             const uint32_t noff = active ? RB + (node << SHW) : zrec;
             const int d = active ? (int)(cur.b0.x >> 16) : 0;

@@ -478,6 +478,15 @@ static pa_status build_plan(pa_solver *s, const pa_schedule *sch, int R, Plan &p
         return fail(PA_EINVAL, "sweep kernel 1 needs max degree <= %d and tile 4, 8 or 16", kMaxBytesDegree);
     if (req != 2 && bytes_ok) {
         W = tile;
+        if (W == 0 && s->dmax <= 8 && bytes_fit(8)) {
+            // Measured on MI355X: on low-degree graphs (tori) a round's work per
+            // node is small and 8-replica tiles spread the per-node cost over
+            // the most replicas, even with fewer workgroups than CUs; 256
+            // threads when two workgroups fit a CU, else 512.
+            W = 8;
+            if (sch->wg_threads == 0)
+                p.threads = 2 * pa::sweep_bytes_lds(8, p.sgn, n, s->dmax) <= max_lds ? 256 : 512;
+        }
         if (W == 0) {
             // Measured on MI355X: two resident workgroups of 512 threads per CU
             // hide the per-level latency best. Take the widest tile whose LDS

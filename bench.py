@@ -61,6 +61,7 @@ def measured_traffic_per_launch(workload: str):
 def cpu_baseline(wl, sample_steps: int):
     from oracle import oracle as O
     betas = wl["betas"][:sample_steps]
+    cores = O.num_threads()       # before the one-thread sample below changes it
     t0 = time.perf_counter()
     O.run_workload(wl, betas=betas, want_population=False, want_counts=False)
     dt = time.perf_counter() - t0
@@ -71,7 +72,7 @@ def cpu_baseline(wl, sample_steps: int):
     O.run_workload(one, want_population=False, want_counts=False)
     dt1 = time.perf_counter() - t1
     attempts1 = one["R"] * wl["graph"].n * wl["sweeps"] * 2
-    return {"value": attempts / dt, "unit": "attempts/s", "cores": O.num_threads(),
+    return {"value": attempts / dt, "unit": "attempts/s", "cores": cores,
             "kind": "oracle",
             "sample": f"first {len(betas)} of {len(wl['betas'])} temperature steps of the same "
                       f"workload (R={wl['R']}, N={wl['graph'].n}, S={wl['sweeps']}), "

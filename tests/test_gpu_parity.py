@@ -265,6 +265,33 @@ def test_every_adjacency_block_size(pa, cls):
         _compare(pa, g, wl, dict(sweep_kernel=1, tile_replicas=tile))
 
 
+def _cycle_with_hub(n: int, deg: int):
+    """Signed cycle on n nodes plus chords from node 0 to deg - 2 others, so
+    node 0 has degree deg and every other node degree 2 or 3."""
+    i = list(range(n))
+    j = [(k + 1) % n for k in range(n)]
+    targets = np.linspace(2, n - 2, deg - 2).round().astype(int)
+    assert len(set(targets.tolist())) == deg - 2
+    i += [0] * (deg - 2)
+    j += targets.tolist()
+    sgn = np.where(W.splitmix64(17 + deg, len(i)) & np.uint64(1), -1, 1)
+    return W.from_edges(n, np.array(i), np.array(j), sgn, f"cyclehub{deg}")
+
+
+@pytest.mark.parametrize("deg", [5, 8, 9, 12, 13, 16, 17, 20, 21, 24, 25, 28, 29, 30, 31, 33])
+def test_hub_degree_at_every_read_boundary(pa, deg):
+    """The node-per-lane kernel reads adjacency entries in groups sized by the
+    largest degree in a wave; every lane of the hub's wave reads that many
+    entries of its own block. One hub degree on each side of every group
+    boundary, both tile widths, against the oracle."""
+    g = _cycle_with_hub(160, deg)
+    assert int(g.degrees().max()) == deg
+    wl = dict(W.workload("small800"), graph=g, R=72, betas=W.linear_betas(0.2, 2.5, 4),
+              sweeps=2, order=W.natural_order(g.n), nl_period=0)
+    for tile in (4, 8):
+        _compare(pa, g, wl, dict(sweep_kernel=1, tile_replicas=tile))
+
+
 def test_tiny_inverse_temperatures(pa):
     """beta = 0 and 1e-20 (every uphill move accepted), 1e-17 (exp rounds to 1
     for the smallest moves only: served by the word kernel), then normal."""

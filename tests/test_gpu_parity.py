@@ -411,3 +411,25 @@ def test_repeated_runs_are_identical(pa):
     assert np.array_equal(a_x, b_x) and np.array_equal(a_E, b_E)
     s.run(pa.params_from_workload(wl, seed=43))
     assert not np.array_equal(s.population()[1], a_E)
+
+
+def test_gset_file_command_line_solve(pa, tmp_path):
+    """A G-set file through the command-line solve: its best cut and hex
+    configuration equal the oracle's run of the same schedule, and the hex
+    decodes to a configuration with that eq. (1) cut."""
+    from paper_2510_21105_amd import gset, hexcfg, solve
+    g = W.random_graph(300, 1200, 12)
+    gp, hp = tmp_path / "g.txt", tmp_path / "best.hex"
+    gset.save(g, str(gp))
+    _say(f"solve command on {gp.name}: n={g.n} m={g.n_edges}")
+    out = solve.main(["--gset", str(gp), "--replicas", "192", "--steps", "30", "--sweeps", "4",
+                      "--nl-period", "5", "--instance", "3", "--hex-out", str(hp)])
+    h = gset.load(str(gp))
+    wl = dict(graph=h, betas=W.linear_betas(0.1, 5.0, 30), sweeps=4, order=W.natural_order(h.n),
+              R=192, seed=42, inst=3, as_enable=1, as_stall_steps=20, as_max_level=4,
+              as_frozen_inv=256, as_gamma=0.8, nl_period=5)
+    ref = O.run_workload(wl, want_population=False, want_counts=False)
+    assert out["best_cut"] == ref.best_cut
+    x = hexcfg.hex_to_config(hp.read_text(), g.n)
+    assert np.array_equal(x, ref.best_x)
+    assert gset.cut_value(g, x) == out["best_cut"]

@@ -62,7 +62,11 @@ def lib():
         L.oracle_resample_counts.restype = u64
         L.oracle_icm_pair.argtypes = [i32, P, P, P, P, u32, P]
         L.oracle_icm_pair.restype = i32
-        L.oracle_run.argtypes = [i32, P, P, P, i32, P, i32, P, i32, i32, i32, i32, f64, i32,
+        L.oracle_bond_threshold.argtypes = [f64]
+        L.oracle_bond_threshold.restype = u64
+        L.oracle_wolff.argtypes = [i32, P, P, P, P, P, u64, u64, u32, u32, u32, P]
+        L.oracle_wolff.restype = i32
+        L.oracle_run.argtypes = [i32, P, P, P, i32, P, i32, P, i32, i32, i32, i32, f64, i32, i32,
                                  i32, u64, u32, i32, P, P, P, P, P, P, P]
         L.oracle_run.restype = ctypes.c_int
         L.oracle_num_threads.argtypes = []
@@ -120,6 +124,20 @@ def icm_pair(g, xa, xb, d: int):
     return xa, xb, mask.astype(bool), int(size)
 
 
+def bond_threshold(a: float) -> int:
+    return int(lib().oracle_bond_threshold(a))
+
+
+def wolff(g, x, q: int, seed: int, inst: int, step: int, replica: int):
+    """One single-replica cluster update of a copy of x with bond threshold q;
+    return (x', mask, size)."""
+    x = np.array(x, dtype=np.int8)
+    mask = np.zeros(g.n, dtype=np.uint8)
+    size = lib().oracle_wolff(g.n, _p(g.row_ptr), _p(g.col), _p(g.w), _p(x), None, q, seed, inst,
+                              step, replica, _p(mask))
+    return x, mask.astype(bool), int(size)
+
+
 def num_threads() -> int:
     return int(lib().oracle_num_threads())
 
@@ -145,7 +163,7 @@ class RunResult:
 
 def run(g, betas, sweeps, R, seed, inst=0, order=None, as_enable=0, as_stall_steps=20,
         as_max_level=4, as_frozen_inv=256, as_gamma=0.8, nl_period=0, nthreads=0,
-        want_population=True, want_counts=True) -> RunResult:
+        want_population=True, want_counts=True, nl_kind=0) -> RunResult:
     betas = np.ascontiguousarray(betas, dtype=np.float64)
     K = betas.shape[0]
     order_a = None if order is None else np.ascontiguousarray(order, dtype=np.int32)
@@ -158,7 +176,8 @@ def run(g, betas, sweeps, R, seed, inst=0, order=None, as_enable=0, as_stall_ste
     counts = np.zeros((K, R), dtype=np.int32) if want_counts else None
     rc = lib().oracle_run(g.n, _p(g.row_ptr), _p(g.col), _p(g.w), K, _p(betas), sweeps,
                           _p(order_a), as_enable, as_stall_steps, as_max_level, as_frozen_inv,
-                          as_gamma, nl_period, R, seed, inst, nthreads, _p(x_init), _p(x_out),
+                          as_gamma, nl_period, nl_kind, R, seed, inst, nthreads, _p(x_init),
+                          _p(x_out),
                           _p(E), _p(best), _p(best_x), _p(stats), _p(counts))
     if rc != 0:
         raise ValueError(f"oracle_run rejected its arguments (rc={rc})")
@@ -174,4 +193,4 @@ def run_workload(wl: dict, **over) -> RunResult:
     return run(p["graph"], p["betas"], p["sweeps"], p["R"], p["seed"], p["inst"], p["order"],
                p["as_enable"], p["as_stall_steps"], p["as_max_level"], p["as_frozen_inv"],
                p["as_gamma"], p["nl_period"], p.get("nthreads", 0),
-               p.get("want_population", True), p.get("want_counts", True))
+               p.get("want_population", True), p.get("want_counts", True), p.get("nl_kind", 0))

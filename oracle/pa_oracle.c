@@ -24,7 +24,8 @@
  *         (tag, sweep s, step k, node i, replica r) is word (r & 3) of
  *         Philox(key = (lo32 seed, hi32 seed),
  *                ctr = (i, s | tag << 16, k, (r >> 2) | inst << 16)).
- *         Tags: 0 Metropolis, 1 initial spins, 2 resampling, 3 non-local.
+ *         Tags: 0 Metropolis, 1 initial spins, 2 resampling, 3 non-local
+ *         pair seed, 4 single-replica cluster seed, 5 bond activation.
  *   Init  x_i^r = +1 if bit 0 of draw(1, 0, 0, i, r) is set, else -1.
  *   Sweep for each replica, for t = 0..N-1, i = order[t]:
  *         h_i = sum_j w_ij x_j, m = -x_i h_i (the flip changes E by 2m);
@@ -41,6 +42,17 @@
  *         both replicas, the connected component of that node in the
  *         subgraph induced by D (Houdayer's cluster move). Then the best
  *         check runs again (recorded with sweep index S).
+ *   NL, single-replica kind (nl_kind 1, same steps): every replica r on its
+ *         own makes one Wolff cluster update at the step's sweep temperature
+ *         beta' = beta_k gamma^l. Seed s = floor(draw(4, 0, k, 0, r) * N /
+ *         2^32). Each edge {i < j} whose term w_ij x_i x_j is negative (a
+ *         satisfied bond of the couplings J = -w) is activated iff
+ *         draw(5, j, k, i, r) < Q(beta' |w_ij|), Q(a) = floor(2^32 * (1 -
+ *         exp(-2a))) evaluated as -expm1(-2a) in FP64. The connected component
+ *         of s in the graph of active bonds is flipped (Wolff's construction
+ *         for couplings of either sign: it satisfies detailed balance with
+ *         respect to exp(-beta' E) and needs no acceptance test). Then the
+ *         best check runs again (recorded with sweep index S).
  *   AS    if the best improved during step k: level l <- 0, stall <- 0;
  *         else stall += 1, and if stall >= P_stall and
  *         frozen_inv * (uphill accepts) < (uphill attempts) during step k
@@ -235,6 +247,59 @@ int32_t oracle_icm_pair(int32_t n, const int32_t *row_ptr, const int32_t *col,
     return tail;
 }
 
+/* floor(2^32 * (1 - exp(-2a))): the probability of activating a satisfied
+ * bond of strength a / beta at inverse temperature beta. */
+uint64_t oracle_bond_threshold(double a)
+{
+    double q = -expm1(-2.0 * a);
+    return (uint64_t)floor(ldexp(q, 32));
+}
+
+/* Wolff cluster update of one replica (Wolff, PRL 62, 361 (1989), with bond
+ * activation on satisfied bonds of either sign). x is modified in place;
+ * q = oracle_bond_threshold(beta) applies to every edge of weight +-1 and
+ * q_of_w (NULL for unit weights) holds thresholds by |w| (index |w|).
+ * in_cluster (n bytes, may be NULL) receives 1 for flipped nodes. The bond
+ * draws are draw(5, j, step, i, replica) for the edge {i < j}; the seed is
+ * floor(draw(4, 0, step, 0, replica) * n / 2^32). Returns the cluster size. */
+int32_t oracle_wolff(int32_t n, const int32_t *row_ptr, const int32_t *col, const int8_t *w,
+                     int8_t *x, const uint64_t *q_of_w, uint64_t q, uint64_t seed, uint32_t inst,
+                     uint32_t step, uint32_t replica, uint8_t *in_cluster)
+{
+    if (n <= 0) return 0;
+    uint32_t d = oracle_draw(seed, inst, 4, 0, step, 0, replica);
+    int32_t s = (int32_t)(((uint64_t)d * (uint64_t)n) >> 32);
+    uint8_t *seen = (uint8_t *)calloc((size_t)n, 1);
+    int32_t *queue = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    int32_t head = 0, tail = 0;
+    queue[tail++] = s;
+    seen[s] = 1;
+    /* Breadth-first growth over active bonds; whether a bond is active
+     * depends only on its endpoints' spins before the update and its own
+     * draw, so the order of growth does not matter. */
+    while (head < tail) {
+        int32_t i = queue[head++];
+        for (int32_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
+            int32_t j = col[e];
+            if (seen[j]) continue;
+            if ((int32_t)w[e] * x[i] * x[j] >= 0) continue;           /* not satisfied */
+            int32_t lo = i < j ? i : j, hi = i < j ? j : i;
+            uint64_t qq = q_of_w ? q_of_w[w[e] < 0 ? -w[e] : w[e]] : q;
+            uint32_t u = oracle_draw(seed, inst, 5, (uint32_t)hi, step, (uint32_t)lo, replica);
+            if ((uint64_t)u < qq) { seen[j] = 1; queue[tail++] = j; }
+        }
+    }
+    if (in_cluster) memset(in_cluster, 0, (size_t)n);
+    for (int32_t t = 0; t < tail; ++t) {
+        int32_t i = queue[t];
+        x[i] = (int8_t)-x[i];
+        if (in_cluster) in_cluster[i] = 1;
+    }
+    free(seen);
+    free(queue);
+    return tail;
+}
+
 /* ------------------------------------------------------------ PA driver */
 
 static void best_check(int32_t R, int32_t n, const int32_t *E, const int8_t *x,
@@ -265,14 +330,15 @@ static void best_check(int32_t R, int32_t n, const int32_t *E, const int8_t *x,
 int oracle_run(int32_t n, const int32_t *row_ptr, const int32_t *col, const int8_t *w,
                int32_t K, const double *beta, int32_t S, const int32_t *order,
                int32_t as_enable, int32_t as_stall_steps, int32_t as_max_level,
-               int32_t as_frozen_inv, double as_gamma, int32_t nl_period,
+               int32_t as_frozen_inv, double as_gamma, int32_t nl_period, int32_t nl_kind,
                int32_t R, uint64_t seed, uint32_t inst, int32_t nthreads,
                int8_t *x_init, int8_t *x_out, int32_t *E_out, int64_t *best,
                int8_t *best_x, int64_t *stats, int32_t *counts)
 {
     if (n <= 0 || K <= 0 || S <= 0 || S > 65535 || R <= 0 || R > 32768 || inst > 65535)
         return -1;
-    if (nl_period > 0 && (R & 1)) return -1;
+    if (nl_kind != 0 && nl_kind != 1) return -1;
+    if (nl_period > 0 && nl_kind == 0 && (R & 1)) return -1;
     if (as_enable && (as_stall_steps < 1 || as_max_level < 0 || as_frozen_inv < 1)) return -1;
     for (int32_t k = 0; k < K; ++k) {
         if (!(beta[k] >= 0.0) || !isfinite(beta[k])) return -1;
@@ -361,7 +427,19 @@ int oracle_run(int32_t n, const int32_t *row_ptr, const int32_t *col, const int8
         uint64_t att_up = 0, acc_up = 0;
         for (int32_t r = 0; r < R; ++r) { att_up += att[r]; acc_up += acc[r]; }
 
-        if (nl_period > 0 && (k + 1) % nl_period == 0) {
+        if (nl_period > 0 && (k + 1) % nl_period == 0 && nl_kind == 1) {
+            uint64_t q = oracle_bond_threshold(b);
+#pragma omp parallel for schedule(dynamic, 1)
+            for (int32_t r = 0; r < R; ++r) {
+                int8_t *xr = x + (size_t)r * n;
+                if (oracle_wolff(n, row_ptr, col, w, xr, NULL, q, seed, inst, (uint32_t)k,
+                                 (uint32_t)r, NULL) > 0) {
+                    E[r] = (int32_t)oracle_energy(n, row_ptr, col, w, xr);
+                    fields(n, row_ptr, col, w, xr, h + (size_t)r * n);
+                }
+            }
+            best_check(R, n, E, x, bst, bx, k, S, &improved);
+        } else if (nl_period > 0 && (k + 1) % nl_period == 0) {
             int32_t half = R / 2;
 #pragma omp parallel for schedule(dynamic, 1)
             for (int32_t p = 0; p < half; ++p) {

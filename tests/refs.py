@@ -91,3 +91,11 @@ def component_of(g, mask, node) -> np.ndarray:
     a = sp.coo_matrix((np.ones(int(keep.sum())), (i[keep], j[keep])), shape=(g.n, g.n))
     _, lab = csg.connected_components(a, directed=False)
     return (lab == lab[node]) & mask
+
+
+def component_over_edges(n, i, j, active, node) -> np.ndarray:
+    """Connected component of ``node`` in the graph on n nodes whose edges are
+    (i[k], j[k]) for the k with active[k] (scipy's connected components)."""
+    a = sp.coo_matrix((np.ones(int(active.sum())), (i[active], j[active])), shape=(n, n))
+    _, lab = csg.connected_components(a, directed=False)
+    return lab == lab[node]

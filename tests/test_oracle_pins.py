@@ -313,6 +313,117 @@ def test_cluster_move_identical_replicas_is_noop():
     assert size == 0 and not mask.any() and np.array_equal(ya, x)
 
 
+# ------------------------------------------- single-replica cluster move ----
+
+def _exact_bond_floor(a: float) -> tuple[int, bool]:
+    """floor(2^32 * (1 - exp(-2a))) in 60-digit decimal; flag near-integers."""
+    getcontext().prec = 60
+    v = (1 - Decimal(-2 * a).exp()) * (Decimal(2) ** 32)
+    f = int(v)
+    frac = v - f
+    return f, (frac < Decimal("1e-6") or frac > 1 - Decimal("1e-6"))
+
+
+@pytest.mark.parametrize("a", [0.0, 1e-12, 1e-6, 0.05, 0.5, 0.8 * 2.2, 5.0, 11.0, 30.0])
+def test_bond_threshold_matches_high_precision_exp(a):
+    q = O.bond_threshold(a)
+    f, edge = _exact_bond_floor(a)
+    assert abs(q - f) <= (1 if edge else 0)
+    assert 0 <= q <= 2 ** 32
+    assert O.bond_threshold(a + 0.1) >= q
+
+
+def test_wolff_at_beta_zero_flips_the_seed_only():
+    """No bond is active at beta = 0: the update flips exactly the seed node,
+    floor(u * N / 2^32) for the replica's seed draw u, uniform over nodes."""
+    g = W.random_graph(37, 120, 3)
+    rng = np.random.default_rng(1)
+    hits = np.zeros(g.n, np.int64)
+    for t in range(3700):
+        x = rng.choice(np.array([-1, 1], np.int8), size=g.n)
+        y, mask, size = O.wolff(g, x, 0, 42, 0, t, t % 5)
+        assert size == 1 and int(mask.sum()) == 1
+        s = int(np.nonzero(mask)[0][0])
+        assert s == (O.draw(42, 0, 4, 0, t, 0, t % 5) * g.n) >> 32
+        assert y[s] == -x[s] and np.array_equal(np.delete(y, s), np.delete(x, s))
+        hits[s] += 1
+    chi2 = float(((hits - 100.0) ** 2 / 100.0).sum())
+    assert chi2 < 80.0      # 36 dof
+
+
+@pytest.mark.parametrize("gen", ["random", "torus"])
+def test_wolff_with_every_satisfied_bond_active(gen):
+    """q = 2^32 activates every satisfied bond (w_ij x_i x_j < 0): the flipped
+    set is the seed's component in the graph of those edges."""
+    g = W.random_graph(300, 700, 5) if gen == "random" else W.torus(12, 9, True)
+    i, j, w = g.edges()
+    rng = np.random.default_rng(2)
+    for t in range(20):
+        x = rng.choice(np.array([-1, 1], np.int8), size=g.n)
+        y, mask, size = O.wolff(g, x, 2 ** 32, 7, 1, t, 3)
+        seed_node = (O.draw(7, 1, 4, 0, t, 0, 3) * g.n) >> 32
+        sat = (w * x[i].astype(np.int64) * x[j]) < 0
+        comp = refs.component_over_edges(g.n, i, j, sat, seed_node)
+        assert np.array_equal(mask, comp) and size == int(comp.sum())
+        assert np.array_equal(y[comp], -x[comp]) and np.array_equal(y[~comp], x[~comp])
+        # the flipped cluster's boundary holds only unsatisfied bonds before the move
+        cross = comp[i] != comp[j]
+        assert not np.any(sat & cross)
+
+
+def test_wolff_samples_boltzmann_distribution():
+    """Many single-replica cluster updates at fixed beta on a small signed
+    graph: the visited states follow exp(-beta E) / Z (Wolff's move satisfies
+    detailed balance with no acceptance step)."""
+    g = W.from_edges(7, [0, 0, 1, 2, 3, 4, 5, 1, 2, 0, 3],
+                     [1, 2, 3, 4, 5, 6, 6, 5, 6, 6, 6],
+                     [1, -1, 1, 1, -1, 1, 1, 1, -1, -1, 1])
+    beta = 0.5
+    q = O.bond_threshold(beta)
+    E = refs.all_energies(g)
+    p = np.exp(-beta * (E - E.min()))
+    p /= p.sum()
+    x = np.ones(g.n, np.int8)
+    T = 60000
+    states = np.zeros(T, np.int64)
+    for t in range(T):
+        x, _, _ = O.wolff(g, x, q, 11, 0, t, 0)
+        states[t] = refs.state_index(x[None, :])[0]
+    obs = np.bincount(states, minlength=p.shape[0])
+    # successive states are correlated; compare frequencies with a loose
+    # total-variation bound and rule out the wrong temperature
+    assert 0.5 * np.abs(obs / T - p).sum() < 0.03
+    p_bad = np.exp(-2.0 * beta * (E - E.min()))
+    p_bad /= p_bad.sum()
+    assert 0.5 * np.abs(obs / T - p_bad).sum() > 0.08
+
+
+def test_wolff_in_run_keeps_energies_and_estimator():
+    """Population annealing with a single-replica cluster update after every
+    step: energies stay those of the configurations and the free-energy
+    estimator still reproduces ln Z(beta) by enumeration."""
+    g = W.random_graph(12, 30, 9)
+    betas = W.linear_betas(0.0, 1.5, 31)
+    R = 20000
+    r = _run(g, betas, sweeps=5, R=R, seed=3, nl_period=1, nl_kind=1)
+    i, j, w = g.edges()
+    for q in range(0, R, 997):
+        xq = r.x[q].astype(np.int64)
+        assert int(r.E[q]) == int(np.sum(w * xq[i] * xq[j]))
+    est = g.n * math.log(2.0)
+    for k in range(len(betas) - 1):
+        dbeta = betas[k + 1] - betas[k]
+        est += math.log(float(r.stats[k, 7]) / (R * 2.0 ** 32)) - dbeta * float(r.stats[k, 0])
+    E = refs.all_energies(g)
+    b = betas[-1]
+    exact = float(np.log(np.exp(-b * (E - E.min())).sum()) - b * E.min())
+    assert abs(est - exact) < 0.03
+    plain = _run(g, betas, sweeps=5, R=R, seed=3)
+    assert not np.array_equal(plain.x, r.x)
+    # an odd population is fine without pairing
+    _run(g, betas[:3], sweeps=1, R=7, nl_period=1, nl_kind=1)
+
+
 # --------------------------------------------------------- run invariants ----
 
 @pytest.mark.parametrize("name,over", [

@@ -58,7 +58,8 @@ typedef struct {
     int32_t as_max_level;     /* highest noise level, 0..15                       */
     int32_t as_frozen_inv;    /* raise only if frozen_inv * uphill_accepts < uphill_attempts, >= 1 */
     double as_gamma;          /* level l sweeps at beta_k * gamma^l, 0 < gamma <= 1 */
-    int32_t nl_period;        /* non-local cluster moves every nl_period steps, 0 = off */
+    int32_t nl_period;        /* non-local cluster moves every nl_period steps, 0 = off;
+                                 the kind is nl_kind below                       */
     int32_t sweep_kernel;     /* 0 = automatic; 1 = one node per lane over byte spin
                                  records (max degree <= 127); 2 = one replica per lane
                                  over bit spin words. Results never depend on it.  */
@@ -69,6 +70,17 @@ typedef struct {
                                  multiple of 64 in [64, 1024]. Results never depend on it. */
     int32_t record;           /* bit 0: keep per-step copy counts; bit 1: keep the
                                  initial population (both for pa_get_* below)     */
+    int32_t nl_kind;          /* kind of non-local move (the paper names the moves, section
+                                 3, without defining them):
+                                 0 = Houdayer cluster move on the replica pairs
+                                     (p, p + R/2), R even: the connected component of a
+                                     random node of the set where the two disagree is
+                                     flipped in both;
+                                 1 = single-replica Wolff cluster update of every
+                                     replica at the step's sweep temperature beta' =
+                                     beta_k gamma^l: a bond with w_ij x_i x_j < 0 is
+                                     activated with probability 1 - exp(-2 beta'), and
+                                     the active-bond component of a random node flips. */
 } pa_schedule;
 
 /* Text of the last error on this thread ("" if none). */

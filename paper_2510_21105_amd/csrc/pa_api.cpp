@@ -58,7 +58,8 @@ constexpr size_t kAlign = 256;
 size_t align_up(size_t b, size_t a = kAlign) { return (b + a - 1) / a * a; }
 
 struct Layout {
-    size_t row_ptr, col, npos, edges, vout, sched, level_off, blocks, stream, thr, wtab, wtab_off, wtab_len;
+    size_t row_ptr, col, npos, edges, vout, qtab, sched, level_off, blocks, stream, thr, wtab, wtab_off,
+        wtab_len;
     size_t X0, X1, E0, E1, cand, snap, counters, as_state, best, best_x, stats, parent;
     size_t counts, xinit, total;
 };
@@ -74,6 +75,7 @@ struct Plan {
     std::vector<int> rounds;        // kernel 1: [n_rounds][4]
     std::vector<uint64_t> thr, wtab;
     std::vector<uint32_t> thr32;   // kernel 1: [K][lmax1][dmax + 1] = T[1..dmax], saturation flag
+    std::vector<uint64_t> qtab;    // single-replica cluster moves: [K][lmax1] bond thresholds
     std::vector<int> wtab_off, wtab_len;
     Layout L{};
 };
@@ -229,7 +231,9 @@ static pa_status check_schedule(const pa_solver *s, const pa_schedule *sch, int 
     }
     if (sch->nl_period < 0) return fail(PA_EINVAL, "nl_period must be >= 0");
     if (R < 1 || R > kMaxR) return fail(PA_ERANGE, "R=%d outside [1, %d]", R, kMaxR);
-    if (sch->nl_period > 0 && (R & 1)) return fail(PA_EINVAL, "non-local moves pair replicas: R must be even");
+    if (sch->nl_kind != 0 && sch->nl_kind != 1) return fail(PA_EINVAL, "nl_kind must be 0 or 1");
+    if (sch->nl_period > 0 && sch->nl_kind == 0 && (R & 1))
+        return fail(PA_EINVAL, "pair cluster moves pair replicas: R must be even");
     if (sch->tile_replicas != 0 && sch->tile_replicas != 4 && sch->tile_replicas != 8 &&
         sch->tile_replicas != 16 && sch->tile_replicas != 32 && sch->tile_replicas != 64)
         return fail(PA_EINVAL, "tile_replicas must be 0, 4, 8, 16, 32 or 64");
@@ -412,6 +416,14 @@ static uint64_t threshold_fixed(double beta, int m)
     return (uint64_t)std::floor(std::ldexp(x, 32));
 }
 
+// floor(2^32 (1 - exp(-2 beta))): activation of a satisfied unit bond in the
+// single-replica cluster update (1 - exp as -expm1 in FP64).
+static uint64_t bond_fixed(double beta)
+{
+    const double q = -std::expm1(-2.0 * beta);
+    return (uint64_t)std::floor(std::ldexp(q, 32));
+}
+
 // floor(2^32 * exp(-(dbeta * n))): Boltzmann reweighting factor of a replica
 // n above the population minimum when beta grows by dbeta.
 static uint64_t weight_fixed(double dbeta, long long n)
@@ -568,6 +580,16 @@ static pa_status build_plan(pa_solver *s, const pa_schedule *sch, int R, Plan &p
         total = 1;
         if (tables) p.wtab.push_back(0);
     }
+    if (tables && sch->nl_period > 0 && sch->nl_kind == 1) {
+        p.qtab.assign((size_t)p.K * p.lmax1, 0);
+        for (int k = 0; k < p.K; ++k) {
+            double g = 1.0;
+            for (int l = 0; l < p.lmax1; ++l) {
+                p.qtab[(size_t)k * p.lmax1 + l] = bond_fixed(sch->beta[k] * g);
+                g = g * sch->as_gamma;
+            }
+        }
+    }
     if (tables && p.kind == 1) {
         const int D = s->dmax + 1;
         p.thr32.assign((size_t)p.K * p.lmax1 * D, 0);
@@ -609,7 +631,10 @@ static pa_status build_plan(pa_solver *s, const pa_schedule *sch, int R, Plan &p
     L.col = take(sizeof(int) * s->nnz);
     L.npos = take(sizeof(int) * n);
     L.edges = take(sizeof(uint32_t) * s->edges.size());
-    L.vout = sch->nl_period > 0 ? take(sizeof(uint32_t) * (size_t)(R / 2) * p.nw32) : 0;
+    L.vout = sch->nl_period > 0
+                 ? take(sizeof(uint32_t) * (size_t)(sch->nl_kind == 1 ? R : R / 2) * p.nw32)
+                 : 0;
+    L.qtab = sch->nl_period > 0 && sch->nl_kind == 1 ? take(sizeof(uint64_t) * (size_t)p.K * p.lmax1) : 0;
     L.sched = take(sizeof(int) * n);
     L.level_off = take(sizeof(int) * (p.n_levels + 1));
     L.blocks = take(sizeof(uint32_t) * p.blocks.size());
@@ -697,6 +722,9 @@ extern "C" pa_status pa_run(pa_solver *s, const pa_schedule *sch, int32_t R, uin
                                hipMemcpyHostToDevice, hs));
     else
         HIP_TRY(hipMemcpyAsync(ws + L.stream, P.stream.data(), sizeof(int) * P.stream.size(),
+                               hipMemcpyHostToDevice, hs));
+    if (!P.qtab.empty())
+        HIP_TRY(hipMemcpyAsync(ws + L.qtab, P.qtab.data(), sizeof(uint64_t) * P.qtab.size(),
                                hipMemcpyHostToDevice, hs));
     if (P.kind == 1)
         HIP_TRY(hipMemcpyAsync(ws + L.thr, P.thr32.data(), sizeof(uint32_t) * P.thr32.size(),
@@ -867,6 +895,10 @@ extern "C" pa_status pa_run(pa_solver *s, const pa_schedule *sch, int32_t R, uin
             ic.X = reinterpret_cast<uint64_t *>(ws + Xc);
             ic.E = reinterpret_cast<int *>(ws + Ec);
             ic.vout = reinterpret_cast<uint32_t *>(ws + L.vout);
+            ic.kind = sch->nl_kind;
+            ic.lmax1 = P.lmax1;
+            ic.qtab = reinterpret_cast<const uint64_t *>(ws + L.qtab);
+            ic.as_state = reinterpret_cast<const int *>(ws + L.as_state);
             LAUNCH_TRY(pa::launch_icm(ic, hs));
             e.do_pop = 1;
             e.pop_step = k;

@@ -100,10 +100,14 @@ struct GatherArgs {
 struct IcmArgs {
     GraphDev g;
     int R, G, k, nw32;
+    int kind;                   // 0: pairs (p, p + R/2); 1: single-replica Wolff update
+    int lmax1;                  // noise levels per step in qtab
     uint32_t seed_lo, seed_hi, inst;
     uint64_t *X;
     int *E;
-    uint32_t *vout;             // [R/2][nw32] cluster bitmap of each pair
+    uint32_t *vout;             // [R/2 or R][nw32] cluster bitmap of each pair or replica
+    const uint64_t *qtab;       // kind 1: [K][lmax1] bond thresholds floor(2^32 (1 - e^{-2 beta'}))
+    const int *as_state;        // kind 1: [0] = the noise level of the step's sweeps
 };
 
 struct InitArgs {

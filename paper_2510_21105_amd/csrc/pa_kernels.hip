@@ -21,7 +21,8 @@
 //     as bit words; for degrees above 127 and as an independent check.
 //   epilogue_kernel: best tracking, noise level, reweighting and systematic
 //     resampling of a step (one workgroup).
-//   icm_kernel / icm_apply_kernel: the cluster move on replica pairs.
+//   icm_kernel / icm_apply_kernel: the cluster move on replica pairs;
+//     wolff_kernel (+ icm_apply_kernel): the single-replica cluster update.
 //   gather_kernel: resampling copies for kernel 2 (kernel 1 reads through the
 //     parent list itself).
 #include <hip/hip_runtime.h>
@@ -1495,8 +1496,121 @@ __global__ __launch_bounds__(kIcmThreads) void icm_kernel(IcmArgs a)
     }
 }
 
-// Flip every pair's cluster in both of its replicas: wave (word w, group g)
-// gathers the 64 replicas' bits of nodes 32w..32w+31 with ballots.
+// ---------------------------------------------------------------------------
+// Non-local move, single-replica kind: Wolff's cluster update of every
+// replica (couplings J = -w of either sign). One workgroup per replica: the
+// satisfied bonds (w_ij x_i x_j < 0) are activated with the step's bond
+// threshold, a union-find over the active bonds (LDS parents, as above) gives
+// the components, the seed's component is the cluster; the energy change
+// comes from the edges that cross its boundary. Bond {i < j} of replica r
+// draws word (r & 3) of Philox(key = seed, ctr = (i, j | 5 << 16, k,
+// (r >> 2) | inst << 16)); the seed is floor(u N / 2^32) for the tag-4 draw u.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kIcmThreads) void wolff_kernel(IcmArgs a)
+{
+    // LDS: P = union-find parents [n], A = spins of the replica, V = cluster.
+    extern __shared__ __align__(16) uint32_t lds[];
+    __shared__ long long red_l[16];
+    __shared__ uint32_t root_s;
+    const int tid = threadIdx.x, lane = tid & 63, nt = blockDim.x;
+    const int n = a.g.n, nw = a.nw32;
+    lds_vu32 *P = (lds_vu32 *)lds;
+    uint32_t *A = lds + n, *V = A + nw;
+    const int r = blockIdx.x, br = r & 63;
+    const uint64_t *Xr = a.X + (size_t)(r >> 6) * n;
+    uint32_t *Vout = a.vout + (size_t)r * nw;
+
+    for (int base = 0; base < nw * 32; base += 4 * nt) {
+        uint64_t v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int i = base + u * nt + tid;
+            v[u] = i < n ? Xr[i] : 0ull;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int i = base + u * nt + tid;
+            if (i < n) P[i] = (uint32_t)i;
+            const unsigned long long m = __ballot(i < n && ((v[u] >> br) & 1ull));
+            const int w0 = (base + u * nt + (tid & ~63)) >> 5;
+            if (lane == 0 && w0 < nw) A[w0] = (uint32_t)m;
+            if (lane == 32 && w0 + 1 < nw) A[w0 + 1] = (uint32_t)(m >> 32);
+        }
+    }
+    __syncthreads();
+    const uint64_t q = a.qtab[(size_t)a.k * a.lmax1 + a.as_state[0]];
+    auto bit = [&](const uint32_t *B, uint32_t i) { return (B[i >> 5] >> (i & 31)) & 1u; };
+    // Active bonds: a lane takes 8 edges of the (shuffled) edge list and draws
+    // only for the satisfied ones.
+    const uint32_t *edges = a.g.edges;
+    const int ne = a.g.ne;
+    for (int e0 = tid; e0 < ne; e0 += 8 * nt) {
+        uint32_t ev[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int idx = e0 + u * nt;
+            ev[u] = idx < ne ? edges[idx] : 0u;
+        }
+        uint32_t pend = 0;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const uint32_t i = ev[u] & 0x7FFFu, j = (ev[u] >> 15) & 0x7FFFu;
+            const uint32_t sat = bit(A, i) ^ bit(A, j) ^ ((ev[u] >> 30) & 1u);
+            if (e0 + u * nt < ne && sat) pend |= 1u << u;
+        }
+        while (pend) {
+            const int u = __ffs(pend) - 1;
+            pend &= pend - 1;
+            uint32_t e = ev[0];
+#pragma unroll
+            for (int v = 1; v < 8; ++v) e = u == v ? ev[v] : e;
+            const uint32_t i = e & 0x7FFFu, j = (e >> 15) & 0x7FFFu;
+            const uint32_t d = draw(a.seed_lo, a.seed_hi, a.inst, 5, j, (uint32_t)a.k, i, (uint32_t)r);
+            if ((uint64_t)d < q) uf_unite(P, i, j);
+        }
+    }
+    __syncthreads();
+    if (tid == 0) {
+        const uint32_t d = draw(a.seed_lo, a.seed_hi, a.inst, 4, 0, (uint32_t)a.k, 0u, (uint32_t)r);
+        root_s = uf_find(P, (uint32_t)(((uint64_t)d * (uint64_t)n) >> 32));
+    }
+    __syncthreads();
+    const uint32_t root = root_s;
+    for (int base = 0; base < nw * 32; base += nt) {
+        const int i = base + tid;
+        const bool in = i < n && uf_find(P, (uint32_t)i) == root;
+        const unsigned long long m = __ballot(in);
+        const int w0 = (base + (tid & ~63)) >> 5;
+        if (lane == 0 && w0 < nw) V[w0] = (uint32_t)m;
+        if (lane == 32 && w0 + 1 < nw) V[w0 + 1] = (uint32_t)(m >> 32);
+    }
+    __syncthreads();
+    // Energy change: each edge with one end in the cluster changes sign.
+    long long dE = 0;
+    for (int e0 = tid; e0 < ne; e0 += 8 * nt) {
+        uint32_t ev[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int idx = e0 + u * nt;
+            ev[u] = idx < ne ? edges[idx] : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const uint32_t i = ev[u] & 0x7FFFu, j = (ev[u] >> 15) & 0x7FFFu;
+            if (e0 + u * nt < ne && bit(V, i) != bit(V, j)) {
+                const int s = (int)(bit(A, i) ^ bit(A, j) ^ ((ev[u] >> 30) & 1u));
+                dE += -2 * (1 - 2 * s);
+            }
+        }
+    }
+    dE = block_sum_ll(dE, red_l);
+    for (int w = tid; w < nw; w += nt) Vout[w] = V[w];
+    if (tid == 0) a.E[r] += (int)dE;
+}
+
+// Flip every pair's cluster in both of its replicas (kind 0), or every
+// replica's own cluster (kind 1): wave (word w, group g) gathers the 64
+// replicas' bits of nodes 32w..32w+31 with ballots.
 __global__ __launch_bounds__(256) void icm_apply_kernel(IcmArgs a)
 {
     const int lane = threadIdx.x & 63;
@@ -1504,7 +1618,7 @@ __global__ __launch_bounds__(256) void icm_apply_kernel(IcmArgs a)
     const int g = blockIdx.y;
     if (w >= a.nw32) return;
     const int q = g * 64 + lane, half = a.R / 2;
-    const int pr = q < a.R ? (q < half ? q : q - half) : -1;
+    const int pr = q < a.R ? (a.kind == 1 ? q : (q < half ? q : q - half)) : -1;
     const uint32_t v = pr >= 0 ? a.vout[(size_t)pr * a.nw32 + w] : 0u;
     uint64_t out = 0;
 #pragma unroll
@@ -1661,15 +1775,21 @@ int launch_gather(const GatherArgs &a, void *stream)
 int launch_icm(const IcmArgs &a, void *stream)
 {
     const int lds = icm_lds_bytes(a.g.n, a.nw32);
-    static int configured = 0;
-    if (configured < lds) {
-        if (hipFuncSetAttribute(reinterpret_cast<const void *>(&icm_kernel),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess)
-            return check("hipFuncSetAttribute(icm)");
-        configured = lds;
+    static int configured[2] = {0, 0};
+    const void *fn = a.kind == 1 ? reinterpret_cast<const void *>(&wolff_kernel)
+                                 : reinterpret_cast<const void *>(&icm_kernel);
+    if (configured[a.kind] < lds) {
+        if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess)
+            return check("hipFuncSetAttribute(cluster move)");
+        configured[a.kind] = lds;
     }
-    hipLaunchKernelGGL(icm_kernel, dim3(a.R / 2), dim3(kIcmThreads), lds, (hipStream_t)stream, a);
-    if (int st = check("icm_kernel")) return st;
+    if (a.kind == 1) {
+        hipLaunchKernelGGL(wolff_kernel, dim3(a.R), dim3(kIcmThreads), lds, (hipStream_t)stream, a);
+        if (int st = check("wolff_kernel")) return st;
+    } else {
+        hipLaunchKernelGGL(icm_kernel, dim3(a.R / 2), dim3(kIcmThreads), lds, (hipStream_t)stream, a);
+        if (int st = check("icm_kernel")) return st;
+    }
     hipLaunchKernelGGL(icm_apply_kernel, dim3((a.nw32 + 3) / 4, a.G), dim3(256), 0, (hipStream_t)stream, a);
     return check("icm_apply_kernel");
 }

@@ -51,6 +51,7 @@ class Schedule(ctypes.Structure):
         ("tile_replicas", ctypes.c_int32),
         ("wg_threads", ctypes.c_int32),
         ("record", ctypes.c_int32),
+        ("nl_kind", ctypes.c_int32),
     ]
 
 
@@ -136,6 +137,7 @@ class RunParams:
     tile_replicas: int = 0
     wg_threads: int = 0
     record: int = 0
+    nl_kind: int = 0              # 0: pair cluster moves; 1: single-replica Wolff updates
 
 
 class Solver:
@@ -191,6 +193,7 @@ class Solver:
         sch.tile_replicas = p.tile_replicas
         sch.wg_threads = p.wg_threads
         sch.record = p.record
+        sch.nl_kind = p.nl_kind
         return sch, (betas, order)
 
     def workspace_bytes(self, p: RunParams) -> int:
@@ -331,4 +334,4 @@ def params_from_workload(wl: dict, **over) -> RunParams:
                      as_frozen_inv=d["as_frozen_inv"], as_gamma=d["as_gamma"],
                      nl_period=d["nl_period"], sweep_kernel=d.get("sweep_kernel", 0),
                      tile_replicas=d.get("tile_replicas", 0), wg_threads=d.get("wg_threads", 0),
-                     record=d.get("record", 0))
+                     record=d.get("record", 0), nl_kind=d.get("nl_kind", 0))

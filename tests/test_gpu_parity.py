@@ -433,3 +433,48 @@ def test_gset_file_command_line_solve(pa, tmp_path):
     x = hexcfg.hex_to_config(hp.read_text(), g.n)
     assert np.array_equal(x, ref.best_x)
     assert gset.cut_value(g, x) == out["best_cut"]
+
+
+# ------------------------------------------- single-replica cluster move ----
+
+def _signed(base, seed, name):
+    i, j, _ = base.edges()
+    sgn = np.where(W.splitmix64(seed, i.shape[0]) & np.uint64(1), -1, 1)
+    return W.from_edges(base.n, i, j, sgn, name)
+
+
+@pytest.mark.parametrize("kernel,tile", [(1, 4), (1, 8), (2, 16)])
+def test_single_replica_cluster_moves_signed_graph(pa, kernel, tile):
+    """Wolff updates after every second step on a signed random graph with an
+    odd population (no pairing needed), each sweep kernel."""
+    g = _signed(W.random_graph(600, 2400, 31), 78, "signed600")
+    wl = dict(W.workload("small800"), graph=g, R=99, betas=W.linear_betas(0.1, 3.0, 12),
+              sweeps=3, order=W.natural_order(g.n), nl_period=2, nl_kind=1)
+    _compare(pa, g, wl, dict(sweep_kernel=kernel, tile_replicas=tile))
+
+
+def test_single_replica_cluster_moves_torus_every_step(pa):
+    wl = W.workload("torus100")
+    wl = dict(wl, R=160, betas=wl["betas"][:6], sweeps=2, nl_period=1, nl_kind=1)
+    _compare(pa, wl["graph"], wl)
+
+
+def test_single_replica_cluster_moves_g63_shape_with_noise_levels(pa):
+    """7,000-node G63-shaped graph, ragged R, adaptive levels changing the
+    bond temperature between steps."""
+    wl = W.workload("g63like")
+    wl = dict(wl, R=300, betas=W.linear_betas(4.0, 5.0, 16), sweeps=2, as_stall_steps=1,
+              as_frozen_inv=8, nl_period=2, nl_kind=1)
+    s, ref = _compare(pa, wl["graph"], wl)
+    lv = ref.stats[:, 4]
+    assert np.any(lv[1::2] > 0)      # a cluster-move step ran at a raised level
+
+
+def test_single_replica_cluster_moves_at_high_and_zero_beta(pa):
+    """beta = 0 (no active bond: one spin flips per replica) and a large beta
+    (nearly every satisfied bond active: large clusters)."""
+    g = W.random_graph(500, 3000, 41)
+    for betas in (np.zeros(4), np.full(4, 6.0)):
+        wl = dict(W.workload("small800"), graph=g, R=70, betas=betas, sweeps=1,
+                  order=W.natural_order(g.n), nl_period=1, nl_kind=1)
+        _compare(pa, g, wl)

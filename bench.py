@@ -217,7 +217,7 @@ def main():
     ap.add_argument("--steps", type=int, default=3, help="timed solves")
     ap.add_argument("--warmup", type=int, default=1, help="untimed solves")
     ap.add_argument("--workload", default="g63like",
-                    help="g63like, g63color, torus100, small800, batchN (N uneven "
+                    help="g63like, g63color, g63wolff, torus100, small800, batchN (N uneven "
                          "instances) or serveN (N served requests)")
     ap.add_argument("--streams", type=int, default=8, help="streams for batchN / serveN (1..32)")
     ap.add_argument("--hbm-budget-gb", type=float, default=32.0,

@@ -199,6 +199,8 @@ def workload(name: str) -> dict:
       2000 steps 0.1 -> 5.0, 10 sweeps/step, natural order, adaptive
       stochasticity and non-local moves on.
     * ``g63color``: ``g63like`` swept in greedy-colouring order.
+    * ``g63wolff``: ``g63like`` with single-replica cluster updates in place
+      of the pair cluster moves.
     * ``torus100``: 100 x 100 torus with +-1 weights, seed 4, R=16384,
       1000 steps 0.1 -> 4.0, 5 sweeps/step, checkerboard order.
 
@@ -236,6 +238,12 @@ def workload(name: str) -> dict:
                     desc="random G(N=7000, M=41459) seed 3 (G63 shape), R=4096, K=2000 linear "
                          "beta 0.1->5.0, S=10, greedy-colouring order, adaptive stochasticity + "
                          "cluster moves every 10 steps")
+    if name == "g63wolff":
+        wl = workload("g63like")
+        return dict(wl, nl_kind=1,
+                    desc="random G(N=7000, M=41459) seed 3 (G63 shape), R=4096, K=2000 linear "
+                         "beta 0.1->5.0, S=10, natural order, adaptive stochasticity + "
+                         "single-replica cluster updates every 10 steps")
     if name == "torus100":
         g = torus(100, 4, True, "torus100")
         return dict(base, graph=g, betas=linear_betas(0.1, 4.0, 1000), sweeps=5,

@@ -131,6 +131,8 @@ def test_workspace_grows_with_population():
     (dict(as_enable=1, as_gamma=1.5), pa.PA_EINVAL),
     (dict(as_enable=1, as_frozen_inv=0), pa.PA_EINVAL),
     (dict(record=4), pa.PA_EINVAL),
+    (dict(nl_kind=2, nl_period=2), pa.PA_EINVAL),
+    (dict(nl_kind=-1), pa.PA_EINVAL),
 ])
 def test_schedule_validation(bad, status):
     wl = W.workload("small800")
@@ -138,6 +140,21 @@ def test_schedule_validation(bad, status):
     with pytest.raises(pa.PAError) as e:
         _bytes(s, pa.params_from_workload(wl, **bad))
     assert e.value.status == status
+
+
+def test_single_replica_cluster_moves_take_odd_populations_and_more_scratch():
+    """The pair move needs an even R; the single-replica update does not, and
+    keeps one cluster bitmap per replica instead of per pair plus its bond
+    thresholds."""
+    wl = W.workload("small800")
+    s = pa.Solver(wl["graph"])
+    odd = _bytes(s, pa.params_from_workload(wl, R=7, nl_period=2, nl_kind=1))
+    assert odd > 0
+    pair = _bytes(s, pa.params_from_workload(wl, R=64, nl_period=2, nl_kind=0))
+    single = _bytes(s, pa.params_from_workload(wl, R=64, nl_period=2, nl_kind=1))
+    assert single > pair
+    off = _bytes(s, pa.params_from_workload(wl, R=64, nl_period=0, nl_kind=1))
+    assert off < pair
 
 
 def test_order_must_be_permutation():

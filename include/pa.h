@@ -114,7 +114,7 @@ pa_status pa_workspace_bytes(const pa_solver *s, const pa_schedule *sch, int32_t
 
 /*
  * Run population annealing with R replicas (1 <= R <= 32768; even when
- * nl_period > 0), 64-bit seed and instance id (0..65535). Asynchronous on
+ * nl_period > 0 and nl_kind = 0), 64-bit seed and instance id (0..65535). Asynchronous on
  * `stream` (a hipStream_t; NULL is the default stream) inside `workspace`
  * (device memory of at least pa_workspace_bytes, 256-byte aligned). The
  * workspace holds the results and must stay untouched until the last
@@ -127,8 +127,9 @@ pa_status pa_workspace_bytes(const pa_solver *s, const pa_schedule *sch, int32_t
  *      m = -x_i h_i with h_i = sum_j w_ij x_j; accept iff m <= 0 or
  *      draw(0, s, k, i, r) < floor(2^32 exp(-(beta_k gamma^l * 2m))); the best
  *      configuration is tracked after every sweep.
- *   2. Every nl_period steps: Houdayer cluster move on replica pairs
- *      (p, p + R/2), then a best check.
+ *   2. Every nl_period steps: the non-local move of kind nl_kind (Houdayer
+ *      cluster move on replica pairs, or a Wolff update of every replica),
+ *      then a best check.
  *   3. Noise level update (adaptive stochasticity).
  *   4. If k < K-1: weights floor(2^32 exp(-((beta_{k+1}-beta_k)(E_r-E_min)))),
  *      systematic resampling back to R replicas.
@@ -137,6 +138,56 @@ pa_status pa_workspace_bytes(const pa_solver *s, const pa_schedule *sch, int32_t
  */
 pa_status pa_run(pa_solver *s, const pa_schedule *sch, int32_t R, uint64_t seed,
                  uint32_t instance, void *workspace, size_t workspace_bytes, void *stream);
+
+/*
+ * Steps [k_begin, k_end) of the same run as pa_run (0 <= k_begin <= k_end <=
+ * K), for schedules too long for one call and for checkpoints. k_begin = 0
+ * starts the run (initial population) in `workspace`; k_begin > 0 continues
+ * the run that this solver holds in the same workspace, which must have
+ * reached exactly step k_begin with the same graph, schedule (launch-shape
+ * fields aside), R, seed and instance, either through earlier pa_run_steps
+ * calls or pa_checkpoint_load. Splitting a run into ranges gives results
+ * identical to one pa_run. The best and statistics calls report the steps
+ * run so far; pa_get_population returns the population that the next step
+ * starts from (after resampling). Errors as pa_run, plus PA_EINVAL for a bad
+ * range, PA_ESTATE when there is no such run to continue (wrong step, other
+ * schedule, R, seed or instance) and PA_EWORKSPACE for another workspace.
+ * A stream other than the previous call's is ordered after it by a host
+ * synchronisation.
+ */
+pa_status pa_run_steps(pa_solver *s, const pa_schedule *sch, int32_t R, uint64_t seed,
+                       uint32_t instance, int32_t k_begin, int32_t k_end, void *workspace,
+                       size_t workspace_bytes, void *stream);
+
+/*
+ * Checkpoints (runs of many hours, paper section 3, need them): the complete
+ * state between two steps, as a host byte blob. Counter-based draws make a
+ * restored run continue exactly as the uninterrupted one.
+ *   pa_checkpoint_bytes  size of the blob for the solver's current run.
+ *   pa_checkpoint_save   writes it into caller memory `out` (at least that
+ *                        many bytes); synchronises the run's stream. The blob
+ *                        holds the population (with the pending resampling
+ *                        applied), energies, noise-level state, best
+ *                        configuration and its record, the per-step
+ *                        statistics of the steps run, and the recorded copy
+ *                        counts / initial population, plus a header with the
+ *                        next step and a hash of graph, schedule (launch-shape
+ *                        fields aside), R, seed and instance.
+ *   pa_checkpoint_load   prepares `workspace` for that run (as pa_run would)
+ *                        and restores the state from `in`; synchronises
+ *                        `stream`. Continue with pa_run_steps(k, K) where k
+ *                        is the saved next step. The launch shape may differ
+ *                        from the saved run's.
+ * Errors: PA_EINVAL for null pointers, a short buffer, or a blob of another
+ * library version, graph, schedule, R, seed or instance (checked before any
+ * device call); PA_ESTATE when the solver has no run to save; as pa_run for
+ * the workspace and device.
+ */
+pa_status pa_checkpoint_bytes(const pa_solver *s, size_t *bytes);
+pa_status pa_checkpoint_save(pa_solver *s, void *out, size_t bytes);
+pa_status pa_checkpoint_load(pa_solver *s, const pa_schedule *sch, int32_t R, uint64_t seed,
+                             uint32_t instance, const void *in, size_t bytes, void *workspace,
+                             size_t workspace_bytes, void *stream);
 
 /* One run of a batch: the arguments of pa_run. */
 typedef struct {

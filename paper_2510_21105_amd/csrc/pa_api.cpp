@@ -97,10 +97,23 @@ struct pa_solver {
     hipStream_t stream = nullptr;
     size_t final_x = 0, final_E = 0;
     int device = 0;
+    // State carried from one pa_run_steps call to the next.
+    struct RunCtx {
+        bool valid = false;
+        uint64_t key = 0;               // run_key of the run in the workspace
+        int next_step = 0;              // first step not run yet
+        bool parents_pending = false;   // kernel 1: the next population is Xc read through the parents
+        size_t Xc = 0, Xn = 0, Ec = 0, En = 0;
+        uint32_t seed_lo = 0, seed_hi = 0, instance = 0;
+        int nl_period = 0, nl_kind = 0;
+        pa::GraphDev gd{};
+        pa::SweepArgs sa{};
+        pa::EpiArgs ea{};
+    } rc;
     // timing
     int timing = 0;
     std::vector<hipEvent_t> ev;
-    int ev_used = 0;
+    int ev_first = 0, ev_used = 0;
 };
 
 extern "C" const char *pa_last_error(void) { return g_error; }
@@ -677,8 +690,40 @@ extern "C" pa_status pa_workspace_bytes(const pa_solver *s, const pa_schedule *s
 
 // ------------------------------------------------------------------ run ----
 
-extern "C" pa_status pa_run(pa_solver *s, const pa_schedule *sch, int32_t R, uint64_t seed,
-                            uint32_t instance, void *workspace, size_t workspace_bytes, void *stream)
+// Hash (FNV-1a, 64 bit) of everything a run's results depend on: the graph,
+// the schedule without its launch-shape fields, R, seed and instance.
+static uint64_t fnv(uint64_t h, const void *p, size_t n)
+{
+    const unsigned char *b = static_cast<const unsigned char *>(p);
+    for (size_t q = 0; q < n; ++q) h = (h ^ b[q]) * 0x100000001B3ull;
+    return h;
+}
+
+static uint64_t run_key(const pa_solver *s, const pa_schedule *sch, int32_t R, uint64_t seed,
+                        uint32_t instance)
+{
+    uint64_t h = 0xCBF29CE484222325ull;
+    h = fnv(h, &s->n, sizeof s->n);
+    h = fnv(h, s->row_ptr.data(), sizeof(int) * s->row_ptr.size());
+    h = fnv(h, s->col.data(), sizeof(int) * s->col.size());
+    h = fnv(h, s->npos.data(), sizeof(int) * s->npos.size());
+    const int32_t ints[] = {sch->n_steps, sch->sweeps_per_step, sch->as_enable, sch->as_stall_steps,
+                            sch->as_max_level, sch->as_frozen_inv, sch->nl_period, sch->nl_kind,
+                            sch->record, R, (int32_t)instance};
+    h = fnv(h, ints, sizeof ints);
+    h = fnv(h, &sch->as_gamma, sizeof sch->as_gamma);
+    h = fnv(h, &seed, sizeof seed);
+    h = fnv(h, sch->beta, sizeof(double) * (size_t)sch->n_steps);
+    if (sch->order) h = fnv(h, sch->order, sizeof(int32_t) * (size_t)s->n);
+    return h;
+}
+
+// Plan the run, upload the graph and tables into the workspace and set up the
+// launch arguments. A fresh run also clears the state, draws the initial
+// population and takes its best; a restored one leaves the state to the caller.
+static pa_status start_run(pa_solver *s, const pa_schedule *sch, int32_t R, uint64_t seed,
+                           uint32_t instance, void *workspace, size_t workspace_bytes, void *stream,
+                           bool fresh)
 {
     g_error[0] = 0;
     pa_status st = check_schedule(s, sch, R);
@@ -737,11 +782,14 @@ extern "C" pa_status pa_run(pa_solver *s, const pa_schedule *sch, int32_t R, uin
     HIP_TRY(hipMemcpyAsync(ws + L.wtab_len, P.wtab_len.data(), sizeof(int) * P.K, hipMemcpyHostToDevice, hs));
 
     auto U64 = [&](size_t off) { return reinterpret_cast<unsigned long long *>(ws + off); };
-    LAUNCH_TRY(pa::launch_fill_u64(U64(L.counters), 0ull, 2, hs));
-    LAUNCH_TRY(pa::launch_fill_u64(U64(L.as_state), 0ull, 2, hs));
-    LAUNCH_TRY(pa::launch_fill_u64(U64(L.best), 0ull, 4, hs));
-    LAUNCH_TRY(pa::launch_fill_u64(U64(L.stats), 0ull, (long long)P.K * pa::kStatFields, hs));
-    if (P.record & 1) LAUNCH_TRY(pa::launch_fill_u64(U64(L.counts), 0ull, ((long long)P.K * R + 1) / 2, hs));
+    if (fresh) {
+        LAUNCH_TRY(pa::launch_fill_u64(U64(L.counters), 0ull, 2, hs));
+        LAUNCH_TRY(pa::launch_fill_u64(U64(L.as_state), 0ull, 2, hs));
+        LAUNCH_TRY(pa::launch_fill_u64(U64(L.best), 0ull, 4, hs));
+        LAUNCH_TRY(pa::launch_fill_u64(U64(L.stats), 0ull, (long long)P.K * pa::kStatFields, hs));
+        if (P.record & 1)
+            LAUNCH_TRY(pa::launch_fill_u64(U64(L.counts), 0ull, ((long long)P.K * R + 1) / 2, hs));
+    }
 
     pa::GraphDev gd;
     gd.n = n;
@@ -763,11 +811,13 @@ extern "C" pa_status pa_run(pa_solver *s, const pa_schedule *sch, int32_t R, uin
     ia.inst = instance;
     ia.X = reinterpret_cast<uint64_t *>(ws + Xc);
     ia.E = reinterpret_cast<int *>(ws + Ec);
-    LAUNCH_TRY(pa::launch_init(ia, hs));
-    LAUNCH_TRY(pa::launch_energy(ia, hs));
-    if (P.record & 2)
-        HIP_TRY(hipMemcpyAsync(ws + L.xinit, ws + Xc, sizeof(uint64_t) * (size_t)P.G * n,
-                               hipMemcpyDeviceToDevice, hs));
+    if (fresh) {
+        LAUNCH_TRY(pa::launch_init(ia, hs));
+        LAUNCH_TRY(pa::launch_energy(ia, hs));
+        if (P.record & 2)
+            HIP_TRY(hipMemcpyAsync(ws + L.xinit, ws + Xc, sizeof(uint64_t) * (size_t)P.G * n,
+                                   hipMemcpyDeviceToDevice, hs));
+    }
 
     pa::EpiArgs ea{};
     ea.R = R;
@@ -798,7 +848,7 @@ extern "C" pa_status pa_run(pa_solver *s, const pa_schedule *sch, int32_t R, uin
     ea.counts_rec = (P.record & 1) ? reinterpret_cast<int *>(ws + L.counts) : nullptr;
 
     // Best of the initial population.
-    {
+    if (fresh) {
         pa::EpiArgs e0 = ea;
         e0.k = 0;
         e0.do_pop = 1;
@@ -849,9 +899,44 @@ extern "C" pa_status pa_run(pa_solver *s, const pa_schedule *sch, int32_t R, uin
             s->ev.push_back(e);
         }
     }
+    s->ev_first = 0;
     s->ev_used = 0;
 
-    for (int k = 0; k < P.K; ++k) {
+    pa_solver::RunCtx &c = s->rc;
+    c.valid = true;
+    c.key = run_key(s, sch, R, seed, instance);
+    c.next_step = 0;
+    c.parents_pending = false;
+    c.Xc = Xc; c.Xn = Xn; c.Ec = Ec; c.En = En;
+    c.seed_lo = seed_lo; c.seed_hi = seed_hi; c.instance = instance;
+    c.nl_period = sch->nl_period;
+    c.nl_kind = sch->nl_kind;
+    c.gd = gd;
+    c.sa = sa;
+    c.ea = ea;
+    s->final_x = Xc;
+    s->final_E = Ec;
+    return PA_OK;
+}
+
+// Steps [k0, k1) of the run prepared by start_run (and any steps before k0).
+static pa_status run_range(pa_solver *s, int k0, int k1)
+{
+    Plan &P = s->plan;
+    const Layout &L = P.L;
+    pa_solver::RunCtx &c = s->rc;
+    unsigned char *ws = s->ws;
+    hipStream_t hs = s->stream;
+    const int n = s->n, R = P.R;
+    const uint32_t seed_lo = c.seed_lo, seed_hi = c.seed_hi, instance = c.instance;
+    const pa::GraphDev gd = c.gd;
+    const pa::EpiArgs ea = c.ea;
+    pa::SweepArgs sa = c.sa;
+    size_t Xc = c.Xc, Xn = c.Xn, Ec = c.Ec, En = c.En;
+    if (s->ev_used < k0) s->ev_first = k0;     // steps before k0 ran in another call or process
+    c.valid = false;                           // until every step of the range is enqueued
+
+    for (int k = k0; k < k1; ++k) {
         sa.k = k;
         if (s->timing) HIP_TRY(hipEventRecord(s->ev[2 * k], hs));
         if (P.kind == 1) {
@@ -861,10 +946,11 @@ extern "C" pa_status pa_run(pa_solver *s, const pa_schedule *sch, int32_t R, uin
             sa.Ein = reinterpret_cast<const int *>(ws + Ec);
             sa.X = reinterpret_cast<uint64_t *>(ws + Xn);
             sa.E = reinterpret_cast<int *>(ws + En);
-            sa.parent = k > 0 ? reinterpret_cast<const int *>(ws + L.parent) : nullptr;
+            sa.parent = c.parents_pending ? reinterpret_cast<const int *>(ws + L.parent) : nullptr;
             LAUNCH_TRY(pa::launch_sweep_bytes(P.W, P.sgn, P.threads, P.nblk, sa, hs));
             std::swap(Xc, Xn);
             std::swap(Ec, En);
+            c.parents_pending = false;
         } else {
             sa.X = reinterpret_cast<uint64_t *>(ws + Xc);
             sa.E = reinterpret_cast<int *>(ws + Ec);
@@ -878,7 +964,7 @@ extern "C" pa_status pa_run(pa_solver *s, const pa_schedule *sch, int32_t R, uin
         e.k = k;
         e.E = reinterpret_cast<const int *>(ws + Ec);
         e.X = reinterpret_cast<const uint64_t *>(ws + Xc);
-        const bool nl = sch->nl_period > 0 && (k + 1) % sch->nl_period == 0;
+        const bool nl = c.nl_period > 0 && (k + 1) % c.nl_period == 0;
         if (nl) {
             pa::EpiArgs e1 = e;
             e1.do_cand = 1;
@@ -895,7 +981,7 @@ extern "C" pa_status pa_run(pa_solver *s, const pa_schedule *sch, int32_t R, uin
             ic.X = reinterpret_cast<uint64_t *>(ws + Xc);
             ic.E = reinterpret_cast<int *>(ws + Ec);
             ic.vout = reinterpret_cast<uint32_t *>(ws + L.vout);
-            ic.kind = sch->nl_kind;
+            ic.kind = c.nl_kind;
             ic.lmax1 = P.lmax1;
             ic.qtab = reinterpret_cast<const uint64_t *>(ws + L.qtab);
             ic.as_state = reinterpret_cast<const int *>(ws + L.as_state);
@@ -909,6 +995,7 @@ extern "C" pa_status pa_run(pa_solver *s, const pa_schedule *sch, int32_t R, uin
             e.do_rest = 1;
         }
         LAUNCH_TRY(pa::launch_epilogue(e, hs));
+        if (P.kind == 1 && k + 1 < P.K) c.parents_pending = true;
         if (P.kind == 2 && k + 1 < P.K) {
             pa::GatherArgs ga;
             ga.n = n;
@@ -924,10 +1011,53 @@ extern "C" pa_status pa_run(pa_solver *s, const pa_schedule *sch, int32_t R, uin
             std::swap(Ec, En);
         }
     }
+    c.Xc = Xc; c.Xn = Xn; c.Ec = Ec; c.En = En;
+    c.next_step = k1;
+    c.valid = true;
     s->final_x = Xc;
     s->final_E = Ec;
     s->has_run = true;
     return PA_OK;
+}
+
+extern "C" pa_status pa_run_steps(pa_solver *s, const pa_schedule *sch, int32_t R, uint64_t seed,
+                                  uint32_t instance, int32_t k_begin, int32_t k_end, void *workspace,
+                                  size_t workspace_bytes, void *stream)
+{
+    g_error[0] = 0;
+    if (!s) return fail(PA_EINVAL, "null solver");
+    pa_status st = check_schedule(s, sch, R);
+    if (st != PA_OK) return st;
+    if (instance > 65535) return fail(PA_ERANGE, "instance=%u outside [0, 65535]", instance);
+    if (k_begin < 0 || k_end < k_begin || k_end > sch->n_steps)
+        return fail(PA_EINVAL, "steps [%d, %d) outside the schedule's [0, %d]", k_begin, k_end, sch->n_steps);
+    if (k_begin == 0) {
+        st = start_run(s, sch, R, seed, instance, workspace, workspace_bytes, stream, true);
+        if (st != PA_OK) return st;
+    } else {
+        const pa_solver::RunCtx &c = s->rc;
+        if (!c.valid || c.key != run_key(s, sch, R, seed, instance))
+            return fail(PA_ESTATE, "no run of this schedule, R, seed and instance to continue");
+        if (c.next_step != k_begin)
+            return fail(PA_ESTATE, "the run in the workspace continues at step %d, not %d", c.next_step, k_begin);
+        if (workspace != s->ws) return fail(PA_EWORKSPACE, "a run continues in its own workspace");
+        if (stream != (void *)s->stream) {
+            // The previous steps were enqueued on another stream: order after them.
+            HIP_TRY(hipStreamSynchronize(s->stream));
+            s->stream = static_cast<hipStream_t>(stream);
+        }
+    }
+    return run_range(s, k_begin, k_end);
+}
+
+extern "C" pa_status pa_run(pa_solver *s, const pa_schedule *sch, int32_t R, uint64_t seed,
+                            uint32_t instance, void *workspace, size_t workspace_bytes, void *stream)
+{
+    if (!sch) {
+        g_error[0] = 0;
+        return fail(PA_EINVAL, "null schedule");
+    }
+    return pa_run_steps(s, sch, R, seed, instance, 0, sch->n_steps, workspace, workspace_bytes, stream);
 }
 
 // -------------------------------------------------------------- results ----
@@ -1081,15 +1211,33 @@ extern "C" pa_status pa_get_population(pa_solver *s, int8_t *x, int32_t *E)
 {
     if (!s || !s->has_run) return fail(PA_ESTATE, "no completed pa_run on this solver");
     const Plan &P = s->plan;
+    // After a range that stopped before the last step, kernel 1 still holds
+    // the population of the next step as the current buffer read through the
+    // resampling parents: apply them here.
+    std::vector<int> parent;
+    if (s->rc.parents_pending) {
+        parent.resize(P.R);
+        pa_status st = fetch(s, parent.data(), P.L.parent, sizeof(int) * P.R);
+        if (st != PA_OK) return st;
+    }
     if (x) {
         std::vector<uint64_t> X((size_t)P.G * s->n);
         pa_status st = fetch(s, X.data(), s->final_x, sizeof(uint64_t) * X.size());
         if (st != PA_OK) return st;
-        unpack_population(X, s->n, P.R, x);
+        if (parent.empty()) {
+            unpack_population(X, s->n, P.R, x);
+        } else {
+            std::vector<int8_t> all((size_t)P.R * s->n);
+            unpack_population(X, s->n, P.R, all.data());
+            for (int r = 0; r < P.R; ++r)
+                std::memcpy(x + (size_t)r * s->n, all.data() + (size_t)parent[r] * s->n, (size_t)s->n);
+        }
     }
     if (E) {
-        pa_status st = fetch(s, E, s->final_E, sizeof(int) * P.R);
+        std::vector<int> Eall(P.R);
+        pa_status st = fetch(s, Eall.data(), s->final_E, sizeof(int) * P.R);
         if (st != PA_OK) return st;
+        for (int r = 0; r < P.R; ++r) E[r] = Eall[parent.empty() ? r : parent[r]];
     }
     return PA_OK;
 }
@@ -1139,6 +1287,148 @@ extern "C" pa_status pa_get_launch_info(pa_solver *s, int64_t out[8])
     return PA_OK;
 }
 
+// ------------------------------------------------------------ checkpoint ----
+
+namespace {
+struct CkptHeader {
+    char magic[8];
+    uint64_t key;
+    uint64_t bytes;
+    int32_t n, R, K, G, nw32, next_step, record, version;
+};
+constexpr char kCkptMagic[8] = {'P', 'A', 'C', 'K', 'P', 'T', '0', '1'};
+
+// Device regions of the state between steps, in blob order.
+struct CkptPart {
+    size_t off, bytes;
+};
+
+std::vector<CkptPart> ckpt_parts(const pa_solver *s)
+{
+    const Plan &P = s->plan;
+    const Layout &L = P.L;
+    std::vector<CkptPart> v;
+    v.push_back({s->rc.Xc, sizeof(uint64_t) * (size_t)P.G * s->n});
+    v.push_back({s->rc.Ec, sizeof(int) * (size_t)P.R});
+    v.push_back({L.as_state, sizeof(int) * 4});
+    v.push_back({L.best, sizeof(int) * 8});
+    v.push_back({L.counters, sizeof(uint64_t) * 2});
+    v.push_back({L.best_x, sizeof(uint32_t) * (size_t)P.nw32});
+    v.push_back({L.stats, sizeof(long long) * (size_t)P.K * pa::kStatFields});
+    if (P.record & 1) v.push_back({L.counts, sizeof(int) * (size_t)P.K * P.R});
+    if (P.record & 2) v.push_back({L.xinit, sizeof(uint64_t) * (size_t)P.G * s->n});
+    return v;
+}
+
+size_t ckpt_bytes(const std::vector<CkptPart> &parts)
+{
+    size_t b = sizeof(CkptHeader);
+    for (const CkptPart &q : parts) b += (q.bytes + 7) & ~size_t(7);
+    return b;
+}
+}  // namespace
+
+extern "C" pa_status pa_checkpoint_bytes(const pa_solver *s, size_t *bytes)
+{
+    g_error[0] = 0;
+    if (!s || !bytes) return fail(PA_EINVAL, "pa_checkpoint_bytes: null argument");
+    if (!s->rc.valid || !s->has_run) return fail(PA_ESTATE, "no run on this solver to checkpoint");
+    *bytes = ckpt_bytes(ckpt_parts(s));
+    return PA_OK;
+}
+
+extern "C" pa_status pa_checkpoint_save(pa_solver *s, void *out, size_t bytes)
+{
+    g_error[0] = 0;
+    if (!s || !out) return fail(PA_EINVAL, "pa_checkpoint_save: null argument");
+    if (!s->rc.valid || !s->has_run) return fail(PA_ESTATE, "no run on this solver to checkpoint");
+    pa_solver::RunCtx &c = s->rc;
+    const Plan &P = s->plan;
+    if (bytes < ckpt_bytes(ckpt_parts(s)))
+        return fail(PA_EINVAL, "checkpoint buffer of %zu bytes < %zu", bytes, ckpt_bytes(ckpt_parts(s)));
+    HIP_TRY(hipSetDevice(s->device));
+    if (c.parents_pending) {
+        // Store the population itself: copy it through the parent list into
+        // the other buffer, which becomes the current one.
+        pa::GatherArgs ga;
+        ga.n = s->n;
+        ga.R = P.R;
+        ga.G = P.G;
+        ga.parent = reinterpret_cast<const int *>(s->ws + P.L.parent);
+        ga.Xin = reinterpret_cast<const uint64_t *>(s->ws + c.Xc);
+        ga.Xout = reinterpret_cast<uint64_t *>(s->ws + c.Xn);
+        ga.Ein = reinterpret_cast<const int *>(s->ws + c.Ec);
+        ga.Eout = reinterpret_cast<int *>(s->ws + c.En);
+        LAUNCH_TRY(pa::launch_gather(ga, s->stream));
+        std::swap(c.Xc, c.Xn);
+        std::swap(c.Ec, c.En);
+        c.parents_pending = false;
+        s->final_x = c.Xc;
+        s->final_E = c.Ec;
+    }
+    const std::vector<CkptPart> parts = ckpt_parts(s);
+    unsigned char *o = static_cast<unsigned char *>(out);
+    CkptHeader h;
+    std::memcpy(h.magic, kCkptMagic, 8);
+    h.key = c.key;
+    h.bytes = ckpt_bytes(parts);
+    h.n = s->n;
+    h.R = P.R;
+    h.K = P.K;
+    h.G = P.G;
+    h.nw32 = P.nw32;
+    h.next_step = c.next_step;
+    h.record = P.record;
+    h.version = 1;
+    std::memcpy(o, &h, sizeof h);
+    size_t at = sizeof h;
+    for (const CkptPart &q : parts) {
+        HIP_TRY(hipMemcpyAsync(o + at, s->ws + q.off, q.bytes, hipMemcpyDeviceToHost, s->stream));
+        at += (q.bytes + 7) & ~size_t(7);
+    }
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    return PA_OK;
+}
+
+extern "C" pa_status pa_checkpoint_load(pa_solver *s, const pa_schedule *sch, int32_t R, uint64_t seed,
+                                        uint32_t instance, const void *in, size_t bytes, void *workspace,
+                                        size_t workspace_bytes, void *stream)
+{
+    g_error[0] = 0;
+    if (!s || !sch || !in) return fail(PA_EINVAL, "pa_checkpoint_load: null argument");
+    pa_status st = check_schedule(s, sch, R);
+    if (st != PA_OK) return st;
+    if (instance > 65535) return fail(PA_ERANGE, "instance=%u outside [0, 65535]", instance);
+    CkptHeader h;
+    if (bytes < sizeof h) return fail(PA_EINVAL, "checkpoint of %zu bytes is too short", bytes);
+    std::memcpy(&h, in, sizeof h);
+    if (std::memcmp(h.magic, kCkptMagic, 8) != 0 || h.version != 1)
+        return fail(PA_EINVAL, "not a checkpoint of this library");
+    if (h.bytes > bytes) return fail(PA_EINVAL, "checkpoint truncated: %zu of %llu bytes", bytes,
+                                     (unsigned long long)h.bytes);
+    if (h.key != run_key(s, sch, R, seed, instance) || h.n != s->n || h.R != R || h.K != sch->n_steps ||
+        h.record != sch->record)
+        return fail(PA_EINVAL, "checkpoint belongs to another graph, schedule, population, seed or instance");
+    if (h.next_step < 0 || h.next_step > h.K) return fail(PA_EINVAL, "checkpoint step %d outside the schedule", h.next_step);
+    st = start_run(s, sch, R, seed, instance, workspace, workspace_bytes, stream, false);
+    if (st != PA_OK) return st;
+    const std::vector<CkptPart> parts = ckpt_parts(s);
+    if (ckpt_bytes(parts) != h.bytes || h.G != s->plan.G || h.nw32 != s->plan.nw32)
+        return fail(PA_EINVAL, "checkpoint layout does not match this run");
+    const unsigned char *p = static_cast<const unsigned char *>(in);
+    size_t at = sizeof h;
+    for (const CkptPart &q : parts) {
+        HIP_TRY(hipMemcpyAsync(s->ws + q.off, p + at, q.bytes, hipMemcpyHostToDevice, s->stream));
+        at += (q.bytes + 7) & ~size_t(7);
+    }
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    s->rc.next_step = h.next_step;
+    s->rc.parents_pending = false;
+    s->ev_first = s->ev_used = h.next_step;
+    s->has_run = true;
+    return PA_OK;
+}
+
 extern "C" pa_status pa_set_timing(pa_solver *s, int32_t on)
 {
     if (!s) return fail(PA_EINVAL, "null solver");
@@ -1152,12 +1442,12 @@ extern "C" pa_status pa_get_sweep_time(pa_solver *s, double *ms, int64_t *launch
     if (!s->timing) return fail(PA_ESTATE, "timing mode was off during the run");
     HIP_TRY(hipStreamSynchronize(s->stream));
     double tot = 0.0;
-    for (int k = 0; k < s->ev_used; ++k) {
+    for (int k = s->ev_first; k < s->ev_used; ++k) {
         float t = 0.f;
         HIP_TRY(hipEventElapsedTime(&t, s->ev[2 * k], s->ev[2 * k + 1]));
         tot += t;
     }
     if (ms) *ms = tot;
-    if (launches) *launches = s->ev_used;
+    if (launches) *launches = s->ev_used > s->ev_first ? s->ev_used - s->ev_first : 0;
     return PA_OK;
 }

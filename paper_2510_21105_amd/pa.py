@@ -26,7 +26,8 @@ _STATUS = {PA_EINVAL: "PA_EINVAL", PA_ERANGE: "PA_ERANGE", PA_EWORKSPACE: "PA_EW
 EXPORTS = ("pa_last_error", "pa_create", "pa_destroy", "pa_graph_info", "pa_workspace_bytes",
            "pa_run", "pa_run_batch", "pa_build_tables", "pa_best_cut", "pa_best_info", "pa_best_config", "pa_best_config_hex",
            "pa_get_population", "pa_get_initial_population", "pa_get_step_stats",
-           "pa_get_counts", "pa_get_launch_info", "pa_set_timing", "pa_get_sweep_time")
+           "pa_get_counts", "pa_get_launch_info", "pa_set_timing", "pa_get_sweep_time",
+           "pa_run_steps", "pa_checkpoint_bytes", "pa_checkpoint_save", "pa_checkpoint_load")
 
 
 class PAError(RuntimeError):
@@ -101,6 +102,11 @@ def lib():
             "pa_get_launch_info": [P, P],
             "pa_set_timing": [P, i32],
             "pa_get_sweep_time": [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)],
+            "pa_run_steps": [P, ctypes.POINTER(Schedule), i32, u64, u32, i32, i32, P, ctypes.c_size_t, P],
+            "pa_checkpoint_bytes": [P, ctypes.POINTER(ctypes.c_size_t)],
+            "pa_checkpoint_save": [P, P, ctypes.c_size_t],
+            "pa_checkpoint_load": [P, ctypes.POINTER(Schedule), i32, u64, u32, P, ctypes.c_size_t, P,
+                                   ctypes.c_size_t, P],
         }
         for name, args in sigs.items():
             f = getattr(L, name)
@@ -231,6 +237,39 @@ class Solver:
         self._started(p, sch, keep, workspace)
         return self
 
+    def run_steps(self, p: RunParams, k_begin: int, k_end: int, stream=None, workspace=None):
+        """Enqueue steps [k_begin, k_end) of the run (k_begin > 0 continues the
+        run this solver holds, in the same workspace)."""
+        import torch
+        if k_begin > 0 and workspace is None and self._keep is not None:
+            workspace = self._keep[1]
+        sch, keep, workspace, aligned, avail = self._prepare(p, workspace)
+        st = torch.cuda.current_stream() if stream is None else stream
+        _check(lib().pa_run_steps(self._h, ctypes.byref(sch), p.R, p.seed, p.inst, k_begin, k_end,
+                                  ctypes.c_void_p(aligned), avail, ctypes.c_void_p(st.cuda_stream)))
+        self._started(p, sch, keep, workspace)
+        return self
+
+    def checkpoint(self) -> bytes:
+        """The run's state between steps as bytes (synchronises its stream)."""
+        n = ctypes.c_size_t()
+        _check(lib().pa_checkpoint_bytes(self._h, ctypes.byref(n)))
+        buf = ctypes.create_string_buffer(n.value)
+        _check(lib().pa_checkpoint_save(self._h, buf, n.value))
+        return buf.raw
+
+    def restore(self, p: RunParams, blob: bytes, stream=None, workspace=None):
+        """Prepare a run of ``p`` and load the state saved by ``checkpoint``;
+        continue with ``run_steps(p, k, K)`` (k = ``next_step(blob)``)."""
+        import torch
+        sch, keep, workspace, aligned, avail = self._prepare(p, workspace)
+        st = torch.cuda.current_stream() if stream is None else stream
+        _check(lib().pa_checkpoint_load(self._h, ctypes.byref(sch), p.R, p.seed, p.inst, blob,
+                                        len(blob), ctypes.c_void_p(aligned), avail,
+                                        ctypes.c_void_p(st.cuda_stream)))
+        self._started(p, sch, keep, workspace)
+        return self
+
     # ---- results (each synchronises the run's stream) ----
     def best_cut(self) -> int:
         cut = ctypes.c_int64()
@@ -335,3 +374,12 @@ def params_from_workload(wl: dict, **over) -> RunParams:
                      nl_period=d["nl_period"], sweep_kernel=d.get("sweep_kernel", 0),
                      tile_replicas=d.get("tile_replicas", 0), wg_threads=d.get("wg_threads", 0),
                      record=d.get("record", 0), nl_kind=d.get("nl_kind", 0))
+
+
+def next_step(blob: bytes) -> int:
+    """The step a checkpoint continues at (its header: magic, key, size, then
+    n, R, K, G, words, next step, record, version as int32)."""
+    import struct
+    if len(blob) < 56 or blob[:8] != b"PACKPT01":
+        raise ValueError("not a checkpoint of this library")
+    return struct.unpack_from("<8i", blob, 24)[5]

@@ -282,3 +282,40 @@ def test_build_tables_rejects_bad_input():
     with pytest.raises(pa.PAError) as e:
         pa.build_tables(pa.params_from_workload(wl), 5000, 10)
     assert e.value.status == pa.PA_ERANGE
+
+
+# ------------------------------------------------------------ checkpoints ----
+
+def _sched_args(s, p):
+    sch, keep = s._schedule(p)
+    return sch, keep
+
+
+def test_resume_and_checkpoint_errors_without_device_calls():
+    """Continuing, saving or loading without a matching run fails before any
+    device call."""
+    wl = W.workload("small800")
+    s = pa.Solver(wl["graph"])
+    p = pa.params_from_workload(wl, R=64)
+    sch, keep = _sched_args(s, p)
+    L = pa.lib()
+    n = ctypes.c_size_t()
+    assert L.pa_checkpoint_bytes(s._h, ctypes.byref(n)) == pa.PA_ESTATE
+    buf = ctypes.create_string_buffer(64)
+    assert L.pa_checkpoint_save(s._h, buf, 64) == pa.PA_ESTATE
+    ws = ctypes.c_void_p(256)     # never dereferenced: every call below fails first
+    K = len(p.betas)
+    assert L.pa_run_steps(s._h, ctypes.byref(sch), p.R, p.seed, p.inst, 3, K, ws, 1 << 30, None) == pa.PA_ESTATE
+    assert L.pa_run_steps(s._h, ctypes.byref(sch), p.R, p.seed, p.inst, 0, K + 1, ws, 1 << 30, None) == pa.PA_EINVAL
+    assert L.pa_run_steps(s._h, ctypes.byref(sch), p.R, p.seed, p.inst, 5, 4, ws, 1 << 30, None) == pa.PA_EINVAL
+    for blob in (b"", b"x" * 100, b"PACKPT01" + bytes(200)):
+        assert L.pa_checkpoint_load(s._h, ctypes.byref(sch), p.R, p.seed, p.inst, blob, len(blob),
+                                    ws, 1 << 30, None) == pa.PA_EINVAL
+    with pytest.raises(ValueError):
+        pa.next_step(b"x" * 100)
+
+
+def test_checkpoint_header_is_read_back():
+    import struct
+    hdr = b"PACKPT01" + struct.pack("<QQ8i", 1, 56, 800, 64, 50, 1, 25, 17, 0, 1)
+    assert pa.next_step(hdr) == 17

@@ -478,3 +478,80 @@ def test_single_replica_cluster_moves_at_high_and_zero_beta(pa):
         wl = dict(W.workload("small800"), graph=g, R=70, betas=betas, sweeps=1,
                   order=W.natural_order(g.n), nl_period=1, nl_kind=1)
         _compare(pa, g, wl)
+
+
+# ------------------------------------------------- resumable runs, checkpoints ----
+
+def _results(s):
+    x, E = s.population()
+    info = s.best_info()
+    return dict(stats=s.step_stats(), x=x, E=E, best=(info["E"], info["step"], info["sweep"],
+                info["replica"]), bx=s.best_config())
+
+
+def _assert_same(a, b):
+    assert np.array_equal(a["stats"], b["stats"]), _first_diff(a["stats"], b["stats"])
+    assert np.array_equal(a["x"], b["x"]) and np.array_equal(a["E"], b["E"])
+    assert a["best"] == b["best"] and np.array_equal(a["bx"], b["bx"])
+
+
+@pytest.mark.parametrize("over", [dict(), dict(sweep_kernel=2, tile_replicas=32),
+                                  dict(nl_kind=1, nl_period=3)])
+def test_split_run_equals_one_run(pa, over):
+    """Steps in three ranges give exactly the one-call run (both sweep kernels,
+    both kinds of non-local move), and equal the oracle."""
+    wl = W.workload("g63like")
+    wl = dict(wl, R=200, betas=wl["betas"][:9], sweeps=2, as_stall_steps=1, as_frozen_inv=8,
+              nl_period=over.get("nl_period", 2), nl_kind=over.get("nl_kind", 0))
+    kw = {k: v for k, v in over.items() if k in ("sweep_kernel", "tile_replicas")}
+    p = pa.params_from_workload(wl, record=3, **kw)
+    _say(f"split run {over}")
+    one = pa.Solver(wl["graph"]).run(p)
+    ref_one = _results(one)
+    s = pa.Solver(wl["graph"])
+    s.run_steps(p, 0, 4)
+    mid = _results(s)                       # population the fifth step starts from
+    s.run_steps(p, 4, 7).run_steps(p, 7, 9)
+    _assert_same(_results(s), ref_one)
+    assert np.array_equal(s.counts()[:-1], one.counts()[:-1])
+    assert np.array_equal(s.initial_population(), one.initial_population())
+    ref = O.run_workload(wl, want_counts=False)
+    assert np.array_equal(ref_one["stats"], ref.stats) and np.array_equal(ref_one["x"], ref.x)
+    # the mid-run population is a valid resampled population of the run
+    i, j, w = wl["graph"].edges()
+    for q in range(0, p.R, 37):
+        xq = mid["x"][q].astype(np.int64)
+        assert int(mid["E"][q]) == int(np.sum(w * xq[i] * xq[j]))
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+def test_checkpoint_resume_in_new_solver_and_other_launch_shape(pa, kind):
+    """Checkpoint after step 5, restore into a new solver with another launch
+    shape, finish: identical to the uninterrupted run and to the oracle."""
+    wl = W.workload("g63like")
+    wl = dict(wl, R=160, betas=W.linear_betas(0.5, 5.0, 12), sweeps=2, as_stall_steps=1,
+              as_frozen_inv=8, nl_period=3, nl_kind=kind)
+    p = pa.params_from_workload(wl, record=3)
+    _say(f"checkpoint kind={kind}")
+    full = _results(pa.Solver(wl["graph"]).run(p))
+    a = pa.Solver(wl["graph"]).run_steps(p, 0, 5)
+    blob = a.checkpoint()
+    assert pa.next_step(blob) == 5
+    mid = _results(a)
+    assert a.checkpoint() == blob                       # saving twice gives the same bytes
+    a.run_steps(p, 5, 12)                               # the saved run still continues
+    _assert_same(_results(a), full)
+    q = pa.params_from_workload(wl, record=3, sweep_kernel=2, tile_replicas=16)
+    b = pa.Solver(wl["graph"]).restore(q, blob)
+    m2 = _results(b)
+    assert np.array_equal(m2["x"], mid["x"]) and np.array_equal(m2["E"], mid["E"])
+    b.run_steps(q, 5, 12)
+    _assert_same(_results(b), full)
+    ref = O.run_workload(wl, want_counts=False)
+    assert np.array_equal(full["stats"], ref.stats) and np.array_equal(full["x"], ref.x)
+    assert full["best"] == (ref.best_E, ref.best_step, ref.best_sweep, ref.best_replica)
+    # a checkpoint of another seed or schedule is refused
+    with pytest.raises(pa.PAError):
+        pa.Solver(wl["graph"]).restore(pa.params_from_workload(wl, record=3, seed=43), blob)
+    with pytest.raises(pa.PAError):
+        pa.Solver(wl["graph"]).restore(pa.params_from_workload(dict(wl, sweeps=3), record=3), blob)

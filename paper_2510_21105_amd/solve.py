@@ -2,18 +2,24 @@
 
     python -m paper_2510_21105_amd.solve --gset G63.txt --hex-out best.hex
     python -m paper_2510_21105_amd.solve --gset G63.txt --check-hex config.hex
+    python -m paper_2510_21105_amd.solve --gset G63.txt --checkpoint run.ckpt --checkpoint-every 100
+    python -m paper_2510_21105_amd.solve --gset G63.txt --resume run.ckpt
 
 The first form runs population annealing (linear inverse-temperature steps,
 adaptive stochasticity and cluster moves on by default) and prints one JSON
 line with the best cut (eq. (1)) and its configuration in the paper's
 hexadecimal format (section 3). The second evaluates eq. (1) for a given
-configuration without solving. Every annealing step runs in the library's
-kernels; this module only parses arguments and files.
+configuration without solving. With --checkpoint the run's state is written
+to a file every --checkpoint-every steps (and at the end); --resume continues
+such a file with the same flags and gives the result of the uninterrupted
+run. Every annealing step runs in the library's kernels; this module only
+parses arguments and files.
 """
 from __future__ import annotations
 
 import argparse
 import json
+import os
 import sys
 import time
 
@@ -35,6 +41,9 @@ def _args(argv):
     ap.add_argument("--seed", type=int, default=42)
     ap.add_argument("--instance", type=int, default=0)
     ap.add_argument("--hex-out", help="write the best configuration here")
+    ap.add_argument("--checkpoint", help="write the run's state to this file")
+    ap.add_argument("--checkpoint-every", type=int, default=100, help="steps between checkpoints")
+    ap.add_argument("--resume", help="continue the run saved in this checkpoint file")
     return ap.parse_args(argv)
 
 
@@ -58,8 +67,24 @@ def main(argv=None) -> dict:
               as_enable=0 if a.no_as else 1, as_stall_steps=20, as_max_level=4,
               as_frozen_inv=256, as_gamma=0.8, nl_period=a.nl_period)
     s = pa.Solver(g)
+    p = pa.params_from_workload(wl)
     t0 = time.perf_counter()
-    s.run(pa.params_from_workload(wl))
+    k = 0
+    if a.resume:
+        with open(a.resume, "rb") as f:
+            blob = f.read()
+        s.restore(p, blob)
+        k = pa.next_step(blob)
+    every = a.steps if not a.checkpoint else max(1, a.checkpoint_every)
+    while k < a.steps:
+        k1 = min(a.steps, k + every)
+        s.run_steps(p, k, k1)
+        k = k1
+        if a.checkpoint:
+            blob = s.checkpoint()
+            with open(a.checkpoint + ".tmp", "wb") as f:
+                f.write(blob)
+            os.replace(a.checkpoint + ".tmp", a.checkpoint)
     cut = s.best_cut()
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0

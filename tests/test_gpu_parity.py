@@ -555,3 +555,30 @@ def test_checkpoint_resume_in_new_solver_and_other_launch_shape(pa, kind):
         pa.Solver(wl["graph"]).restore(pa.params_from_workload(wl, record=3, seed=43), blob)
     with pytest.raises(pa.PAError):
         pa.Solver(wl["graph"]).restore(pa.params_from_workload(dict(wl, sweeps=3), record=3), blob)
+
+
+def test_command_line_checkpoint_and_resume(pa, tmp_path):
+    """The solve command with checkpoints every 7 steps, and resumed from a
+    checkpoint taken after step 9, both give the uninterrupted run's result."""
+    from paper_2510_21105_amd import gset, solve
+    g = W.random_graph(400, 1600, 13)
+    gp = tmp_path / "g.txt"
+    gset.save(g, str(gp))
+    args = ["--gset", str(gp), "--replicas", "128", "--steps", "20", "--sweeps", "3",
+            "--nl-period", "4", "--instance", "5"]
+    _say("solve command: plain, checkpointed, resumed")
+    plain = solve.main(args)
+    ck = tmp_path / "run.ckpt"
+    chk = solve.main(args + ["--checkpoint", str(ck), "--checkpoint-every", "7"])
+    assert (chk["best_cut"], chk["hex"]) == (plain["best_cut"], plain["hex"])
+    assert pa.next_step(ck.read_bytes()) == 20
+    # a checkpoint after step 9, written through the library, resumed by the command
+    h = gset.load(str(gp))
+    wl = dict(graph=h, betas=W.linear_betas(0.1, 5.0, 20), sweeps=3, order=W.natural_order(h.n),
+              R=128, seed=42, inst=5, as_enable=1, as_stall_steps=20, as_max_level=4,
+              as_frozen_inv=256, as_gamma=0.8, nl_period=4)
+    s = pa.Solver(h).run_steps(pa.params_from_workload(wl), 0, 9)
+    mid = tmp_path / "mid.ckpt"
+    mid.write_bytes(s.checkpoint())
+    res = solve.main(args + ["--resume", str(mid)])
+    assert (res["best_cut"], res["hex"]) == (plain["best_cut"], plain["hex"])

@@ -18,9 +18,9 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "pa_oracle.c")
 LIB = os.path.join(HERE, "liboracle.so")
-STAT_FIELDS = 8
+STAT_FIELDS = 10
 STAT_NAMES = ("E_min", "E_sum", "uphill_attempts", "uphill_accepts", "level",
-              "best_E", "parents", "weight_sum")
+              "best_E", "parents", "weight_sum", "grid_index", "jump")
 
 _lib = None
 
@@ -62,12 +62,14 @@ def lib():
         L.oracle_resample_counts.restype = u64
         L.oracle_icm_pair.argtypes = [i32, P, P, P, P, u32, P]
         L.oracle_icm_pair.restype = i32
+        L.oracle_adapt_jump.argtypes = [i32, P, i64, P, i32, i32, i32]
+        L.oracle_adapt_jump.restype = i32
         L.oracle_bond_threshold.argtypes = [f64]
         L.oracle_bond_threshold.restype = u64
         L.oracle_wolff.argtypes = [i32, P, P, P, P, P, u64, u64, u32, u32, u32, P]
         L.oracle_wolff.restype = i32
         L.oracle_run.argtypes = [i32, P, P, P, i32, P, i32, P, i32, i32, i32, i32, f64, i32, i32,
-                                 i32, u64, u32, i32, P, P, P, P, P, P, P]
+                                 i32, i32, i32, i32, i32, u64, u32, i32, P, P, P, P, P, P, P]
         L.oracle_run.restype = ctypes.c_int
         L.oracle_num_threads.argtypes = []
         L.oracle_num_threads.restype = ctypes.c_int
@@ -138,6 +140,12 @@ def wolff(g, x, q: int, seed: int, inst: int, step: int, replica: int):
     return x, mask.astype(bool), int(size)
 
 
+def adapt_jump(E, betas, jmax: int, num: int, den: int) -> int:
+    E = np.ascontiguousarray(E, dtype=np.int32)
+    b = np.ascontiguousarray(betas, dtype=np.float64)
+    return int(lib().oracle_adapt_jump(E.shape[0], _p(E), int(E.min()), _p(b), jmax, num, den))
+
+
 def num_threads() -> int:
     return int(lib().oracle_num_threads())
 
@@ -163,7 +171,8 @@ class RunResult:
 
 def run(g, betas, sweeps, R, seed, inst=0, order=None, as_enable=0, as_stall_steps=20,
         as_max_level=4, as_frozen_inv=256, as_gamma=0.8, nl_period=0, nthreads=0,
-        want_population=True, want_counts=True, nl_kind=0) -> RunResult:
+        want_population=True, want_counts=True, nl_kind=0, beta_adapt=0, adapt_jump=8,
+        adapt_num=1, adapt_den=2) -> RunResult:
     betas = np.ascontiguousarray(betas, dtype=np.float64)
     K = betas.shape[0]
     order_a = None if order is None else np.ascontiguousarray(order, dtype=np.int32)
@@ -176,7 +185,8 @@ def run(g, betas, sweeps, R, seed, inst=0, order=None, as_enable=0, as_stall_ste
     counts = np.zeros((K, R), dtype=np.int32) if want_counts else None
     rc = lib().oracle_run(g.n, _p(g.row_ptr), _p(g.col), _p(g.w), K, _p(betas), sweeps,
                           _p(order_a), as_enable, as_stall_steps, as_max_level, as_frozen_inv,
-                          as_gamma, nl_period, nl_kind, R, seed, inst, nthreads, _p(x_init),
+                          as_gamma, nl_period, nl_kind, beta_adapt, adapt_jump, adapt_num, adapt_den,
+                          R, seed, inst, nthreads, _p(x_init),
                           _p(x_out),
                           _p(E), _p(best), _p(best_x), _p(stats), _p(counts))
     if rc != 0:
@@ -193,4 +203,6 @@ def run_workload(wl: dict, **over) -> RunResult:
     return run(p["graph"], p["betas"], p["sweeps"], p["R"], p["seed"], p["inst"], p["order"],
                p["as_enable"], p["as_stall_steps"], p["as_max_level"], p["as_frozen_inv"],
                p["as_gamma"], p["nl_period"], p.get("nthreads", 0),
-               p.get("want_population", True), p.get("want_counts", True), p.get("nl_kind", 0))
+               p.get("want_population", True), p.get("want_counts", True), p.get("nl_kind", 0),
+               p.get("beta_adapt", 0), p.get("adapt_jump", 8), p.get("adapt_num", 1),
+               p.get("adapt_den", 2))

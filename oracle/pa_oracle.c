@@ -58,6 +58,16 @@
  *         frozen_inv * (uphill accepts) < (uphill attempts) during step k
  *         then l <- min(l + 1, l_max) and stall <- 0. The level applies to the
  *         next step's sweeps. Uphill means m > 0.
+ *   Adaptive steps (beta_adapt 1): beta[] is a grid of K inverse
+ *         temperatures and step k sweeps at the current grid point g_k
+ *         (g_0 = 0). After step k (if g_k < K-1) the run moves to
+ *         g_k + j for the largest j in [1, min(J, K-1-g_k)] whose weights
+ *         W_r = floor(2^32 exp(-(dbeta_j (E_r - E_min)))), dbeta_j =
+ *         beta_j - beta_0, keep the normalised effective population
+ *         (sum W)^2 / (R sum W^2) at or above num/den (exact in 128-bit
+ *         integers; j = 1 when none does), and resamples with those weights.
+ *         The run ends after the step at the last grid point, so it takes at
+ *         most K steps. Without adaptation g_k = k and j = 1.
  *   Resample (steps k < K-1): dbeta = beta_{k+1} - beta_k (FP64);
  *         E_min = min_r E_r; W_r = floor(2^32 * exp(-(dbeta * (E_r - E_min))));
  *         S = sum W (uint64); C_r = W_0 + ... + W_r;
@@ -81,7 +91,7 @@
 #include <omp.h>
 #endif
 
-#define ORACLE_STAT_FIELDS 8
+#define ORACLE_STAT_FIELDS 10
 /* stats record per step k (int64):
  *   0 E_min   (after sweeps and NL, before resampling)
  *   1 E_sum
@@ -90,7 +100,9 @@
  *   4 AS level used by the step's sweeps
  *   5 best_E after the step
  *   6 number of replicas with at least one copy (0 on the last step)
- *   7 weight sum S (0 on the last step)                                  */
+ *   7 weight sum S (0 on the last step)
+ *   8 grid index of the step's inverse temperature (= k without adaptation)
+ *   9 grid points to the next step (1 without adaptation; 0 on the last)  */
 
 /* ------------------------------------------------------------------ RNG */
 
@@ -300,6 +312,26 @@ int32_t oracle_wolff(int32_t n, const int32_t *row_ptr, const int32_t *col, cons
     return tail;
 }
 
+/* Adaptive step: the largest j in [1, jmax] whose weights
+ * W_r = floor(2^32 exp(-((beta_j - beta_0)(E_r - emin)))) satisfy
+ * den (sum W)^2 >= num R (sum W^2), else 1 (128-bit integers throughout). */
+int32_t oracle_adapt_jump(int32_t R, const int32_t *E, int64_t emin, const double *beta, int32_t jmax,
+                          int32_t num, int32_t den)
+{
+    for (int32_t j = jmax; j > 1; --j) {
+        double dbeta = beta[j] - beta[0];
+        unsigned __int128 S1 = 0, S2 = 0;
+        for (int32_t r = 0; r < R; ++r) {
+            uint64_t W = oracle_weight(dbeta, (int64_t)E[r] - emin);
+            S1 += W;
+            S2 += (unsigned __int128)W * W;
+        }
+        if (S1 * S1 * (unsigned __int128)(uint32_t)den >= (unsigned __int128)(uint32_t)num * (uint32_t)R * S2)
+            return j;
+    }
+    return 1;
+}
+
 /* ------------------------------------------------------------ PA driver */
 
 static void best_check(int32_t R, int32_t n, const int32_t *E, const int8_t *x,
@@ -331,6 +363,7 @@ int oracle_run(int32_t n, const int32_t *row_ptr, const int32_t *col, const int8
                int32_t K, const double *beta, int32_t S, const int32_t *order,
                int32_t as_enable, int32_t as_stall_steps, int32_t as_max_level,
                int32_t as_frozen_inv, double as_gamma, int32_t nl_period, int32_t nl_kind,
+               int32_t beta_adapt, int32_t adapt_jump, int32_t adapt_num, int32_t adapt_den,
                int32_t R, uint64_t seed, uint32_t inst, int32_t nthreads,
                int8_t *x_init, int8_t *x_out, int32_t *E_out, int64_t *best,
                int8_t *best_x, int64_t *stats, int32_t *counts)
@@ -338,6 +371,10 @@ int oracle_run(int32_t n, const int32_t *row_ptr, const int32_t *col, const int8
     if (n <= 0 || K <= 0 || S <= 0 || S > 65535 || R <= 0 || R > 32768 || inst > 65535)
         return -1;
     if (nl_kind != 0 && nl_kind != 1) return -1;
+    if (beta_adapt != 0 && beta_adapt != 1) return -1;
+    if (beta_adapt && (adapt_jump < 1 || adapt_num < 0 || adapt_den < 1 || adapt_num > adapt_den ||
+                       adapt_den > 65536))
+        return -1;
     if (nl_period > 0 && nl_kind == 0 && (R & 1)) return -1;
     if (as_enable && (as_stall_steps < 1 || as_max_level < 0 || as_frozen_inv < 1)) return -1;
     for (int32_t k = 0; k < K; ++k) {
@@ -382,10 +419,10 @@ int oracle_run(int32_t n, const int32_t *row_ptr, const int32_t *col, const int8
     int dummy = 0;
     best_check(R, n, E, x, bst, bx, -1, -1, &dummy);
 
-    int32_t level = 0, stall = 0;
-    for (int32_t k = 0; k < K; ++k) {
+    int32_t level = 0, stall = 0, gk = 0, done = 0;
+    for (int32_t k = 0; k < K && !done; ++k) {
         int improved = 0;
-        double b = oracle_level_beta(beta[k], as_gamma, level);
+        double b = oracle_level_beta(beta[gk], as_gamma, level);
         thr[0] = 0;
         for (int32_t m = 1; m <= dmax; ++m) thr[m] = oracle_threshold(b, m);
         (void)lmax;
@@ -478,9 +515,21 @@ int oracle_run(int32_t n, const int32_t *row_ptr, const int32_t *col, const int8
 
         int64_t parents = 0;
         uint64_t wsum = 0;
-        if (k < K - 1) {
-            double dbeta = beta[k + 1] - beta[k];
-            for (int32_t r = 0; r < R; ++r) Wr[r] = oracle_weight(dbeta, (int64_t)E[r] - emin);
+        int32_t jump = 0;
+        const int32_t g_used = gk;
+        if (gk < K - 1) {
+            double dbeta;
+            if (!beta_adapt) {
+                jump = 1;
+                dbeta = beta[gk + 1] - beta[gk];
+                for (int32_t r = 0; r < R; ++r) Wr[r] = oracle_weight(dbeta, (int64_t)E[r] - emin);
+            } else {
+                int32_t jmax = K - 1 - gk < adapt_jump ? K - 1 - gk : adapt_jump;
+                jump = oracle_adapt_jump(R, E, emin, beta, jmax, adapt_num, adapt_den);
+                dbeta = beta[jump] - beta[0];
+                for (int32_t r = 0; r < R; ++r) Wr[r] = oracle_weight(dbeta, (int64_t)E[r] - emin);
+            }
+            gk += jump;
             uint64_t U = oracle_resample_uniform(seed, inst, (uint32_t)k);
             wsum = oracle_resample_counts(R, Wr, U, cnt);
             int32_t slot = 0;
@@ -497,10 +546,14 @@ int oracle_run(int32_t n, const int32_t *row_ptr, const int32_t *col, const int8
             int32_t *th = h; h = h2; h2 = th;
             int32_t *te = E; E = E2; E2 = te;
         }
+        else {
+            done = 1;
+        }
         if (stats) {
             int64_t *st = stats + (size_t)k * ORACLE_STAT_FIELDS;
             st[0] = emin; st[1] = esum; st[2] = (int64_t)att_up; st[3] = (int64_t)acc_up;
             st[4] = level_used; st[5] = bst[0]; st[6] = parents; st[7] = (int64_t)wsum;
+            st[8] = g_used; st[9] = jump;
         }
     }
     if (x_out) memcpy(x_out, x, (size_t)R * n);

@@ -424,6 +424,78 @@ def test_wolff_in_run_keeps_energies_and_estimator():
     _run(g, betas[:3], sweeps=1, R=7, nl_period=1, nl_kind=1)
 
 
+# ---------------------------------------------------- adaptive steps ----
+
+def test_adaptive_jump_against_exact_integers():
+    """The jump rule in exact Python integers: the largest j <= jmax with
+    den (sum W)^2 >= num R sum W^2, W = floor(2^32 exp(-(beta_j - beta_0) dE))
+    (weights from the pinned weight function), on populations large enough
+    to need 128-bit sums."""
+    rng = np.random.default_rng(8)
+    betas = W.linear_betas(0.2, 3.0, 41)
+    for trial in range(40):
+        R = int(rng.choice([1, 7, 300, 4096, 32768]))
+        spread = int(rng.choice([0, 2, 20, 400]))
+        E = (-1000 + rng.integers(0, spread + 1, size=R)).astype(np.int32)
+        jmax = int(rng.integers(1, 17))
+        num, den = [(1, 2), (9, 10), (0, 1), (1, 1), (1, 20)][trial % 5]
+        got = O.adapt_jump(E, betas, jmax, num, den)
+        want = 1
+        emin = int(E.min())
+        hist = np.bincount(E.astype(np.int64) - emin)
+        for j in range(jmax, 1, -1):
+            db = betas[j] - betas[0]
+            ws = [O.weight(db, d) for d in range(hist.shape[0])]
+            S1 = sum(int(c) * w for c, w in zip(hist, ws))
+            S2 = sum(int(c) * w * w for c, w in zip(hist, ws))
+            if den * S1 * S1 >= num * R * S2:
+                want = j
+                break
+        assert got == want, (trial, R, spread, jmax, num, den)
+
+
+def test_adaptive_steps_with_target_zero_take_the_largest_jumps():
+    g = W.random_graph(40, 120, 2)
+    K, J = 23, 4
+    r = _run(g, W.linear_betas(0.0, 2.0, K), sweeps=2, R=64, beta_adapt=1, adapt_jump=J,
+             adapt_num=0, adapt_den=1)
+    grid = [0, 4, 8, 12, 16, 20, 22]
+    steps = len(grid)
+    assert r.stats[:steps, 8].tolist() == grid
+    assert r.stats[:steps, 9].tolist() == [4, 4, 4, 4, 4, 2, 0]
+    assert not r.stats[steps:].any() and not r.counts[steps - 1:].any()
+
+
+def test_adaptive_steps_reproduce_free_energy_by_enumeration():
+    """Adaptive steps on a 12-node graph: the estimator sum_k ln(S_k / (R
+    2^32)) - dbeta_k E_min,k with dbeta_k = beta_{j_k} - beta_0 still gives
+    ln Z(beta_end) by enumeration, and the jumps vary."""
+    g = W.random_graph(12, 30, 9)
+    betas = W.linear_betas(0.0, 1.5, 121)
+    R = 20000
+    r = _run(g, betas, sweeps=5, R=R, seed=3, beta_adapt=1, adapt_jump=32, adapt_num=95, adapt_den=100)
+    steps = int(np.count_nonzero(r.stats[:, 6])) + 1
+    assert r.stats[steps - 1, 8] == len(betas) - 1 and r.stats[steps - 1, 9] == 0
+    jumps = r.stats[:steps - 1, 9]
+    assert len(set(jumps.tolist())) > 1 and steps < len(betas)
+    assert np.array_equal(np.cumsum(np.r_[0, jumps]), r.stats[:steps, 8])
+    est = g.n * math.log(2.0)
+    for k in range(steps - 1):
+        dbeta = betas[int(r.stats[k, 9])] - betas[0]
+        est += math.log(float(r.stats[k, 7]) / (R * 2.0 ** 32)) - dbeta * float(r.stats[k, 0])
+    E = refs.all_energies(g)
+    b = betas[-1]
+    exact = float(np.log(np.exp(-b * (E - E.min())).sum()) - b * E.min())
+    assert abs(est - exact) < 0.03
+
+
+def test_adaptive_target_one_steps_one_grid_point_while_energies_differ():
+    g = W.random_graph(200, 800, 4)
+    r = _run(g, W.linear_betas(0.0, 0.5, 12), sweeps=1, R=64, beta_adapt=1, adapt_jump=6,
+             adapt_num=1, adapt_den=1)
+    assert r.stats[:-1, 9].tolist() == [1] * 11 and r.stats[:, 8].tolist() == list(range(12))
+
+
 # --------------------------------------------------------- run invariants ----
 
 @pytest.mark.parametrize("name,over", [

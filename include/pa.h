@@ -81,6 +81,19 @@ typedef struct {
                                      beta_k gamma^l: a bond with w_ij x_i x_j < 0 is
                                      activated with probability 1 - exp(-2 beta'), and
                                      the active-bond component of a random node flips. */
+    int32_t beta_adapt;       /* 0: step k sweeps at beta[k] (K steps). 1: adaptive steps:
+                                 beta[] is a grid; each step sweeps at the current grid
+                                 point g and then moves to g + j for the largest j in
+                                 [1, min(adapt_jump, K-1-g)] whose resampling weights
+                                 W_r = floor(2^32 exp(-((beta[j] - beta[0])(E_r - E_min))))
+                                 keep (sum W)^2 / (R sum W^2) >= adapt_num / adapt_den
+                                 (decided in exact integers; j = 1 if none), resampling
+                                 with those weights. The run ends after the step at the
+                                 last grid point (at most K steps; later steps are
+                                 empty). The paper adapts the annealing without
+                                 defining how (section 3); this is one definition.  */
+    int32_t adapt_jump;       /* 1..64, largest jump in grid points (beta_adapt = 1)  */
+    int32_t adapt_num, adapt_den; /* target, 0 <= adapt_num <= adapt_den <= 65536, den >= 1 */
 } pa_schedule;
 
 /* Text of the last error on this thread ("" if none). */
@@ -222,8 +235,9 @@ pa_status pa_run_batch(const pa_batch_run *runs, int32_t count, void *const *str
  *     stochasticity else 1: entry m = floor(2^32 exp(-(beta_k gamma^l * 2m)))
  *     for m >= 1 (gamma^l as l successive FP64 products) and 2^32 for m = 0;
  *   weights [K - 1][e_span + 1]: entry n = floor(2^32 exp(-(beta_{k+1} -
- *     beta_k) n)).
- * *bytes = 8 (K L (d_max + 1) + (K - 1)(e_span + 1)). PA_EINVAL for a bad
+ *     beta_k) n)); with beta_adapt = 1 instead [J][e_span + 1], J =
+ *     min(adapt_jump, K - 1), row j - 1 for beta_j - beta_0.
+ * *bytes = 8 (K L (d_max + 1) + (K - 1 or J)(e_span + 1)). PA_EINVAL for a bad
  * schedule (as for pa_run) or negative sizes, PA_ERANGE when
  * d_max > 4096, e_span > 2^26 or *bytes is too small for a non-NULL `out`.
  */

@@ -106,6 +106,7 @@ struct pa_solver {
         size_t Xc = 0, Xn = 0, Ec = 0, En = 0;
         uint32_t seed_lo = 0, seed_hi = 0, instance = 0;
         int nl_period = 0, nl_kind = 0;
+        int adapt = 0;                  // adaptive steps: the run may end before step K
         pa::GraphDev gd{};
         pa::SweepArgs sa{};
         pa::EpiArgs ea{};
@@ -245,6 +246,13 @@ static pa_status check_schedule(const pa_solver *s, const pa_schedule *sch, int 
     if (sch->nl_period < 0) return fail(PA_EINVAL, "nl_period must be >= 0");
     if (R < 1 || R > kMaxR) return fail(PA_ERANGE, "R=%d outside [1, %d]", R, kMaxR);
     if (sch->nl_kind != 0 && sch->nl_kind != 1) return fail(PA_EINVAL, "nl_kind must be 0 or 1");
+    if (sch->beta_adapt != 0 && sch->beta_adapt != 1) return fail(PA_EINVAL, "beta_adapt must be 0 or 1");
+    if (sch->beta_adapt) {
+        if (sch->adapt_jump < 1 || sch->adapt_jump > pa::kMaxJump)
+            return fail(PA_EINVAL, "adapt_jump must be in [1, %d]", pa::kMaxJump);
+        if (sch->adapt_den < 1 || sch->adapt_den > 65536 || sch->adapt_num < 0 || sch->adapt_num > sch->adapt_den)
+            return fail(PA_EINVAL, "adaptive target needs 0 <= adapt_num <= adapt_den <= 65536, den >= 1");
+    }
     if (sch->nl_period > 0 && sch->nl_kind == 0 && (R & 1))
         return fail(PA_EINVAL, "pair cluster moves pair replicas: R must be even");
     if (sch->tile_replicas != 0 && sch->tile_replicas != 4 && sch->tile_replicas != 8 &&
@@ -569,12 +577,15 @@ static pa_status build_plan(pa_solver *s, const pa_schedule *sch, int R, Plan &p
 
     // Weight-table sizes (needed for the workspace size even without tables).
     const long long span = s->nnz;  // E_r - E_min <= sum |w_ij| over both directions
-    p.wtab_off.assign(p.K, 0);
-    p.wtab_len.assign(p.K, 0);
+    // Fixed steps: the table of step k (beta_{k+1} - beta_k). Adaptive steps:
+    // the table of jump j at index j - 1 (beta_j - beta_0).
+    const int n_tab = sch->beta_adapt ? std::min(sch->adapt_jump, p.K - 1) : p.K - 1;
+    p.wtab_off.assign(std::max(p.K, 1), 0);
+    p.wtab_len.assign(std::max(p.K, 1), 0);
     std::map<uint64_t, std::pair<int, int>> seen;
     long long total = 0;
-    for (int k = 0; k + 1 < p.K; ++k) {
-        const double db = sch->beta[k + 1] - sch->beta[k];
+    for (int k = 0; k < n_tab; ++k) {
+        const double db = sch->beta_adapt ? sch->beta[k + 1] - sch->beta[0] : sch->beta[k + 1] - sch->beta[k];
         uint64_t key;
         std::memcpy(&key, &db, sizeof key);
         auto it = seen.find(key);
@@ -709,7 +720,9 @@ static uint64_t run_key(const pa_solver *s, const pa_schedule *sch, int32_t R, u
     h = fnv(h, s->npos.data(), sizeof(int) * s->npos.size());
     const int32_t ints[] = {sch->n_steps, sch->sweeps_per_step, sch->as_enable, sch->as_stall_steps,
                             sch->as_max_level, sch->as_frozen_inv, sch->nl_period, sch->nl_kind,
-                            sch->record, R, (int32_t)instance};
+                            sch->record, R, (int32_t)instance, sch->beta_adapt,
+                            sch->beta_adapt ? sch->adapt_jump : 0, sch->beta_adapt ? sch->adapt_num : 0,
+                            sch->beta_adapt ? sch->adapt_den : 0};
     h = fnv(h, ints, sizeof ints);
     h = fnv(h, &sch->as_gamma, sizeof sch->as_gamma);
     h = fnv(h, &seed, sizeof seed);
@@ -831,6 +844,10 @@ static pa_status start_run(pa_solver *s, const pa_schedule *sch, int32_t R, uint
     ea.as_stall = sch->as_stall_steps;
     ea.as_lmax = sch->as_enable ? sch->as_max_level : 0;
     ea.as_frozen_inv = sch->as_frozen_inv;
+    ea.adapt = sch->beta_adapt;
+    ea.adapt_jump = sch->adapt_jump;
+    ea.adapt_num = sch->adapt_num;
+    ea.adapt_den = sch->adapt_den;
     ea.as_state = reinterpret_cast<int *>(ws + L.as_state);
     ea.cand = U64(L.cand);
     ea.snap = reinterpret_cast<const uint32_t *>(ws + L.snap);
@@ -874,6 +891,7 @@ static pa_status start_run(pa_solver *s, const pa_schedule *sch, int32_t R, uint
     sa.S = P.S;
     sa.lmax1 = P.lmax1;
     sa.n_levels = P.n_levels;
+    sa.K = P.K;
     sa.seed_lo = seed_lo;
     sa.seed_hi = seed_hi;
     sa.inst = instance;
@@ -911,6 +929,7 @@ static pa_status start_run(pa_solver *s, const pa_schedule *sch, int32_t R, uint
     c.seed_lo = seed_lo; c.seed_hi = seed_hi; c.instance = instance;
     c.nl_period = sch->nl_period;
     c.nl_kind = sch->nl_kind;
+    c.adapt = sch->beta_adapt;
     c.gd = gd;
     c.sa = sa;
     c.ea = ea;
@@ -937,6 +956,15 @@ static pa_status run_range(pa_solver *s, int k0, int k1)
     c.valid = false;                           // until every step of the range is enqueued
 
     for (int k = k0; k < k1; ++k) {
+        if (c.adapt && k > 0 && (k - k0) % 64 == 0) {
+            // Adaptive steps end at the last grid point, usually well before
+            // step K: look every 64 steps and enqueue no more once it is done
+            // (the remaining steps would do nothing).
+            int g = 0;
+            HIP_TRY(hipMemcpyAsync(&g, ws + L.as_state + 3 * sizeof(int), sizeof g, hipMemcpyDeviceToHost, hs));
+            HIP_TRY(hipStreamSynchronize(hs));
+            if (g >= P.K) break;
+        }
         sa.k = k;
         if (s->timing) HIP_TRY(hipEventRecord(s->ev[2 * k], hs));
         if (P.kind == 1) {
@@ -974,6 +1002,7 @@ static pa_status run_range(pa_solver *s, int k0, int k1)
             ic.R = R;
             ic.G = P.G;
             ic.k = k;
+            ic.K = P.K;
             ic.nw32 = P.nw32;
             ic.seed_lo = seed_lo;
             ic.seed_hi = seed_hi;
@@ -1099,7 +1128,8 @@ extern "C" pa_status pa_build_tables(const pa_schedule *sch, int32_t d_max, int3
                            sch->as_gamma > 1))
         return fail(PA_EINVAL, "pa_build_tables: noise levels need 0 <= as_max_level <= 15, 0 < gamma <= 1");
     const int K = sch->n_steps, Lv = sch->as_enable ? sch->as_max_level + 1 : 1, D = d_max + 1;
-    const size_t n_thr = (size_t)K * Lv * D, n_w = (size_t)(K - 1) * (size_t)(e_span + 1);
+    const int n_tab = sch->beta_adapt ? std::min(std::max(sch->adapt_jump, 1), K - 1) : K - 1;
+    const size_t n_thr = (size_t)K * Lv * D, n_w = (size_t)n_tab * (size_t)(e_span + 1);
     const size_t need = 8 * (n_thr + n_w);
     if (!out) {
         *bytes = need;
@@ -1119,8 +1149,8 @@ extern "C" pa_status pa_build_tables(const pa_schedule *sch, int32_t d_max, int3
         }
     }
     uint64_t *wt = o + n_thr;
-    for (int k = 0; k + 1 < K; ++k) {
-        const double db = sch->beta[k + 1] - sch->beta[k];
+    for (int k = 0; k < n_tab; ++k) {
+        const double db = sch->beta_adapt ? sch->beta[k + 1] - sch->beta[0] : sch->beta[k + 1] - sch->beta[k];
         for (int m = 0; m <= e_span; ++m) wt[(size_t)k * (e_span + 1) + m] = weight_fixed(db, m);
     }
     return PA_OK;

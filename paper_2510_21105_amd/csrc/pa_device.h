@@ -16,7 +16,8 @@
 
 namespace pa {
 
-constexpr int kStatFields = 8;
+constexpr int kStatFields = 10;
+constexpr int kMaxJump = 64;     // largest grid jump of an adaptive step
 constexpr int kMaxThreads = 1024;
 // Kernel 1 LDS: the 256-entry u32 threshold table (indexed by a move byte),
 // then the byte records.
@@ -37,7 +38,8 @@ struct SweepArgs {
     int dmax;
     int R;            // real replicas
     int S;            // sweeps in this step
-    int k;            // step index
+    int k;            // step index (Philox counter)
+    int K;            // grid points; as_state[3] >= K marks a finished run
     int lmax1;        // number of noise levels
     int n_levels;
     uint32_t seed_lo, seed_hi, inst;
@@ -51,9 +53,9 @@ struct SweepArgs {
     int n_rounds;
     int flush_every;            // rounds between widenings of the byte energy accumulators
     int direct;                 // kernel 1: block entries are LDS byte offsets
-    const uint64_t *thr;        // kernel 2: [K][lmax1][dmax+1] T[m] (T[0] unused)
+    const uint64_t *thr;        // kernel 2: [K][lmax1][dmax+1] T[m] (T[0] unused), by grid point
     const uint32_t *thr32;      // kernel 1: [K][lmax1][dmax+1] T[1..dmax], all-accept flag
-    const int *as_state;        // [0] level
+    const int *as_state;        // [0] level, [3] grid point of this step
     uint64_t *X;                // [G][n] population written by the sweep (kernel 2: in place)
     int *E;                     // [Rp]
     const uint64_t *Xin;        // kernel 1: population before resampling, read through parent
@@ -71,7 +73,8 @@ struct EpiArgs {
     int do_cand, do_pop, do_rest;
     int pop_step, pop_sweep;    // best record when the population check wins
     int as_enable, as_stall, as_lmax, as_frozen_inv;
-    int *as_state;              // [0] level, [1] stall, [2] improved this step
+    int adapt, adapt_jump, adapt_num, adapt_den;   // adaptive steps (jump <= kMaxJump)
+    int *as_state;              // [0] level, [1] stall, [2] improved this step, [3] grid point
     const unsigned long long *cand;
     const uint32_t *snap;
     int *best;                  // [0] E, [1] step, [2] sweep, [3] replica, [4] valid
@@ -79,10 +82,11 @@ struct EpiArgs {
     unsigned long long *counters;
     const int *E;
     const uint64_t *X;
-    long long *stats;           // [K][8]
+    long long *stats;           // [K][kStatFields]
     const uint64_t *wtab;       // weight tables
-    const int *wtab_off;        // [K] offset of step k's table (k < K-1)
-    const int *wtab_len;        // [K]
+    const int *wtab_off;        // fixed steps: [K] table of the step from grid point g
+                                // (g < K-1); adaptive: [jumps] table of jump j at j - 1
+    const int *wtab_len;
     uint32_t seed_lo, seed_hi, inst;
     int *parent;                // [R] parent replica of each new slot
     int *counts_rec;            // [K][R] or null
@@ -99,7 +103,7 @@ struct GatherArgs {
 
 struct IcmArgs {
     GraphDev g;
-    int R, G, k, nw32;
+    int R, G, k, K, nw32;
     int kind;                   // 0: pairs (p, p + R/2); 1: single-replica Wolff update
     int lmax1;                  // noise levels per step in qtab
     uint32_t seed_lo, seed_hi, inst;

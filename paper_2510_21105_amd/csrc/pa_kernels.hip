@@ -264,6 +264,8 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs a, const int2 *__
                                                     const int *__restrict__ level_off,
                                                     const uint4 *__restrict__ blocks)
 {
+    // A finished run (adaptive steps past the last grid point): nothing to do.
+    if (a.as_state[3] >= a.K) return;
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int NS = 64 / W;      // node slots per wave
     constexpr int GPS = W / 4;      // Philox calls per slot
@@ -316,7 +318,7 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs a, const int2 *__
         if constexpr (W == 64) lds_put<W>(zoff + 4, 0u);
     }
     const int level = a.as_state[0];
-    const uint64_t *trow = a.thr + ((size_t)a.k * a.lmax1 + level) * (size_t)(a.dmax + 1);
+    const uint64_t *trow = a.thr + ((size_t)a.as_state[3] * a.lmax1 + level) * (size_t)(a.dmax + 1);
     for (int m = tid; m <= a.dmax; m += blockDim.x) T[m] = m == 0 ? (1ull << 32) : trow[m];
     if (tid < W) Eblk[tid] = (r0 + tid < a.R) ? a.E[r0 + tid] : 0;
     if (tid == 0) {
@@ -615,6 +617,19 @@ template <int W, bool SIGNED, bool DIRECT>
 __global__ __launch_bounds__(1024) void sweep_bytes_kernel(SweepArgs a, const int4 *__restrict__ rounds,
                                                           const uint4 *__restrict__ blocks)
 {
+    if (a.as_state[3] >= a.K) {
+        // A finished run (adaptive steps past the last grid point): carry the
+        // population over to the output buffer unchanged (the parent list is
+        // the identity then), each workgroup a slice.
+        const size_t words = (size_t)((a.R + 63) >> 6) * a.n;
+        const size_t per = (words + gridDim.x - 1) / gridDim.x;
+        const size_t w0 = (size_t)blockIdx.x * per, w1 = w0 + per < words ? w0 + per : words;
+        for (size_t w = w0 + threadIdx.x; w < w1; w += blockDim.x) a.X[w] = a.Xin[w];
+        const int rper = (a.R + (int)gridDim.x - 1) / (int)gridDim.x;
+        const int e0 = (int)blockIdx.x * rper, e1 = e0 + rper < a.R ? e0 + rper : a.R;
+        for (int r = e0 + (int)threadIdx.x; r < e1; r += blockDim.x) a.E[r] = a.Ein[r];
+        return;
+    }
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int NR = W / 4;
     const int n = a.n;
@@ -702,7 +717,7 @@ __global__ __launch_bounds__(1024) void sweep_bytes_kernel(SweepArgs a, const in
     }
     if (tid < NR) *(lds_u32 *)(uintptr_t)(zrec + 4 * tid) = 0u;
     const int level = a.as_state[0];
-    const uint32_t *trow = a.thr32 + ((size_t)a.k * a.lmax1 + level) * (size_t)(a.dmax + 1);
+    const uint32_t *trow = a.thr32 + ((size_t)a.as_state[3] * a.lmax1 + level) * (size_t)(a.dmax + 1);
     // Move byte 0x80 + (m - 1) of an uphill move indexes T[m]; the lower half
     // (downhill moves, accepted by mask) stays zero.
     for (int m = tid; m < 256; m += nt) T[m] = m >= 128 && m - 128 < a.dmax ? trow[m - 128] : 0u;
@@ -1048,6 +1063,9 @@ __global__ __launch_bounds__(1024) void epilogue_kernel(EpiArgs a)
     __shared__ unsigned long long w_cand[16], w_key[16], w_scan[16];
     __shared__ long long w_sum[16];
     __shared__ long long par_total;
+    __shared__ int admissible[kMaxJump + 1];
+    const int g = a.as_state[3];       // grid point of this step's inverse temperature
+    if (g >= a.K) return;              // finished run (adaptive steps)
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int nt = blockDim.x, nwv = nt >> 6;
     const int R = a.R;
@@ -1063,8 +1081,8 @@ __global__ __launch_bounds__(1024) void epilogue_kernel(EpiArgs a)
         for (int q = 0; q < 5; ++q) brec[q] = a.best[q];
     int simp = a.as_state[2];
     // Loads needed after the reductions, issued now.
-    const bool resample = a.do_rest && a.k < a.K - 1;
-    const int off = resample ? a.wtab_off[a.k] : 0, len = resample ? a.wtab_len[a.k] : 0;
+    const bool resample = a.do_rest && g < a.K - 1;
+    int off = resample && !a.adapt ? a.wtab_off[g] : 0, len = resample && !a.adapt ? a.wtab_len[g] : 0;
     int level_used = 0, stall0 = 0;
     unsigned long long att = 0, acc = 0;
     if (tid == 0 && a.do_rest) {
@@ -1168,6 +1186,54 @@ __global__ __launch_bounds__(1024) void epilogue_kernel(EpiArgs a)
             st[0] = emin; st[1] = es; st[2] = (long long)att; st[3] = (long long)acc;
             st[4] = level_used; st[5] = bE;
             st[6] = 0; st[7] = 0;
+            st[8] = g; st[9] = 0;
+            if (!resample) a.as_state[3] = a.K;            // the last grid point: run finished
+        }
+        int jump = 1;
+        if (resample && a.adapt) {
+            // Largest jump j (<= adapt_jump, within the grid) whose weights
+            // keep den (sum W)^2 >= num R sum W^2; wave wv tries j = jmax - wv,
+            // jmax - wv - nwv, ... (128-bit sums), jump 1 needs no test.
+            const int jmax = a.adapt_jump < a.K - 1 - g ? a.adapt_jump : a.K - 1 - g;
+            for (int j = jmax - wv; j >= 2; j -= nwv) {
+                const int oj = a.wtab_off[j - 1], lj = a.wtab_len[j - 1];
+                unsigned long long s1 = 0, q_lo = 0, q_hi = 0;    // sum W, sum W^2 (128 bit)
+                for (int r = lane; r < R; r += 64) {
+                    const int nn = Esh[r] - emin;
+                    const unsigned long long w = nn < lj ? a.wtab[oj + nn] : 0ull;
+                    s1 += w;
+                    const unsigned __int128 w2 = (unsigned __int128)w * w;
+                    const unsigned long long l2 = q_lo + (unsigned long long)w2;
+                    q_hi += (unsigned long long)(w2 >> 64) + (l2 < q_lo ? 1ull : 0ull);
+                    q_lo = l2;
+                }
+#pragma unroll
+                for (int o = 32; o > 0; o >>= 1) {
+                    s1 += __shfl_xor(s1, o, 64);
+                    const unsigned long long lo2 = __shfl_xor(q_lo, o, 64), hi2 = __shfl_xor(q_hi, o, 64);
+                    const unsigned long long l2 = q_lo + lo2;
+                    q_hi += hi2 + (l2 < q_lo ? 1ull : 0ull);
+                    q_lo = l2;
+                }
+                if (lane == 0) {
+                    const unsigned __int128 S2 = ((unsigned __int128)q_hi << 64) | q_lo;
+                    admissible[j] = (unsigned __int128)s1 * s1 * (uint32_t)a.adapt_den >=
+                                    (unsigned __int128)(uint32_t)a.adapt_num * (uint32_t)R * S2;
+                }
+            }
+            __syncthreads();
+            for (int j = jmax; j >= 2; --j)
+                if (admissible[j]) {
+                    jump = j;
+                    break;
+                }
+            off = a.wtab_off[jump - 1];
+            len = a.wtab_len[jump - 1];
+        }
+        if (!resample) {
+            // No resampling after the last grid point: the next population is
+            // this one (identity parents).
+            for (int r = lo; r < hi; ++r) a.parent[r] = r;
         }
         if (resample) {
             uint64_t ws = 0;
@@ -1213,6 +1279,8 @@ __global__ __launch_bounds__(1024) void epilogue_kernel(EpiArgs a)
             if (tid == 0) {
                 st[6] = par_total;
                 st[7] = (long long)S;
+                st[9] = jump;
+                a.as_state[3] = g + jump;
             }
         }
     }
@@ -1320,6 +1388,7 @@ int icm_lds_bytes(int n, int nw32)
 
 __global__ __launch_bounds__(kIcmThreads) void icm_kernel(IcmArgs a)
 {
+    if (a.as_state[3] >= a.K) return;      // finished run
     // LDS: P = union-find parents [n], bitmaps A = spins of replica a,
     // D = disagreement set, V = cluster (nw words each).
     extern __shared__ __align__(16) uint32_t lds[];
@@ -1508,6 +1577,7 @@ __global__ __launch_bounds__(kIcmThreads) void icm_kernel(IcmArgs a)
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kIcmThreads) void wolff_kernel(IcmArgs a)
 {
+    if (a.as_state[3] >= a.K) return;      // finished run
     // LDS: P = union-find parents [n], A = spins of the replica, V = cluster.
     extern __shared__ __align__(16) uint32_t lds[];
     __shared__ long long red_l[16];
@@ -1538,7 +1608,7 @@ __global__ __launch_bounds__(kIcmThreads) void wolff_kernel(IcmArgs a)
         }
     }
     __syncthreads();
-    const uint64_t q = a.qtab[(size_t)a.k * a.lmax1 + a.as_state[0]];
+    const uint64_t q = a.qtab[(size_t)a.as_state[3] * a.lmax1 + a.as_state[0]];
     auto bit = [&](const uint32_t *B, uint32_t i) { return (B[i >> 5] >> (i & 31)) & 1u; };
     // Active bonds: a lane takes 8 edges of the (shuffled) edge list and draws
     // only for the satisfied ones.
@@ -1613,6 +1683,7 @@ __global__ __launch_bounds__(kIcmThreads) void wolff_kernel(IcmArgs a)
 // replicas' bits of nodes 32w..32w+31 with ballots.
 __global__ __launch_bounds__(256) void icm_apply_kernel(IcmArgs a)
 {
+    if (a.as_state[3] >= a.K) return;      // finished run
     const int lane = threadIdx.x & 63;
     const int w = blockIdx.x * 4 + (threadIdx.x >> 6);
     const int g = blockIdx.y;

@@ -15,9 +15,9 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpa.so")
-STAT_FIELDS = 8
+STAT_FIELDS = 10
 STAT_NAMES = ("E_min", "E_sum", "uphill_attempts", "uphill_accepts", "level",
-              "best_E", "parents", "weight_sum")
+              "best_E", "parents", "weight_sum", "grid_index", "jump")
 
 PA_OK, PA_EINVAL, PA_ERANGE, PA_EWORKSPACE, PA_EDEVICE, PA_ESTATE = 0, -1, -2, -3, -4, -5
 _STATUS = {PA_EINVAL: "PA_EINVAL", PA_ERANGE: "PA_ERANGE", PA_EWORKSPACE: "PA_EWORKSPACE",
@@ -53,6 +53,10 @@ class Schedule(ctypes.Structure):
         ("wg_threads", ctypes.c_int32),
         ("record", ctypes.c_int32),
         ("nl_kind", ctypes.c_int32),
+        ("beta_adapt", ctypes.c_int32),
+        ("adapt_jump", ctypes.c_int32),
+        ("adapt_num", ctypes.c_int32),
+        ("adapt_den", ctypes.c_int32),
     ]
 
 
@@ -144,6 +148,10 @@ class RunParams:
     wg_threads: int = 0
     record: int = 0
     nl_kind: int = 0              # 0: pair cluster moves; 1: single-replica Wolff updates
+    beta_adapt: int = 0           # 1: betas is a grid walked by adaptive jumps
+    adapt_jump: int = 8
+    adapt_num: int = 1
+    adapt_den: int = 2
 
 
 class Solver:
@@ -200,6 +208,10 @@ class Solver:
         sch.wg_threads = p.wg_threads
         sch.record = p.record
         sch.nl_kind = p.nl_kind
+        sch.beta_adapt = p.beta_adapt
+        sch.adapt_jump = p.adapt_jump
+        sch.adapt_num = p.adapt_num
+        sch.adapt_den = p.adapt_den
         return sch, (betas, order)
 
     def workspace_bytes(self, p: RunParams) -> int:
@@ -332,7 +344,8 @@ class Solver:
 
 def build_tables(p: RunParams, d_max: int, e_span: int):
     """The run's fixed-point tables (pa_build_tables): thresholds
-    [K][levels][d_max + 1] and weights [K - 1][e_span + 1], as uint64 arrays."""
+    [K][levels][d_max + 1] and weights [K - 1][e_span + 1] (adaptive steps:
+    [min(adapt_jump, K - 1)][e_span + 1], one row per jump), as uint64 arrays."""
     sch, keep = Solver._schedule(p)
     n = ctypes.c_size_t()
     _check(lib().pa_build_tables(ctypes.byref(sch), d_max, e_span, None, ctypes.byref(n)))
@@ -341,7 +354,8 @@ def build_tables(p: RunParams, d_max: int, e_span: int):
     K = len(p.betas)
     L = p.as_max_level + 1 if p.as_enable else 1
     nt = K * L * (d_max + 1)
-    return buf[:nt].reshape(K, L, d_max + 1), buf[nt:].reshape(K - 1, e_span + 1)
+    rows = min(p.adapt_jump, K - 1) if p.beta_adapt else K - 1
+    return buf[:nt].reshape(K, L, d_max + 1), buf[nt:].reshape(rows, e_span + 1)
 
 
 def run_batch(solvers, params, streams):
@@ -373,7 +387,9 @@ def params_from_workload(wl: dict, **over) -> RunParams:
                      as_frozen_inv=d["as_frozen_inv"], as_gamma=d["as_gamma"],
                      nl_period=d["nl_period"], sweep_kernel=d.get("sweep_kernel", 0),
                      tile_replicas=d.get("tile_replicas", 0), wg_threads=d.get("wg_threads", 0),
-                     record=d.get("record", 0), nl_kind=d.get("nl_kind", 0))
+                     record=d.get("record", 0), nl_kind=d.get("nl_kind", 0),
+                     beta_adapt=d.get("beta_adapt", 0), adapt_jump=d.get("adapt_jump", 8),
+                     adapt_num=d.get("adapt_num", 1), adapt_den=d.get("adapt_den", 2))
 
 
 def next_step(blob: bytes) -> int:

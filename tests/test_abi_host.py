@@ -132,6 +132,12 @@ def test_workspace_grows_with_population():
     (dict(as_enable=1, as_frozen_inv=0), pa.PA_EINVAL),
     (dict(record=4), pa.PA_EINVAL),
     (dict(nl_kind=2, nl_period=2), pa.PA_EINVAL),
+    (dict(beta_adapt=2), pa.PA_EINVAL),
+    (dict(beta_adapt=1, adapt_jump=0), pa.PA_EINVAL),
+    (dict(beta_adapt=1, adapt_jump=65), pa.PA_EINVAL),
+    (dict(beta_adapt=1, adapt_num=3, adapt_den=2), pa.PA_EINVAL),
+    (dict(beta_adapt=1, adapt_num=0, adapt_den=0), pa.PA_EINVAL),
+    (dict(beta_adapt=1, adapt_num=1, adapt_den=70000), pa.PA_EINVAL),
     (dict(nl_kind=-1), pa.PA_EINVAL),
 ])
 def test_schedule_validation(bad, status):
@@ -272,6 +278,19 @@ def test_run_tables_equal_oracle_tables(name, over):
     for k in range(len(p.betas) - 1):
         db = float(p.betas[k + 1]) - float(p.betas[k])
         assert [int(v) for v in wts[k]] == [O.weight(db, n) for n in range(span + 1)]
+
+
+@pytest.mark.parametrize("jump", [1, 5, 64])
+def test_adaptive_weight_tables_equal_oracle(jump):
+    """Adaptive steps use one weight table per jump j, for beta_j - beta_0."""
+    from oracle import oracle as O
+    wl = dict(W.workload("small800"), beta_adapt=1, adapt_jump=jump)
+    p = pa.params_from_workload(wl)
+    thr, wts = pa.build_tables(p, 12, 300)
+    assert wts.shape == (min(jump, len(p.betas) - 1), 301)
+    for j in range(1, wts.shape[0] + 1):
+        db = float(p.betas[j]) - float(p.betas[0])
+        assert [int(v) for v in wts[j - 1]] == [O.weight(db, n) for n in range(301)]
 
 
 def test_build_tables_rejects_bad_input():

@@ -582,3 +582,51 @@ def test_command_line_checkpoint_and_resume(pa, tmp_path):
     mid.write_bytes(s.checkpoint())
     res = solve.main(args + ["--resume", str(mid)])
     assert (res["best_cut"], res["hex"]) == (plain["best_cut"], plain["hex"])
+
+
+# ------------------------------------------------------- adaptive steps ----
+
+@pytest.mark.parametrize("over", [dict(), dict(sweep_kernel=2, tile_replicas=32),
+                                  dict(nl_kind=1), dict(tile_replicas=4)])
+def test_adaptive_steps_match_oracle(pa, over):
+    """Adaptive temperature steps on the G63-shaped graph (ragged R, noise
+    levels, cluster moves): grid points, jumps, every statistic, population
+    and best equal the oracle's."""
+    wl = W.workload("g63like")
+    wl = dict(wl, R=200, betas=W.linear_betas(0.1, 5.0, 400), sweeps=2, as_stall_steps=2,
+              as_frozen_inv=8, nl_period=3, nl_kind=over.get("nl_kind", 0), beta_adapt=1,
+              adapt_jump=16, adapt_num=1, adapt_den=4)
+    kw = {k: v for k, v in over.items() if k in ("sweep_kernel", "tile_replicas")}
+    s, ref = _compare(pa, wl["graph"], wl, kw)
+    steps = int(np.count_nonzero(ref.stats[:, 9])) + 1
+    assert steps < len(wl["betas"]) and len(set(ref.stats[:steps - 1, 9].tolist())) > 1
+    assert ref.stats[steps - 1, 8] == len(wl["betas"]) - 1
+
+
+def test_adaptive_steps_end_early_and_stop_enqueueing(pa):
+    """Target 0 takes the largest jumps: the run ends after a few of its 300
+    possible steps; the rest are empty, as in the oracle (the host stops
+    enqueueing after its first look)."""
+    g = W.random_graph(500, 2500, 17)
+    wl = dict(W.workload("small800"), graph=g, R=96, betas=W.linear_betas(0.1, 3.0, 300),
+              sweeps=2, order=W.natural_order(g.n), beta_adapt=1, adapt_jump=64, adapt_num=0,
+              adapt_den=1)
+    s, ref = _compare(pa, g, wl)
+    assert ref.stats[:6, 8].tolist() == [0, 64, 128, 192, 256, 299]
+    assert not ref.stats[6:].any()
+
+
+def test_adaptive_steps_checkpoint_and_resume(pa):
+    wl = W.workload("g63like")
+    wl = dict(wl, R=128, betas=W.linear_betas(0.1, 5.0, 300), sweeps=2, nl_period=4, beta_adapt=1,
+              adapt_jump=24, adapt_num=1, adapt_den=3)
+    p = pa.params_from_workload(wl, record=1)
+    full = _results(pa.Solver(wl["graph"]).run(p))
+    a = pa.Solver(wl["graph"]).run_steps(p, 0, 30)
+    blob = a.checkpoint()
+    q = pa.params_from_workload(wl, record=1, sweep_kernel=2, tile_replicas=16)
+    b = pa.Solver(wl["graph"]).restore(q, blob)
+    b.run_steps(q, 30, len(wl["betas"]))
+    _assert_same(_results(b), full)
+    ref = O.run_workload(wl, want_counts=False)
+    assert np.array_equal(full["stats"], ref.stats) and np.array_equal(full["x"], ref.x)

@@ -135,17 +135,18 @@ pa_status pa_workspace_bytes(const pa_solver *s, const pa_schedule *sch, int32_t
  * (graph, schedule except sweep_kernel, tile_replicas and wg_threads, R, seed,
  * instance).
  *
- * Per step k = 0..K-1 (all integer on the device):
+ * Per step k = 0..K-1 (all integer on the device; g = k unless beta_adapt):
  *   1. S sweeps over `order`; for node i of replica r:
  *      m = -x_i h_i with h_i = sum_j w_ij x_j; accept iff m <= 0 or
- *      draw(0, s, k, i, r) < floor(2^32 exp(-(beta_k gamma^l * 2m))); the best
+ *      draw(0, s, k, i, r) < floor(2^32 exp(-(beta_g gamma^l * 2m))); the best
  *      configuration is tracked after every sweep.
  *   2. Every nl_period steps: the non-local move of kind nl_kind (Houdayer
  *      cluster move on replica pairs, or a Wolff update of every replica),
  *      then a best check.
  *   3. Noise level update (adaptive stochasticity).
- *   4. If k < K-1: weights floor(2^32 exp(-((beta_{k+1}-beta_k)(E_r-E_min)))),
- *      systematic resampling back to R replicas.
+ *   4. If g < K-1: weights floor(2^32 exp(-((beta_{k+1}-beta_k)(E_r-E_min))))
+ *      (adaptive steps: of the chosen jump), systematic resampling back to R
+ *      replicas.
  * draw(tag, s, k, i, r) is word (r & 3) of Philox4x32-10 with key
  * (lo32 seed, hi32 seed) and counter (i, s | tag << 16, k, (r >> 2) | instance << 16).
  */

@@ -19,8 +19,8 @@
 //     8 or 16 replicas, spins as byte records, bytewise neighbour counts.
 //   sweep_kernel (kernel 2): one lane = one replica, W = 16, 32 or 64 replicas
 //     as bit words; for degrees above 127 and as an independent check.
-//   epilogue_kernel: best tracking, noise level, reweighting and systematic
-//     resampling of a step (one workgroup).
+//   epilogue_kernel: best tracking, noise level, the adaptive step's jump,
+//     reweighting and systematic resampling of a step (one workgroup).
 //   icm_kernel / icm_apply_kernel: the cluster move on replica pairs;
 //     wolff_kernel (+ icm_apply_kernel): the single-replica cluster update.
 //   gather_kernel: resampling copies for kernel 2 (kernel 1 reads through the

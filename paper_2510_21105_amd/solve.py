@@ -38,6 +38,11 @@ def _args(argv):
     ap.add_argument("--order", choices=("natural", "coloring"), default="natural")
     ap.add_argument("--no-as", action="store_true", help="adaptive stochasticity off")
     ap.add_argument("--nl-period", type=int, default=10, help="cluster move every P steps (0 off)")
+    ap.add_argument("--nl-kind", type=int, choices=(0, 1), default=0,
+                    help="0: cluster moves on replica pairs; 1: single-replica cluster updates")
+    ap.add_argument("--adaptive", type=int, nargs=3, metavar=("JUMP", "NUM", "DEN"),
+                    help="adaptive steps over the --steps grid: jumps of up to JUMP grid points "
+                         "while the reweighted population keeps NUM/DEN of its effective size")
     ap.add_argument("--seed", type=int, default=42)
     ap.add_argument("--instance", type=int, default=0)
     ap.add_argument("--hex-out", help="write the best configuration here")
@@ -65,7 +70,10 @@ def main(argv=None) -> dict:
     wl = dict(graph=g, betas=W.linear_betas(a.beta[0], a.beta[1], a.steps), sweeps=a.sweeps,
               order=order, R=a.replicas, seed=a.seed, inst=a.instance,
               as_enable=0 if a.no_as else 1, as_stall_steps=20, as_max_level=4,
-              as_frozen_inv=256, as_gamma=0.8, nl_period=a.nl_period)
+              as_frozen_inv=256, as_gamma=0.8, nl_period=a.nl_period, nl_kind=a.nl_kind)
+    if a.adaptive:
+        wl.update(beta_adapt=1, adapt_jump=a.adaptive[0], adapt_num=a.adaptive[1],
+                  adapt_den=a.adaptive[2])
     s = pa.Solver(g)
     p = pa.params_from_workload(wl)
     t0 = time.perf_counter()

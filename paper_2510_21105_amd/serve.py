@@ -6,8 +6,13 @@ the runs in flight, plus the new one (``pa_workspace_bytes``), fit an HBM
 budget; each admitted run is enqueued with ``pa_run`` on its own HIP stream,
 and its completion is detected with an event. Every result is the result of
 the same run alone (runs are pure functions of their inputs), whatever the mix
-it was served in. Argument marshalling and scheduling only: all annealing work
-runs in the library's kernels.
+it was served in. Requests still waiting can be cancelled. Argument
+marshalling and scheduling only: all annealing work runs in the library's
+kernels.
+
+The admission policy (``Admission``) is plain Python with no device calls, so
+its paths (queueing under the budget, refusal of requests larger than the
+budget, cancellation) are testable without a GPU.
 """
 from __future__ import annotations
 
@@ -35,10 +40,61 @@ class Result:
     best_cut: int
     best_E: int
     workspace_bytes: int
+    cancelled: bool = False
 
     @property
     def latency(self) -> float:
         return self.finish - self.arrival
+
+
+class Admission:
+    """Arrival-order admission under a byte budget and a number of slots.
+
+    ``arrive(rid, nbytes)`` queues a request (ValueError if it can never fit);
+    ``cancel(rid)`` drops a waiting request (False if it was already admitted
+    or unknown); ``admit()`` returns the rids that start now, oldest first,
+    stopping at the first that does not fit (no overtaking); ``finish(rid)``
+    returns a running request's bytes and slot.
+    """
+
+    def __init__(self, budget: int, slots: int):
+        if budget < 1 or slots < 1:
+            raise ValueError("budget and slots must be positive")
+        self.budget, self.slots = int(budget), int(slots)
+        self.used = 0
+        self.waiting: deque = deque()       # (rid, nbytes)
+        self.running: dict = {}             # rid -> nbytes
+
+    def arrive(self, rid, nbytes: int) -> None:
+        if nbytes > self.budget:
+            raise ValueError(f"request {rid} needs {nbytes} workspace bytes, more than the "
+                             f"budget {self.budget}")
+        self.waiting.append((rid, int(nbytes)))
+
+    def cancel(self, rid) -> bool:
+        for q, (r, _) in enumerate(self.waiting):
+            if r == rid:
+                del self.waiting[q]
+                return True
+        return False
+
+    def admit(self) -> list:
+        out = []
+        while self.waiting and len(self.running) < self.slots:
+            rid, nb = self.waiting[0]
+            if self.used + nb > self.budget:
+                break
+            self.waiting.popleft()
+            self.running[rid] = nb
+            self.used += nb
+            out.append(rid)
+        return out
+
+    def finish(self, rid) -> None:
+        self.used -= self.running.pop(rid)
+
+    def idle(self) -> bool:
+        return not self.waiting and not self.running
 
 
 @dataclass
@@ -66,63 +122,58 @@ class Server:
             raise ValueError("n_streams must be >= 1")
         self._streams = [torch.cuda.Stream() for _ in range(self.n_streams)]
 
-    def serve(self, requests, realtime: bool = True) -> list:
+    def serve(self, requests, realtime: bool = True, cancel=()) -> list:
         """Serve ``requests`` (arrival times honoured when ``realtime``, else all
-        present at once); return one Result per request in completion order."""
+        present at once); return one Result per request in completion order.
+        ``cancel`` holds (time, rid) pairs: at that time the request is dropped
+        if it is still waiting (reported with ``cancelled``), else it runs."""
         import torch
         pending = deque(sorted(requests, key=lambda r: (r.arrival, r.rid)))
-        waiting: deque = deque()
-        flights: list = []
+        cancels = deque(sorted(cancel))
+        adm = Admission(self.hbm_budget, self.n_streams)
         free = list(self._streams)
-        used = 0
+        flights = {}
+        prepared = {}       # rid -> (request, solver, workspace bytes), made once on arrival
         results = []
         t0 = time.perf_counter()
-        prepared = {}       # rid -> (solver, workspace bytes), made once on arrival
-        while pending or waiting or flights:
+        while pending or not adm.idle():
             now = time.perf_counter() - t0
             while pending and (not realtime or pending[0].arrival <= now):
                 req = pending.popleft()
                 solver = pa.Solver(req.graph)
                 need = solver.workspace_bytes(req.params) + 256
-                if need > self.hbm_budget:
-                    raise ValueError(f"request {req.rid} needs {need} workspace bytes, "
-                                     f"more than the budget {self.hbm_budget}")
-                prepared[req.rid] = (solver, need)
-                waiting.append(req)
+                adm.arrive(req.rid, need)
+                prepared[req.rid] = (req, solver, need)
+            while cancels and (not realtime or cancels[0][0] <= now):
+                _, rid = cancels.popleft()
+                if rid in prepared and adm.cancel(rid):
+                    req, solver, need = prepared.pop(rid)
+                    solver.close()
+                    t = time.perf_counter() - t0
+                    results.append(Result(rid, req.arrival, t, t, 0, 0, need, cancelled=True))
             # completions
-            still = []
-            for f in flights:
+            for rid, f in list(flights.items()):
                 if f.event.query():
                     t = time.perf_counter() - t0
                     cut = f.solver.best_cut()
                     info = f.solver.best_info()
-                    results.append(Result(f.req.rid, f.req.arrival, f.start, t, cut, info["E"],
-                                          f.nbytes))
-                    used -= f.nbytes
+                    results.append(Result(rid, f.req.arrival, f.start, t, cut, info["E"], f.nbytes))
+                    adm.finish(rid)
                     free.append(f.stream)
                     f.solver.close()
-                else:
-                    still.append(f)
-            flights = still
+                    del flights[rid]
             # admissions, in arrival order
-            admitted = False
-            while waiting and free:
-                req = waiting[0]
-                solver, need = prepared[req.rid]
-                if used + need > self.hbm_budget:
-                    break
-                waiting.popleft()
-                del prepared[req.rid]
-                admitted = True
+            started = adm.admit()
+            for rid in started:
+                req, solver, need = prepared.pop(rid)
                 stream = free.pop()
                 ws = torch.empty(need, dtype=torch.uint8, device="cuda")
                 start = time.perf_counter() - t0
                 solver.run(req.params, stream=stream, workspace=ws)
                 ev = torch.cuda.Event()
                 ev.record(stream)
-                flights.append(_Flight(req, solver, stream, ev, start, need))
-                used += need
-            if not admitted:
+                flights[rid] = _Flight(req, solver, stream, ev, start, need)
+            if not started:
                 time.sleep(self.poll_s)
         return results
 

@@ -357,6 +357,14 @@ def test_served_requests_equal_solo_runs(pa):
         g, p = items[r.rid]
         solo = pa.Solver(g).run(p)
         assert r.best_cut == solo.best_cut() and r.best_E == solo.best_info()["E"]
+    # the last request is still waiting when cancelled; the others are unchanged
+    res2 = srv.serve([S.Request(j, g, p, 0.0) for j, (g, p) in enumerate(items)], realtime=False,
+                     cancel=[(0.0, len(items) - 1)])
+    got = {r.rid: r for r in res2}
+    assert got[len(items) - 1].cancelled and sorted(got) == list(range(len(items)))
+    for r in res:
+        if r.rid != len(items) - 1:
+            assert not got[r.rid].cancelled and got[r.rid].best_cut == r.best_cut
 
 
 def test_cluster_moves_on_a_collapsing_population(pa):

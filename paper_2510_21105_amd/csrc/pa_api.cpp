@@ -892,6 +892,7 @@ static pa_status start_run(pa_solver *s, const pa_schedule *sch, int32_t R, uint
     sa.lmax1 = P.lmax1;
     sa.n_levels = P.n_levels;
     sa.K = P.K;
+    sa.adapt = sch->beta_adapt;
     sa.seed_lo = seed_lo;
     sa.seed_hi = seed_hi;
     sa.inst = instance;
@@ -1003,6 +1004,7 @@ static pa_status run_range(pa_solver *s, int k0, int k1)
             ic.G = P.G;
             ic.k = k;
             ic.K = P.K;
+            ic.adapt = c.adapt;
             ic.nw32 = P.nw32;
             ic.seed_lo = seed_lo;
             ic.seed_hi = seed_hi;

@@ -40,6 +40,7 @@ struct SweepArgs {
     int S;            // sweeps in this step
     int k;            // step index (Philox counter)
     int K;            // grid points; as_state[3] >= K marks a finished run
+    int adapt;        // adaptive steps: the grid point is as_state[3], else k
     int lmax1;        // number of noise levels
     int n_levels;
     uint32_t seed_lo, seed_hi, inst;
@@ -104,6 +105,7 @@ struct GatherArgs {
 struct IcmArgs {
     GraphDev g;
     int R, G, k, K, nw32;
+    int adapt;                  // adaptive steps: grid point as_state[3], else k
     int kind;                   // 0: pairs (p, p + R/2); 1: single-replica Wolff update
     int lmax1;                  // noise levels per step in qtab
     uint32_t seed_lo, seed_hi, inst;

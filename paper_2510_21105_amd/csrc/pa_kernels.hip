@@ -265,7 +265,8 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs a, const int2 *__
                                                     const uint4 *__restrict__ blocks)
 {
     // A finished run (adaptive steps past the last grid point): nothing to do.
-    if (a.as_state[3] >= a.K) return;
+    const int gk = a.adapt ? a.as_state[3] : a.k;
+    if (gk >= a.K) return;
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int NS = 64 / W;      // node slots per wave
     constexpr int GPS = W / 4;      // Philox calls per slot
@@ -318,7 +319,7 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs a, const int2 *__
         if constexpr (W == 64) lds_put<W>(zoff + 4, 0u);
     }
     const int level = a.as_state[0];
-    const uint64_t *trow = a.thr + ((size_t)a.as_state[3] * a.lmax1 + level) * (size_t)(a.dmax + 1);
+    const uint64_t *trow = a.thr + ((size_t)gk * a.lmax1 + level) * (size_t)(a.dmax + 1);
     for (int m = tid; m <= a.dmax; m += blockDim.x) T[m] = m == 0 ? (1ull << 32) : trow[m];
     if (tid < W) Eblk[tid] = (r0 + tid < a.R) ? a.E[r0 + tid] : 0;
     if (tid == 0) {
@@ -617,7 +618,8 @@ template <int W, bool SIGNED, bool DIRECT>
 __global__ __launch_bounds__(1024) void sweep_bytes_kernel(SweepArgs a, const int4 *__restrict__ rounds,
                                                           const uint4 *__restrict__ blocks)
 {
-    if (a.as_state[3] >= a.K) {
+    const int gk = a.adapt ? a.as_state[3] : a.k;     // grid point of this step
+    if (gk >= a.K) {
         // A finished run (adaptive steps past the last grid point): carry the
         // population over to the output buffer unchanged (the parent list is
         // the identity then), each workgroup a slice.
@@ -717,7 +719,7 @@ __global__ __launch_bounds__(1024) void sweep_bytes_kernel(SweepArgs a, const in
     }
     if (tid < NR) *(lds_u32 *)(uintptr_t)(zrec + 4 * tid) = 0u;
     const int level = a.as_state[0];
-    const uint32_t *trow = a.thr32 + ((size_t)a.as_state[3] * a.lmax1 + level) * (size_t)(a.dmax + 1);
+    const uint32_t *trow = a.thr32 + ((size_t)gk * a.lmax1 + level) * (size_t)(a.dmax + 1);
     // Move byte 0x80 + (m - 1) of an uphill move indexes T[m]; the lower half
     // (downhill moves, accepted by mask) stays zero.
     for (int m = tid; m < 256; m += nt) T[m] = m >= 128 && m - 128 < a.dmax ? trow[m - 128] : 0u;
@@ -1064,8 +1066,8 @@ __global__ __launch_bounds__(1024) void epilogue_kernel(EpiArgs a)
     __shared__ long long w_sum[16];
     __shared__ long long par_total;
     __shared__ int admissible[kMaxJump + 1];
-    const int g = a.as_state[3];       // grid point of this step's inverse temperature
-    if (g >= a.K) return;              // finished run (adaptive steps)
+    const int g = a.adapt ? a.as_state[3] : a.k;   // grid point of this step's inverse temperature
+    if (g >= a.K) return;                          // finished run (adaptive steps)
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int nt = blockDim.x, nwv = nt >> 6;
     const int R = a.R;
@@ -1388,7 +1390,7 @@ int icm_lds_bytes(int n, int nw32)
 
 __global__ __launch_bounds__(kIcmThreads) void icm_kernel(IcmArgs a)
 {
-    if (a.as_state[3] >= a.K) return;      // finished run
+    if (a.adapt && a.as_state[3] >= a.K) return;      // finished run
     // LDS: P = union-find parents [n], bitmaps A = spins of replica a,
     // D = disagreement set, V = cluster (nw words each).
     extern __shared__ __align__(16) uint32_t lds[];
@@ -1577,7 +1579,7 @@ __global__ __launch_bounds__(kIcmThreads) void icm_kernel(IcmArgs a)
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kIcmThreads) void wolff_kernel(IcmArgs a)
 {
-    if (a.as_state[3] >= a.K) return;      // finished run
+    if (a.adapt && a.as_state[3] >= a.K) return;      // finished run
     // LDS: P = union-find parents [n], A = spins of the replica, V = cluster.
     extern __shared__ __align__(16) uint32_t lds[];
     __shared__ long long red_l[16];
@@ -1608,7 +1610,7 @@ __global__ __launch_bounds__(kIcmThreads) void wolff_kernel(IcmArgs a)
         }
     }
     __syncthreads();
-    const uint64_t q = a.qtab[(size_t)a.as_state[3] * a.lmax1 + a.as_state[0]];
+    const uint64_t q = a.qtab[(size_t)(a.adapt ? a.as_state[3] : a.k) * a.lmax1 + a.as_state[0]];
     auto bit = [&](const uint32_t *B, uint32_t i) { return (B[i >> 5] >> (i & 31)) & 1u; };
     // Active bonds: a lane takes 8 edges of the (shuffled) edge list and draws
     // only for the satisfied ones.
@@ -1683,7 +1685,7 @@ __global__ __launch_bounds__(kIcmThreads) void wolff_kernel(IcmArgs a)
 // replicas' bits of nodes 32w..32w+31 with ballots.
 __global__ __launch_bounds__(256) void icm_apply_kernel(IcmArgs a)
 {
-    if (a.as_state[3] >= a.K) return;      // finished run
+    if (a.adapt && a.as_state[3] >= a.K) return;      // finished run
     const int lane = threadIdx.x & 63;
     const int w = blockIdx.x * 4 + (threadIdx.x >> 6);
     const int g = blockIdx.y;

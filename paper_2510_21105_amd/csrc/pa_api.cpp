@@ -747,6 +747,7 @@ static pa_status start_run(pa_solver *s, const pa_schedule *sch, int32_t R, uint
     // Host staging buffers of the previous run may still be in flight.
     if (s->has_run && s->stream) HIP_TRY(hipStreamSynchronize(s->stream));
     s->has_run = false;
+    s->rc.valid = false;          // until this run's state is complete in the workspace
     Plan p;
     st = build_plan(s, sch, R, p, true);
     if (st != PA_OK) return st;
@@ -922,7 +923,7 @@ static pa_status start_run(pa_solver *s, const pa_schedule *sch, int32_t R, uint
     s->ev_used = 0;
 
     pa_solver::RunCtx &c = s->rc;
-    c.valid = true;
+    c.valid = fresh;              // a restored run becomes valid once its state is loaded
     c.key = run_key(s, sch, R, seed, instance);
     c.next_step = 0;
     c.parents_pending = false;
@@ -1454,6 +1455,7 @@ extern "C" pa_status pa_checkpoint_load(pa_solver *s, const pa_schedule *sch, in
         at += (q.bytes + 7) & ~size_t(7);
     }
     HIP_TRY(hipStreamSynchronize(s->stream));
+    s->rc.valid = true;
     s->rc.next_step = h.next_step;
     s->rc.parents_pending = false;
     s->ev_first = s->ev_used = h.next_step;

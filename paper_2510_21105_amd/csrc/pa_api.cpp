@@ -69,6 +69,7 @@ struct Plan {
     int lmax1 = 1, n_levels = 0, record = 0;
     int kind = 2, sgn = 0, block_bytes = 0, qpad = 0, n_rounds = 0, flush_every = 1;
     int direct = 0;   // kernel 1: block entries are LDS byte offsets (else record indices)
+    int bsg = 0;      // kernel 1 records: 0 unsigned, 1 complemented copies, 2 sign bits in entries
     std::vector<int> sched, level_off;
     std::vector<uint32_t> blocks;   // [n][block_bytes / 4] + 128 B
     std::vector<int> stream;        // kernel 2: [waves][qpad][2]
@@ -324,13 +325,15 @@ static void build_blocks(const pa_solver *s, Plan &p)
         // Kernel 1: u16 {node, degree, neighbour record indices...}, padded
         // with the zero record's index to 8m - 2 entries (a multiple of 16
         // bytes with the header, at least the degree rounded up to 4).
-        // Negative edges name the complemented record n + j. Record indices
+        // Negative edges name the complemented record n + j (record mode 1)
+        // or carry a sign bit, bit 0 of a byte offset or bit 15 of an index
+        // (record mode 2). Record indices
         // count from the start of LDS (the threshold table occupies the first
         // rb records). Blocks n .. n + threads - 1 are all-padding blocks:
         // a lane reads the block of slot (first slot of its round + lane),
         // which may lie past the last node.
         const int rb = pa::kBytesRecBase / p.W;     // records start after the threshold table
-        const int zrec = p.sgn ? 2 * n : n;         // index of the zero record
+        const int zrec = p.bsg == 1 ? 2 * n : n;    // index of the zero record
         // Entries are LDS byte offsets when every record's offset fits in 16
         // bits (one instruction to decode), else record indices.
         p.direct = pa::kBytesRecBase + zrec * p.W <= 0xFFFF;
@@ -353,7 +356,10 @@ static void build_blocks(const pa_solver *s, Plan &p)
             for (int e = e0; e < e1; ++e) {
                 const int j = s->col[e];
                 const bool neg = e >= e0 + s->npos[i];
-                b[2 + (e - e0)] = enc(neg ? n + j : j);
+                if (p.bsg == 2)
+                    b[2 + (e - e0)] = (uint16_t)(enc(j) | (neg ? (p.direct ? 1u : 0x8000u) : 0u));
+                else
+                    b[2 + (e - e0)] = enc(neg ? n + j : j);
             }
         }
         for (int t = n; t < n + p.threads; ++t) {
@@ -483,7 +489,21 @@ static pa_status build_plan(pa_solver *s, const pa_schedule *sch, int R, Plan &p
     // (plus 2.2 KB of fixed scratch).
     if (sch->nl_period > 0 && pa::icm_lds_bytes(n, p.nw32) + 4096 > max_lds)
         return fail(PA_ERANGE, "cluster moves on %d nodes exceed the LDS of a workgroup", n);
-    auto bytes_fit = [&](int W) { return pa::sweep_bytes_lds(W, p.sgn, n, s->dmax) <= max_lds; };
+    // Kernel 1 on a signed graph reads complemented copies of the records for
+    // negative edges (no per-neighbour work), or marks them with a sign bit in
+    // the block entry (one XOR per neighbour, half the LDS). Measured on
+    // MI355X: sign bits pay on low-degree graphs whose workgroups (8 replicas
+    // each) would otherwise queue for LDS -- at least two full waves of them
+    // beyond what fits with copies (100 x 100 torus, R 16,384: 0.83 -> 0.66 ms
+    // per step); with fewer workgroups the XOR only costs (+2 to +8 % on small
+    // tori). Sign bits take bit 15 of a record index, so indices stay below 2^15.
+    p.bsg = p.sgn ? 1 : 0;
+    if (p.sgn && s->dmax <= 8 && n + pa::kBytesRecBase / 4 <= 0x7FFF) {
+        const long long per_cu = max_lds / pa::sweep_bytes_lds(8, 1, n, s->dmax);
+        if (per_cu == 0 || (R + 7) / 8 >= 2LL * cus * per_cu) p.bsg = 2;
+    }
+    const int comp = p.bsg == 1 ? 1 : 0;
+    auto bytes_fit = [&](int W) { return pa::sweep_bytes_lds(W, comp, n, s->dmax) <= max_lds; };
     auto words_fit = [&](int W) { return pa::sweep_lds_bytes(W, p.sgn, n, s->dmax, p.threads) <= max_lds; };
     int W = 0;
     // Kernel 1 compares draws with 32-bit thresholds. A row whose threshold
@@ -505,7 +525,7 @@ static pa_status build_plan(pa_solver *s, const pa_schedule *sch, int R, Plan &p
                                "acceptance rounds to 1 for some uphill moves only");
     // Record indices (complements and the zero record included, offset by the
     // threshold table) are u16.
-    const bool idx_fit = (p.sgn ? 2 * n : n) + pa::kBytesRecBase / 4 <= 0xFFFF;
+    const bool idx_fit = (p.sgn ? 2 * n : n) + pa::kBytesRecBase / 4 <= 0xFFFF;   // either mode
     bool bytes_ok = s->dmax <= kMaxBytesDegree && (tile == 0 || tile <= 16) && !partial_sat && idx_fit;
     if (req == 1 && !bytes_ok)
         return fail(PA_EINVAL, "sweep kernel 1 needs max degree <= %d and tile 4, 8 or 16", kMaxBytesDegree);
@@ -514,11 +534,13 @@ static pa_status build_plan(pa_solver *s, const pa_schedule *sch, int R, Plan &p
         if (W == 0 && s->dmax <= 8 && bytes_fit(8)) {
             // Measured on MI355X: on low-degree graphs (tori) a round's work per
             // node is small and 8-replica tiles spread the per-node cost over
-            // the most replicas, even with fewer workgroups than CUs; 256
-            // threads when two workgroups fit a CU, else 512.
+            // the most replicas, even with fewer workgroups than CUs. 512
+            // threads, or 256 when two workgroups fit a CU and there are fewer
+            // than four workgroups per CU in all.
             W = 8;
             if (sch->wg_threads == 0)
-                p.threads = 2 * pa::sweep_bytes_lds(8, p.sgn, n, s->dmax) <= max_lds ? 256 : 512;
+                p.threads = 2 * pa::sweep_bytes_lds(8, comp, n, s->dmax) <= max_lds && (R + 7) / 8 < 4 * cus
+                                ? 256 : 512;
         }
         if (W == 0) {
             // Measured on MI355X: two resident workgroups of 512 threads per CU
@@ -526,13 +548,13 @@ static pa_status build_plan(pa_solver *s, const pa_schedule *sch, int R, Plan &p
             // allows two per CU and that still gives two workgroups per CU;
             // else the narrowest tile that fits (most workgroups).
             for (int w = 16; w >= 4 && W == 0; w >>= 1)
-                if (2 * pa::sweep_bytes_lds(w, p.sgn, n, s->dmax) <= max_lds && (R + w - 1) / w >= 2 * cus)
+                if (2 * pa::sweep_bytes_lds(w, comp, n, s->dmax) <= max_lds && (R + w - 1) / w >= 2 * cus)
                     W = w;
             for (int w = 4; w <= 16 && W == 0; w <<= 1)
                 if (bytes_fit(w)) W = w;
             if (W == 0) W = 4;
             if (sch->wg_threads == 0)
-                p.threads = 2 * pa::sweep_bytes_lds(W, p.sgn, n, s->dmax) <= max_lds ? 512 : 1024;
+                p.threads = 2 * pa::sweep_bytes_lds(W, comp, n, s->dmax) <= max_lds ? 512 : 1024;
         }
         if (!bytes_fit(W)) {
             if (req == 1)
@@ -977,7 +999,7 @@ static pa_status run_range(pa_solver *s, int k0, int k1)
             sa.X = reinterpret_cast<uint64_t *>(ws + Xn);
             sa.E = reinterpret_cast<int *>(ws + En);
             sa.parent = c.parents_pending ? reinterpret_cast<const int *>(ws + L.parent) : nullptr;
-            LAUNCH_TRY(pa::launch_sweep_bytes(P.W, P.sgn, P.threads, P.nblk, sa, hs));
+            LAUNCH_TRY(pa::launch_sweep_bytes(P.W, P.bsg, P.threads, P.nblk, sa, hs));
             std::swap(Xc, Xn);
             std::swap(Ec, En);
             c.parents_pending = false;
@@ -1312,7 +1334,7 @@ extern "C" pa_status pa_get_launch_info(pa_solver *s, int64_t out[8])
     out[1] = P.W;
     out[2] = P.threads;
     out[3] = P.nblk;
-    out[4] = P.kind == 1 ? pa::sweep_bytes_lds(P.W, P.sgn, s->n, s->dmax)
+    out[4] = P.kind == 1 ? pa::sweep_bytes_lds(P.W, P.bsg == 1 ? 1 : 0, s->n, s->dmax)
                          : pa::sweep_lds_bytes(P.W, P.sgn, s->n, s->dmax, P.threads);
     out[5] = P.n_levels;
     out[6] = P.kind == 1 ? P.n_rounds : P.qpad - 4;

@@ -614,10 +614,16 @@ __device__ __forceinline__ int wave_sum_dpp(int v)
     return __builtin_amdgcn_readlane(v, 63);
 }
 
-template <int W, bool SIGNED, bool DIRECT>
+// SG: 0 = all weights positive; 1 = negative edges read a complemented copy of
+// the neighbour's record (records twice as many); 2 = negative edges carry a
+// sign bit in their block entry and the record is complemented on reading
+// (half the LDS of mode 1, one XOR per neighbour).
+template <int W, int SG, bool DIRECT>
 __global__ __launch_bounds__(1024) void sweep_bytes_kernel(SweepArgs a, const int4 *__restrict__ rounds,
                                                           const uint4 *__restrict__ blocks)
 {
+    constexpr bool SIGNED = SG == 1;     // complemented records in LDS
+    constexpr bool SBIT = SG == 2;       // sign bits in the block entries
     const int gk = a.adapt ? a.as_state[3] : a.k;     // grid point of this step
     if (gk >= a.K) {
         // A finished run (adaptive steps past the last grid point): carry the
@@ -758,6 +764,21 @@ __global__ __launch_bounds__(1024) void sweep_bytes_kernel(SweepArgs a, const in
     unsigned int att = 0, acc = 0;
     constexpr int SHW = W == 4 ? 2 : (W == 8 ? 3 : 4);   // record index -> LDS byte offset
     constexpr int SHC = DIRECT ? 0 : SHW;                // block entry -> LDS byte offset
+    // A 16-bit block entry names a neighbour record: an LDS byte offset
+    // (DIRECT) or a record index. With sign bits, bit 0 of an offset (records
+    // are at least 4-byte aligned) or bit 15 of an index marks a negative
+    // edge, whose record is read complemented (0x01 in every byte).
+    auto ent_off = [](uint32_t e) -> uint32_t {
+        if constexpr (!SBIT) return e << SHC;
+        else if constexpr (DIRECT) return e & 0xFFFEu;
+        else return (e & 0x7FFFu) << SHW;
+    };
+    auto ent_neg = [](uint32_t e) -> uint32_t {
+        if constexpr (!SBIT) return 0u;
+        else if constexpr (DIRECT) return (e & 1u) * 0x01010101u;
+        else return (e >> 15) * 0x01010101u;
+    };
+    const uint32_t zent = DIRECT ? zrec : zrec >> SHW;   // entry of the zero record
 
     Blk bufA, bufB;
     int4 rd = rounds[0];                          // the current round
@@ -830,10 +851,12 @@ __global__ __launch_bounds__(1024) void sweep_bytes_kernel(SweepArgs a, const in
             // compiler from moving the draws after the first use of the reads).
             // Lanes past their degree read the zero record.
             const Rec<NR> X = rec_load<NR>(noff);
-            const Rec<NR> g0 = rec_load<NR>((cur.b0.y & 0xFFFFu) << SHC);
-            const Rec<NR> g1 = rec_load<NR>((cur.b0.y >> 16) << SHC);
-            const Rec<NR> g2 = rec_load<NR>((cur.b0.z & 0xFFFFu) << SHC);
-            const Rec<NR> g3 = rec_load<NR>((cur.b0.z >> 16) << SHC);
+            const uint32_t e0 = cur.b0.y & 0xFFFFu, e1 = cur.b0.y >> 16;
+            const uint32_t e2 = cur.b0.z & 0xFFFFu, e3 = cur.b0.z >> 16;
+            const Rec<NR> g0 = rec_load<NR>(ent_off(e0));
+            const Rec<NR> g1 = rec_load<NR>(ent_off(e1));
+            const Rec<NR> g2 = rec_load<NR>(ent_off(e2));
+            const Rec<NR> g3 = rec_load<NR>(ent_off(e3));
             __builtin_amdgcn_sched_barrier(0);
             uint32_t dr[NR][4];
 #pragma unroll
@@ -846,13 +869,17 @@ __global__ __launch_bounds__(1024) void sweep_bytes_kernel(SweepArgs a, const in
             __builtin_amdgcn_sched_barrier(0);
             uint32_t C[NR];
 #pragma unroll
-            for (int q = 0; q < NR; ++q) C[q] = (g0.v[q] + g1.v[q]) + (g2.v[q] + g3.v[q]);
-#define PA_NB(off)                                              \
+            for (int q = 0; q < NR; ++q)
+                C[q] = ((g0.v[q] ^ ent_neg(e0)) + (g1.v[q] ^ ent_neg(e1))) +
+                       ((g2.v[q] ^ ent_neg(e2)) + (g3.v[q] ^ ent_neg(e3)));
+#define PA_NB(ent)                                              \
     {                                                           \
-        const Rec<NR> nb = rec_load<NR>(off);                   \
-        _Pragma("unroll") for (int q = 0; q < NR; ++q) C[q] += nb.v[q]; \
+        const uint32_t e_ = (ent);                              \
+        const Rec<NR> nb = rec_load<NR>(ent_off(e_));           \
+        const uint32_t m_ = ent_neg(e_);                        \
+        _Pragma("unroll") for (int q = 0; q < NR; ++q) C[q] += nb.v[q] ^ m_; \
     }
-#define PA_W(w) PA_NB(((w) & 0xFFFFu) << SHC) PA_NB(((w) >> 16) << SHC)
+#define PA_W(w) PA_NB((w) & 0xFFFFu) PA_NB((w) >> 16)
             {
                 if (md > 4) {
                     PA_W(cur.b0.w) PA_W(cur.b1.x)
@@ -872,8 +899,8 @@ __global__ __launch_bounds__(1024) void sweep_bytes_kernel(SweepArgs a, const in
                                                 const uint16_t *rest = reinterpret_cast<const uint16_t *>(
                                                     blocks + (size_t)(active ? t : rd.x) * bu4) + 2;
                                                 for (int kk = kBlkCols; kk < md; ++kk) {
-                                                    const uint32_t off = active ? (uint32_t)rest[kk] << SHC : zrec;
-                                                    PA_NB(off)
+                                                    const uint32_t ent = active ? (uint32_t)rest[kk] : zent;
+                                                    PA_NB(ent)
                                                 }
                                             }
                                         }
@@ -1786,10 +1813,10 @@ int launch_sweep(int W, int sgn, int threads, int nblk, const SweepArgs &a, void
     }
 }
 
-template <int W, bool SG, bool D>
+template <int W, int SG, bool D>
 static int launch_bytes_t(int threads, int nblk, const SweepArgs &a, void *stream)
 {
-    const int lds = sweep_bytes_lds(W, SG ? 1 : 0, a.n, a.dmax);
+    const int lds = sweep_bytes_lds(W, SG == 1 ? 1 : 0, a.n, a.dmax);
     static int configured = 0;
     if (configured < lds) {
         if (hipFuncSetAttribute(reinterpret_cast<const void *>(&sweep_bytes_kernel<W, SG, D>),
@@ -1805,10 +1832,12 @@ static int launch_bytes_t(int threads, int nblk, const SweepArgs &a, void *strea
 template <int W>
 static int launch_bytes_w(int sgn, int threads, int nblk, const SweepArgs &a, void *stream)
 {
-    if (sgn) return a.direct ? launch_bytes_t<W, true, true>(threads, nblk, a, stream)
-                             : launch_bytes_t<W, true, false>(threads, nblk, a, stream);
-    return a.direct ? launch_bytes_t<W, false, true>(threads, nblk, a, stream)
-                    : launch_bytes_t<W, false, false>(threads, nblk, a, stream);
+    if (sgn == 2) return a.direct ? launch_bytes_t<W, 2, true>(threads, nblk, a, stream)
+                                  : launch_bytes_t<W, 2, false>(threads, nblk, a, stream);
+    if (sgn == 1) return a.direct ? launch_bytes_t<W, 1, true>(threads, nblk, a, stream)
+                                  : launch_bytes_t<W, 1, false>(threads, nblk, a, stream);
+    return a.direct ? launch_bytes_t<W, 0, true>(threads, nblk, a, stream)
+                    : launch_bytes_t<W, 0, false>(threads, nblk, a, stream);
 }
 
 int launch_sweep_bytes(int W, int sgn, int threads, int nblk, const SweepArgs &a, void *stream)

@@ -638,3 +638,17 @@ def test_adaptive_steps_checkpoint_and_resume(pa):
     _assert_same(_results(b), full)
     ref = O.run_workload(wl, want_counts=False)
     assert np.array_equal(full["stats"], ref.stats) and np.array_equal(full["x"], ref.x)
+
+
+@pytest.mark.parametrize("L,R,tile", [(80, 4096, 8), (100, 16384, 4)])
+def test_sign_bit_records_on_large_populations(pa, L, R, tile):
+    """Signed tori with enough workgroups that kernel 1 marks negative edges by
+    sign bits in the block entries (byte-offset entries in both cases) instead
+    of complemented records: the whole population equals the oracle's."""
+    base = W.workload("torus100")
+    g = W.torus(L, 4, True, f"torus{L}")
+    wl = dict(base, graph=g, order=W.checkerboard_order(L), R=R, betas=base["betas"][:2], sweeps=3)
+    s, _ = _compare(pa, g, wl, dict(tile_replicas=tile), record=0)
+    info = s.launch_info()
+    # one record per node and replica (no complemented copies)
+    assert info["lds_bytes"] < 2 * g.n * tile, info

@@ -32,6 +32,39 @@ def test_philox_known_answers():
         assert [int(t) for t in out] == v[6:10]
 
 
+@pytest.mark.gpu
+@pytest.mark.parametrize("seed", [0x0123456789ABCDEF, 42, 2 ** 64 - 1])
+def test_philox_against_rocrand(seed):
+    """The oracle's Philox4x32-10 against rocRAND's (an implementation this
+    project did not write, installed with ROCm; its host generator needs the
+    HIP runtime with a device). rocRAND's stream for a seed is the words of
+    Philox(counter i as a 128-bit integer, key = (lo32 seed, hi32 seed)),
+    i = 0, 1, ...; an offset of 4 (2^32 - 2) numbers crosses into the second
+    counter word."""
+    import ctypes
+    try:
+        L = ctypes.CDLL("/opt/rocm/lib/librocrand.so")
+    except OSError:
+        pytest.skip("rocRAND not installed")
+    key = [seed & 0xFFFFFFFF, seed >> 32]
+    for offset, ctrs in [(0, [(i, 0, 0, 0) for i in range(8)]),
+                         (4 * (2 ** 32 - 2), [(2 ** 32 - 2, 0, 0, 0), (2 ** 32 - 1, 0, 0, 0),
+                                              (0, 1, 0, 0), (1, 1, 0, 0)])]:
+        gen = ctypes.c_void_p()
+        if L.rocrand_create_generator_host_blocking(ctypes.byref(gen), 404) != 0:   # PHILOX4_32_10
+            pytest.skip("rocRAND host generator unavailable")
+        try:
+            assert L.rocrand_set_seed(gen, ctypes.c_ulonglong(seed)) == 0
+            assert L.rocrand_set_offset(gen, ctypes.c_ulonglong(offset)) == 0
+            out = np.zeros(4 * len(ctrs), dtype=np.uint32)
+            assert L.rocrand_generate(gen, out.ctypes.data_as(ctypes.c_void_p),
+                                      ctypes.c_size_t(out.shape[0])) == 0
+        finally:
+            L.rocrand_destroy_generator(gen)
+        want = np.concatenate([O.philox(list(c), key) for c in ctrs])
+        assert np.array_equal(out, want), (hex(seed), offset)
+
+
 def test_draw_layout():
     """A draw is word (r & 3) of the Philox block keyed by the seed."""
     seed, inst = 0x1234_5678_9ABC_DEF0, 7

@@ -1290,17 +1290,24 @@ __global__ __launch_bounds__(1024) void epilogue_kernel(EpiArgs a)
             const U4 o = philox10(U4{0u, 2u << 16, (uint32_t)a.k, a.inst << 16}, a.seed_lo, a.seed_hi);
             const uint64_t U = (uint64_t)o.x | ((uint64_t)o.y << 32);
             const uint64_t u = __umul64hi(U, S);
-            uint64_t C = excl;
-            uint64_t fprev = sys_f(C, (uint64_t)R, u, S);
+            // f(c) counts the sampling points u + j S below R c: one division
+            // for this thread's first replica, then walk the points (each step
+            // is one copy written), so no division per replica.
+            uint64_t f = sys_f(excl, (uint64_t)R, u, S);
+            uint64_t pt = u + f * S;                    // next sampling point
+            uint64_t RC = (uint64_t)R * excl;
             long long parents = 0;
             for (int r = lo; r < hi; ++r) {
                 const int nn = Esh[r] - emin;
-                C += nn < len ? a.wtab[off + nn] : 0ull;
-                const uint64_t f = sys_f(C, (uint64_t)R, u, S);
-                for (uint64_t q = fprev; q < f; ++q) a.parent[q] = r;
-                if (a.counts_rec) a.counts_rec[(size_t)a.k * R + r] = (int)(f - fprev);
-                parents += f > fprev;
-                fprev = f;
+                RC += (uint64_t)R * (nn < len ? a.wtab[off + nn] : 0ull);
+                const uint64_t f0 = f;
+                while (pt < RC) {
+                    a.parent[f] = r;
+                    ++f;
+                    pt += S;
+                }
+                if (a.counts_rec) a.counts_rec[(size_t)a.k * R + r] = (int)(f - f0);
+                parents += f > f0;
             }
             parents = wave_sum_ll(parents);
             if (lane == 0 && parents) atomicAdd((unsigned long long *)&par_total, (unsigned long long)parents);

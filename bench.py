@@ -233,7 +233,8 @@ def main():
                          "(for scaling HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported",
+        print(f"bench.py: the engine runs on one GPU; --gpus {args.gpus} is not supported "
+              "(the multi-GPU design is replica sharding, not built)",
               file=sys.stderr)
         sys.exit(2)
 

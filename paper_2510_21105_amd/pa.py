@@ -81,7 +81,7 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with "
-                              "`python -c 'import __graft_entry__ as g; g.build()'`")
+                              "`python -m paper_2510_21105_amd.build`")
         L = ctypes.CDLL(LIB_PATH)
         P, i32, i64, u32, u64 = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64,
                                  ctypes.c_uint32, ctypes.c_uint64)

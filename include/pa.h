@@ -91,7 +91,10 @@ typedef struct {
                                  with those weights. The run ends after the step at the
                                  last grid point (at most K steps; later steps are
                                  empty). The paper adapts the annealing without
-                                 defining how (section 3); this is one definition.  */
+                                 defining how (section 3); this is one definition.
+                                 pa_run then looks every 64 steps, with a stream
+                                 synchronisation, whether the run has ended, and
+                                 enqueues no further steps once it has.           */
     int32_t adapt_jump;       /* 1..64, largest jump in grid points (beta_adapt = 1)  */
     int32_t adapt_num, adapt_den; /* target, 0 <= adapt_num <= adapt_den <= 65536, den >= 1 */
 } pa_schedule;

@@ -152,6 +152,14 @@ pa_status pa_workspace_bytes(const pa_solver *s, const pa_schedule *sch, int32_t
  *      replicas.
  * draw(tag, s, k, i, r) is word (r & 3) of Philox4x32-10 with key
  * (lo32 seed, hi32 seed) and counter (i, s | tag << 16, k, (r >> 2) | instance << 16).
+ *
+ * Errors: PA_EINVAL (a malformed schedule field), PA_ERANGE (a count out of
+ * range: R, instance, sweeps_per_step, as_max_level; or a graph whose spin
+ * state does not fit a workgroup's LDS: every graph with +1 weights fits, a
+ * graph with -1 weights fits up to 32,511 nodes at max degree <= 127 and
+ * about 23,500 nodes above),
+ * PA_EWORKSPACE (workspace short or misaligned), PA_EDEVICE (HIP error; text
+ * in pa_last_error). All checks happen before any device work is enqueued.
  */
 pa_status pa_run(pa_solver *s, const pa_schedule *sch, int32_t R, uint64_t seed,
                  uint32_t instance, void *workspace, size_t workspace_bytes, void *stream);

@@ -502,6 +502,13 @@ static pa_status build_plan(pa_solver *s, const pa_schedule *sch, int R, Plan &p
         const long long per_cu = max_lds / pa::sweep_bytes_lds(8, 1, n, s->dmax);
         if (per_cu == 0 || (R + 7) / 8 >= 2LL * cus * per_cu) p.bsg = 2;
     }
+    // Large signed graphs (above about 20,000 nodes) whose complemented
+    // records do not fit a workgroup's LDS even at 4 replicas take sign bits,
+    // which halve the records, rather than the word kernel (which holds 2n
+    // words of a signed graph and n sweep-order entries).
+    if (p.bsg == 1 && n + pa::kBytesRecBase / 4 <= 0x7FFF &&
+        pa::sweep_bytes_lds(4, 1, n, s->dmax) > max_lds && pa::sweep_bytes_lds(4, 0, n, s->dmax) <= max_lds)
+        p.bsg = 2;
     const int comp = p.bsg == 1 ? 1 : 0;
     auto bytes_fit = [&](int W) { return pa::sweep_bytes_lds(W, comp, n, s->dmax) <= max_lds; };
     auto words_fit = [&](int W) { return pa::sweep_lds_bytes(W, p.sgn, n, s->dmax, p.threads) <= max_lds; };
@@ -525,7 +532,8 @@ static pa_status build_plan(pa_solver *s, const pa_schedule *sch, int R, Plan &p
                                "acceptance rounds to 1 for some uphill moves only");
     // Record indices (complements and the zero record included, offset by the
     // threshold table) are u16.
-    const bool idx_fit = (p.sgn ? 2 * n : n) + pa::kBytesRecBase / 4 <= 0xFFFF;   // either mode
+    const bool idx_fit = p.bsg == 2 ? n + pa::kBytesRecBase / 4 <= 0x7FFF
+                                    : (p.sgn ? 2 * n : n) + pa::kBytesRecBase / 4 <= 0xFFFF;
     bool bytes_ok = s->dmax <= kMaxBytesDegree && (tile == 0 || tile <= 16) && !partial_sat && idx_fit;
     if (req == 1 && !bytes_ok)
         return fail(PA_EINVAL, "sweep kernel 1 needs max degree <= %d and tile 4, 8 or 16", kMaxBytesDegree);

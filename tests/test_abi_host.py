@@ -100,6 +100,27 @@ def test_create_rejects_sizes():
     assert _create(40000, np.zeros(40001, np.int32), [], []) == pa.PA_ERANGE
 
 
+def _star(leaves):
+    g = W.from_edges(leaves + 1, np.zeros(leaves, np.int64), np.arange(1, leaves + 1), None)
+    return g.row_ptr, g.col, g.w
+
+
+def test_size_limits_are_inclusive():
+    """n <= 32767, degree <= 4096 and R <= 32768 are accepted at the limit and
+    refused one past it."""
+    assert _create(2, [0, 0, 0], [], []) == pa.PA_OK
+    assert _create(32767, np.zeros(32768, np.int32), [], []) == pa.PA_OK
+    assert _create(32768, np.zeros(32769, np.int32), [], []) == pa.PA_ERANGE
+    assert _create(4097, *_star(4096)) == pa.PA_OK
+    assert _create(4098, *_star(4097)) == pa.PA_ERANGE
+    wl = W.workload("small800")
+    s = pa.Solver(wl["graph"])
+    assert s.workspace_bytes(pa.params_from_workload(wl, R=32768)) > 0
+    with pytest.raises(pa.PAError) as e:
+        s.workspace_bytes(pa.params_from_workload(wl, R=32769))
+    assert e.value.status == pa.PA_ERANGE
+
+
 def _bytes(s, p):
     return s.workspace_bytes(p)
 

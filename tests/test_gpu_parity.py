@@ -652,3 +652,45 @@ def test_sign_bit_records_on_large_populations(pa, L, R, tile):
     info = s.launch_info()
     # one record per node and replica (no complemented copies)
     assert info["lds_bytes"] < 2 * g.n * tile, info
+
+
+# ------------------------------------------------------- maximum sizes ----
+
+def _signed_ring(n: int, seed: int):
+    """Ring lattice on n nodes with neighbours at distance 1 and 2 (degree 4),
+    +-1 weights from the SplitMix64 stream of ``seed``."""
+    i = np.concatenate([np.arange(n), np.arange(n)])
+    j = np.concatenate([(np.arange(n) + 1) % n, (np.arange(n) + 2) % n])
+    sgn = np.where(W.splitmix64(seed, i.shape[0]) & np.uint64(1), -1, 1)
+    return W.from_edges(n, i, j, sgn, f"ring{n}")
+
+
+def _max_case(name):
+    if name == "R32768":
+        return W.random_graph(120, 400, 31, "r120"), 32768
+    if name == "n32767":
+        return W.random_graph(32767, 98301, 32, "n32767"), 40
+    if name == "signed32511":
+        return _signed_ring(32511, 33), 40
+    if name == "deg4096":
+        return _cycle_with_hub(5000, 4096), 24
+    raise KeyError(name)
+
+
+@pytest.mark.parametrize("name", ["R32768", "n32767", "signed32511", "deg4096"])
+def test_maximum_sizes(pa, name):
+    """The documented limits: the largest population (R = 32,768, so 16,384
+    pair moves per call), the most nodes (32,767, cluster moves with their LDS
+    near full), the largest signed graph that kernel 1 holds (32,511 nodes,
+    sign-bit records with bit-15 index entries) and the largest degree (4,096,
+    served by the word kernel). Whole population, statistics and best record
+    against the oracle, with noise levels and a cluster move every step."""
+    g, R = _max_case(name)
+    wl = dict(W.workload("small800"), graph=g, R=R, betas=W.linear_betas(0.3, 1.5, 3), sweeps=2,
+              order=W.natural_order(g.n), nl_period=1, as_stall_steps=1, as_frozen_inv=8)
+    s, _ = _compare(pa, g, wl, record=1)
+    info = s.launch_info()
+    if name == "signed32511":
+        assert info["sweep_kernel"] == 1 and info["lds_bytes"] < 2 * g.n * info["tile_replicas"], info
+    if name == "deg4096":
+        assert info["sweep_kernel"] == 2, info

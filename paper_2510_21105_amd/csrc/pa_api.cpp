@@ -58,8 +58,10 @@ constexpr size_t kAlign = 256;
 size_t align_up(size_t b, size_t a = kAlign) { return (b + a - 1) / a * a; }
 
 struct Layout {
-    size_t row_ptr, col, npos, edges, vout, qtab, sched, level_off, blocks, stream, thr, wtab, wtab_off,
-        wtab_len;
+    // Host inputs, uploaded together: [0, inputs_end).
+    size_t row_ptr, col, npos, edges, qtab, sched, level_off, blocks, stream, thr, wtab, wtab_off,
+        wtab_len, inputs_end;
+    size_t vout;
     size_t X0, X1, E0, E1, cand, snap, counters, as_state, best, best_x, stats, parent;
     size_t counts, xinit, total;
 };
@@ -112,6 +114,12 @@ struct pa_solver {
         pa::SweepArgs sa{};
         pa::EpiArgs ea{};
     } rc;
+    // Pinned host copy of a run's inputs in workspace layout, uploaded with one
+    // copy; the event marks the end of the last upload from it.
+    unsigned char *stage = nullptr;
+    size_t stage_cap = 0;
+    hipEvent_t stage_ev = nullptr;
+    bool stage_pending = false;
     // timing
     int timing = 0;
     std::vector<hipEvent_t> ev;
@@ -207,6 +215,9 @@ extern "C" pa_status pa_destroy(pa_solver *s)
 {
     if (!s) return PA_OK;
     if (s->has_run && s->stream) (void)hipStreamSynchronize(s->stream);
+    if (s->stage_pending) (void)hipEventSynchronize(s->stage_ev);
+    if (s->stage_ev) (void)hipEventDestroy(s->stage_ev);
+    if (s->stage) (void)hipHostFree(s->stage);
     for (hipEvent_t e : s->ev) (void)hipEventDestroy(e);
     delete s;
     return PA_OK;
@@ -685,9 +696,6 @@ static pa_status build_plan(pa_solver *s, const pa_schedule *sch, int R, Plan &p
     L.col = take(sizeof(int) * s->nnz);
     L.npos = take(sizeof(int) * n);
     L.edges = take(sizeof(uint32_t) * s->edges.size());
-    L.vout = sch->nl_period > 0
-                 ? take(sizeof(uint32_t) * (size_t)(sch->nl_kind == 1 ? R : R / 2) * p.nw32)
-                 : 0;
     L.qtab = sch->nl_period > 0 && sch->nl_kind == 1 ? take(sizeof(uint64_t) * (size_t)p.K * p.lmax1) : 0;
     L.sched = take(sizeof(int) * n);
     L.level_off = take(sizeof(int) * (p.n_levels + 1));
@@ -697,6 +705,10 @@ static pa_status build_plan(pa_solver *s, const pa_schedule *sch, int R, Plan &p
     L.wtab = take(sizeof(uint64_t) * (size_t)total);
     L.wtab_off = take(sizeof(int) * p.K);
     L.wtab_len = take(sizeof(int) * p.K);
+    L.inputs_end = o;
+    L.vout = sch->nl_period > 0
+                 ? take(sizeof(uint32_t) * (size_t)(sch->nl_kind == 1 ? R : R / 2) * p.nw32)
+                 : 0;
     L.X0 = take(sizeof(uint64_t) * (size_t)p.G * n);
     L.X1 = take(sizeof(uint64_t) * (size_t)p.G * n);
     L.E0 = take(sizeof(int) * p.Rp);
@@ -774,7 +786,8 @@ static pa_status start_run(pa_solver *s, const pa_schedule *sch, int32_t R, uint
     if (instance > 65535) return fail(PA_ERANGE, "instance=%u outside [0, 65535]", instance);
     if (!workspace) return fail(PA_EWORKSPACE, "workspace is null");
     if (((uintptr_t)workspace) % kAlign) return fail(PA_EWORKSPACE, "workspace must be 256-byte aligned");
-    // Host staging buffers of the previous run may still be in flight.
+    // The previous run may still be using its workspace (perhaps this one, from
+    // another stream).
     if (s->has_run && s->stream) HIP_TRY(hipStreamSynchronize(s->stream));
     s->has_run = false;
     s->rc.valid = false;          // until this run's state is complete in the workspace
@@ -794,36 +807,45 @@ static pa_status start_run(pa_solver *s, const pa_schedule *sch, int32_t R, uint
     HIP_TRY(hipGetDevice(&s->device));
     const int n = s->n;
 
-    HIP_TRY(hipMemcpyAsync(ws + L.row_ptr, s->row_ptr.data(), sizeof(int) * (n + 1), hipMemcpyHostToDevice, hs));
-    if (s->nnz)
-        HIP_TRY(hipMemcpyAsync(ws + L.col, s->col.data(), sizeof(int) * s->nnz, hipMemcpyHostToDevice, hs));
-    HIP_TRY(hipMemcpyAsync(ws + L.npos, s->npos.data(), sizeof(int) * n, hipMemcpyHostToDevice, hs));
-    if (!s->edges.empty())
-        HIP_TRY(hipMemcpyAsync(ws + L.edges, s->edges.data(), sizeof(uint32_t) * s->edges.size(),
-                               hipMemcpyHostToDevice, hs));
-    HIP_TRY(hipMemcpyAsync(ws + L.sched, P.sched.data(), sizeof(int) * n, hipMemcpyHostToDevice, hs));
-    HIP_TRY(hipMemcpyAsync(ws + L.level_off, P.level_off.data(), sizeof(int) * (P.n_levels + 1),
-                           hipMemcpyHostToDevice, hs));
-    HIP_TRY(hipMemcpyAsync(ws + L.blocks, P.blocks.data(), sizeof(uint32_t) * P.blocks.size(),
-                           hipMemcpyHostToDevice, hs));
+    // All host inputs go through the pinned staging buffer in one copy.
+    if (s->stage_pending) {
+        HIP_TRY(hipEventSynchronize(s->stage_ev));
+        s->stage_pending = false;
+    }
+    if (s->stage_cap < L.inputs_end) {
+        if (s->stage) HIP_TRY(hipHostFree(s->stage));
+        s->stage = nullptr;
+        s->stage_cap = 0;
+        HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&s->stage), L.inputs_end, hipHostMallocDefault));
+        std::memset(s->stage, 0, L.inputs_end);
+        s->stage_cap = L.inputs_end;
+    }
+    if (!s->stage_ev) HIP_TRY(hipEventCreateWithFlags(&s->stage_ev, hipEventDisableTiming));
+    auto put = [&](size_t off, const void *src, size_t bytes) {
+        if (bytes) std::memcpy(s->stage + off, src, bytes);
+    };
+    put(L.row_ptr, s->row_ptr.data(), sizeof(int) * (n + 1));
+    put(L.col, s->col.data(), sizeof(int) * s->nnz);
+    put(L.npos, s->npos.data(), sizeof(int) * n);
+    put(L.edges, s->edges.data(), sizeof(uint32_t) * s->edges.size());
+    put(L.sched, P.sched.data(), sizeof(int) * n);
+    put(L.level_off, P.level_off.data(), sizeof(int) * (P.n_levels + 1));
+    put(L.blocks, P.blocks.data(), sizeof(uint32_t) * P.blocks.size());
     if (P.kind == 1)
-        HIP_TRY(hipMemcpyAsync(ws + L.stream, P.rounds.data(), sizeof(int) * P.rounds.size(),
-                               hipMemcpyHostToDevice, hs));
+        put(L.stream, P.rounds.data(), sizeof(int) * P.rounds.size());
     else
-        HIP_TRY(hipMemcpyAsync(ws + L.stream, P.stream.data(), sizeof(int) * P.stream.size(),
-                               hipMemcpyHostToDevice, hs));
-    if (!P.qtab.empty())
-        HIP_TRY(hipMemcpyAsync(ws + L.qtab, P.qtab.data(), sizeof(uint64_t) * P.qtab.size(),
-                               hipMemcpyHostToDevice, hs));
+        put(L.stream, P.stream.data(), sizeof(int) * P.stream.size());
+    put(L.qtab, P.qtab.data(), sizeof(uint64_t) * P.qtab.size());
     if (P.kind == 1)
-        HIP_TRY(hipMemcpyAsync(ws + L.thr, P.thr32.data(), sizeof(uint32_t) * P.thr32.size(),
-                               hipMemcpyHostToDevice, hs));
+        put(L.thr, P.thr32.data(), sizeof(uint32_t) * P.thr32.size());
     else
-        HIP_TRY(hipMemcpyAsync(ws + L.thr, P.thr.data(), sizeof(uint64_t) * P.thr.size(),
-                               hipMemcpyHostToDevice, hs));
-    HIP_TRY(hipMemcpyAsync(ws + L.wtab, P.wtab.data(), sizeof(uint64_t) * P.wtab.size(), hipMemcpyHostToDevice, hs));
-    HIP_TRY(hipMemcpyAsync(ws + L.wtab_off, P.wtab_off.data(), sizeof(int) * P.K, hipMemcpyHostToDevice, hs));
-    HIP_TRY(hipMemcpyAsync(ws + L.wtab_len, P.wtab_len.data(), sizeof(int) * P.K, hipMemcpyHostToDevice, hs));
+        put(L.thr, P.thr.data(), sizeof(uint64_t) * P.thr.size());
+    put(L.wtab, P.wtab.data(), sizeof(uint64_t) * P.wtab.size());
+    put(L.wtab_off, P.wtab_off.data(), sizeof(int) * P.K);
+    put(L.wtab_len, P.wtab_len.data(), sizeof(int) * P.K);
+    HIP_TRY(hipMemcpyAsync(ws, s->stage, L.inputs_end, hipMemcpyHostToDevice, hs));
+    HIP_TRY(hipEventRecord(s->stage_ev, hs));
+    s->stage_pending = true;
 
     auto U64 = [&](size_t off) { return reinterpret_cast<unsigned long long *>(ws + off); };
     if (fresh) {

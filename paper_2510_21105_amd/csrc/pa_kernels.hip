@@ -27,6 +27,8 @@
 //     parent list itself).
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "pa_device.h"
 
 namespace pa {
@@ -1758,6 +1760,28 @@ static int check(const char *what)
     return 0;
 }
 
+// Dynamic LDS beyond the default must be allowed per kernel on each device.
+// `cfg` holds, per device, the largest size allowed so far for one kernel; the
+// mutex keeps concurrent launches from lowering another's setting.
+constexpr int kMaxDevices = 64;
+static std::mutex g_lds_mu;
+
+static int allow_lds(const void *fn, int *cfg, int lds, const char *what)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return check(what);
+    if (dev < 0 || dev >= kMaxDevices) {
+        snprintf(g_err, sizeof g_err, "%s: device %d beyond the %d supported", what, dev, kMaxDevices);
+        return -1;
+    }
+    std::lock_guard<std::mutex> lock(g_lds_mu);
+    if (cfg[dev] >= lds) return 0;
+    if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess)
+        return check(what);
+    cfg[dev] = lds;
+    return 0;
+}
+
 const char *last_hip_error() { return g_err; }
 
 int launch_fill_u64(unsigned long long *p, unsigned long long v, long long count, void *stream)
@@ -1793,13 +1817,10 @@ template <int W, bool SG>
 static int launch_sweep_t(int threads, int nblk, const SweepArgs &a, void *stream)
 {
     const int lds = sweep_lds_bytes(W, SG ? 1 : 0, a.n, a.dmax, threads);
-    static int configured = 0;
-    if (configured < lds) {
-        if (hipFuncSetAttribute(reinterpret_cast<const void *>(&sweep_kernel<W, SG>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess)
-            return check("hipFuncSetAttribute(sweep)");
-        configured = lds;
-    }
+    static int configured[kMaxDevices] = {};
+    if (allow_lds(reinterpret_cast<const void *>(&sweep_kernel<W, SG>), configured, lds,
+                  "hipFuncSetAttribute(sweep)"))
+        return -1;
     hipLaunchKernelGGL((sweep_kernel<W, SG>), dim3(nblk), dim3(threads), lds, (hipStream_t)stream, a,
                        a.stream, a.level_off, a.blocks);
     return check("sweep_kernel");
@@ -1824,13 +1845,10 @@ template <int W, int SG, bool D>
 static int launch_bytes_t(int threads, int nblk, const SweepArgs &a, void *stream)
 {
     const int lds = sweep_bytes_lds(W, SG == 1 ? 1 : 0, a.n, a.dmax);
-    static int configured = 0;
-    if (configured < lds) {
-        if (hipFuncSetAttribute(reinterpret_cast<const void *>(&sweep_bytes_kernel<W, SG, D>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess)
-            return check("hipFuncSetAttribute(sweep_bytes)");
-        configured = lds;
-    }
+    static int configured[kMaxDevices] = {};
+    if (allow_lds(reinterpret_cast<const void *>(&sweep_bytes_kernel<W, SG, D>), configured, lds,
+                  "hipFuncSetAttribute(sweep_bytes)"))
+        return -1;
     hipLaunchKernelGGL((sweep_bytes_kernel<W, SG, D>), dim3(nblk), dim3(threads), lds,
                        (hipStream_t)stream, a, a.rounds, a.blocks);
     return check("sweep_bytes_kernel");
@@ -1862,13 +1880,10 @@ int launch_sweep_bytes(int W, int sgn, int threads, int nblk, const SweepArgs &a
 int launch_epilogue(const EpiArgs &a, void *stream)
 {
     const int lds = a.R * 4;
-    static int configured = 0;
-    if (configured < lds) {
-        if (hipFuncSetAttribute(reinterpret_cast<const void *>(&epilogue_kernel),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess)
-            return check("hipFuncSetAttribute(epilogue)");
-        configured = lds;
-    }
+    static int configured[kMaxDevices] = {};
+    if (allow_lds(reinterpret_cast<const void *>(&epilogue_kernel), configured, lds,
+                  "hipFuncSetAttribute(epilogue)"))
+        return -1;
     hipLaunchKernelGGL(epilogue_kernel, dim3(1), dim3(kMaxThreads), lds, (hipStream_t)stream, a);
     return check("epilogue_kernel");
 }
@@ -1884,14 +1899,10 @@ int launch_gather(const GatherArgs &a, void *stream)
 int launch_icm(const IcmArgs &a, void *stream)
 {
     const int lds = icm_lds_bytes(a.g.n, a.nw32);
-    static int configured[2] = {0, 0};
+    static int configured[2][kMaxDevices] = {};
     const void *fn = a.kind == 1 ? reinterpret_cast<const void *>(&wolff_kernel)
                                  : reinterpret_cast<const void *>(&icm_kernel);
-    if (configured[a.kind] < lds) {
-        if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess)
-            return check("hipFuncSetAttribute(cluster move)");
-        configured[a.kind] = lds;
-    }
+    if (allow_lds(fn, configured[a.kind == 1 ? 1 : 0], lds, "hipFuncSetAttribute(cluster move)")) return -1;
     if (a.kind == 1) {
         hipLaunchKernelGGL(wolff_kernel, dim3(a.R), dim3(kIcmThreads), lds, (hipStream_t)stream, a);
         if (int st = check("wolff_kernel")) return st;

@@ -1131,12 +1131,20 @@ __global__ __launch_bounds__(1024) void epilogue_kernel(EpiArgs a)
     if (a.do_cand)
         for (int b = tid; b < a.nblk; b += nt) kc = a.cand[b] < kc ? a.cand[b] : kc;
     if (need_e)
-        for (int r = tid; r < R; r += nt) {
-            const int v = a.E[r];
-            Esh[r] = v;
-            const unsigned long long kk = ((unsigned long long)((uint32_t)v ^ 0x80000000u) << 32) | (unsigned)r;
-            ke = kk < ke ? kk : ke;
-            es += v;
+        for (int r0 = tid; r0 < R; r0 += 4 * nt) {
+            int v[4];       // four independent loads in flight
+#pragma unroll
+            for (int c = 0; c < 4; ++c) v[c] = r0 + c * nt < R ? a.E[r0 + c * nt] : 0;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const int r = r0 + c * nt;
+                if (r >= R) break;
+                Esh[r] = v[c];
+                const unsigned long long kk =
+                    ((unsigned long long)((uint32_t)v[c] ^ 0x80000000u) << 32) | (unsigned)r;
+                ke = kk < ke ? kk : ke;
+                es += v[c];
+            }
         }
     kc = wave_min_u64(kc);
     ke = wave_min_u64(ke);
@@ -1229,14 +1237,23 @@ __global__ __launch_bounds__(1024) void epilogue_kernel(EpiArgs a)
             for (int j = jmax - wv; j >= 2; j -= nwv) {
                 const int oj = a.wtab_off[j - 1], lj = a.wtab_len[j - 1];
                 unsigned long long s1 = 0, q_lo = 0, q_hi = 0;    // sum W, sum W^2 (128 bit)
-                for (int r = lane; r < R; r += 64) {
-                    const int nn = Esh[r] - emin;
-                    const unsigned long long w = nn < lj ? a.wtab[oj + nn] : 0ull;
-                    s1 += w;
-                    const unsigned __int128 w2 = (unsigned __int128)w * w;
-                    const unsigned long long l2 = q_lo + (unsigned long long)w2;
-                    q_hi += (unsigned long long)(w2 >> 64) + (l2 < q_lo ? 1ull : 0ull);
-                    q_lo = l2;
+                for (int r0 = lane; r0 < R; r0 += 8 * 64) {
+                    unsigned long long wv[8];      // eight table reads in flight
+#pragma unroll
+                    for (int c = 0; c < 8; ++c) {
+                        const int r = r0 + 64 * c;
+                        const int nn = r < R ? Esh[r < R ? r : r0] - emin : lj;
+                        wv[c] = nn < lj ? a.wtab[oj + nn] : 0ull;
+                    }
+#pragma unroll
+                    for (int c = 0; c < 8; ++c) {
+                        const unsigned long long w = wv[c];
+                        s1 += w;
+                        const unsigned __int128 w2 = (unsigned __int128)w * w;
+                        const unsigned long long l2 = q_lo + (unsigned long long)w2;
+                        q_hi += (unsigned long long)(w2 >> 64) + (l2 < q_lo ? 1ull : 0ull);
+                        q_lo = l2;
+                    }
                 }
 #pragma unroll
                 for (int o = 32; o > 0; o >>= 1) {
@@ -1267,11 +1284,23 @@ __global__ __launch_bounds__(1024) void epilogue_kernel(EpiArgs a)
             for (int r = lo; r < hi; ++r) a.parent[r] = r;
         }
         if (resample) {
+            // The weights of this thread's replicas, read 8 at a time so that
+            // the table reads of a chunk are in flight together.
+            constexpr int CH = 8;
+            auto weights = [&](int r0, uint64_t (&wv)[CH]) {
+#pragma unroll
+                for (int c = 0; c < CH; ++c) {
+                    const int r = r0 + c < hi ? r0 + c : r0;
+                    const int nn = r0 + c < hi ? Esh[r] - emin : len;
+                    wv[c] = nn < len ? a.wtab[off + nn] : 0ull;
+                }
+            };
             uint64_t ws = 0;
-#pragma unroll 4
-            for (int r = lo; r < hi; ++r) {
-                const int nn = Esh[r] - emin;
-                ws += nn < len ? a.wtab[off + nn] : 0ull;
+            for (int r0 = lo; r0 < hi; r0 += CH) {
+                uint64_t wv[CH];
+                weights(r0, wv);
+#pragma unroll
+                for (int c = 0; c < CH; ++c) ws += wv[c];
             }
             // Exclusive scan of the per-thread sums: wave scan, then the wave totals.
             uint64_t inc = ws;
@@ -1299,17 +1328,23 @@ __global__ __launch_bounds__(1024) void epilogue_kernel(EpiArgs a)
             uint64_t pt = u + f * S;                    // next sampling point
             uint64_t RC = (uint64_t)R * excl;
             long long parents = 0;
-            for (int r = lo; r < hi; ++r) {
-                const int nn = Esh[r] - emin;
-                RC += (uint64_t)R * (nn < len ? a.wtab[off + nn] : 0ull);
-                const uint64_t f0 = f;
-                while (pt < RC) {
-                    a.parent[f] = r;
-                    ++f;
-                    pt += S;
+            for (int r0 = lo; r0 < hi; r0 += CH) {
+                uint64_t wv[CH];
+                weights(r0, wv);
+#pragma unroll
+                for (int c = 0; c < CH; ++c) {
+                    const int r = r0 + c;
+                    if (r >= hi) break;
+                    RC += (uint64_t)R * wv[c];
+                    const uint64_t f0 = f;
+                    while (pt < RC) {
+                        a.parent[f] = r;
+                        ++f;
+                        pt += S;
+                    }
+                    if (a.counts_rec) a.counts_rec[(size_t)a.k * R + r] = (int)(f - f0);
+                    parents += f > f0;
                 }
-                if (a.counts_rec) a.counts_rec[(size_t)a.k * R + r] = (int)(f - f0);
-                parents += f > f0;
             }
             parents = wave_sum_ll(parents);
             if (lane == 0 && parents) atomicAdd((unsigned long long *)&par_total, (unsigned long long)parents);

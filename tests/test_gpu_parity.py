@@ -624,6 +624,18 @@ def test_adaptive_steps_end_early_and_stop_enqueueing(pa):
     assert not ref.stats[6:].any()
 
 
+def test_adaptive_steps_large_ragged_population(pa):
+    """R = 10,000: the resampling reads each thread's ten weights as a chunk of
+    8 plus a ragged 2, and every jump test reads the table in chunks of 512
+    replicas with a ragged tail."""
+    g = W.random_graph(300, 1200, 19)
+    wl = dict(W.workload("small800"), graph=g, R=10000, betas=W.linear_betas(0.1, 3.0, 40),
+              sweeps=2, order=W.natural_order(g.n), nl_period=0, beta_adapt=1, adapt_jump=8,
+              adapt_num=1, adapt_den=2)
+    s, ref = _compare(pa, g, wl, record=1)
+    assert len(set(ref.stats[:, 9].tolist())) > 2
+
+
 def test_adaptive_steps_checkpoint_and_resume(pa):
     wl = W.workload("g63like")
     wl = dict(wl, R=128, betas=W.linear_betas(0.1, 5.0, 300), sweeps=2, nl_period=4, beta_adapt=1,

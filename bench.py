@@ -30,6 +30,10 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 SWEEP_SOURCE = os.path.join(ROOT, "paper_2510_21105_amd", "csrc", "pa_kernels.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_kernel_hbm_traffic_{}.json")
+INSTR_FILE = os.path.join(ROOT, "profiles", "sweep_kernel_instructions_{}.json")
+# Vector ALU issue peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (a wave64
+# instruction occupies a 16-lane SIMD for 4 cycles).
+VALU_PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
 
 
 def kernel_source_hash() -> str:
@@ -56,6 +60,20 @@ def measured_traffic_per_launch(workload: str):
     if t.get("kernel_source_sha256_16") != kernel_source_hash():
         return None
     return t.get("bytes_per_launch")
+
+
+def measured_valu_per_launch(workload: str):
+    """VALU wave64 instructions per sweep launch from the committed rocprofv3
+    instruction-count summary of this workload, or None when it is absent or
+    was taken on a different kernel source."""
+    try:
+        with open(INSTR_FILE.format(workload)) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    return t.get("valu_wave_instructions_per_launch")
 
 
 def cpu_baseline(wl, sample_steps: int):
@@ -331,6 +349,15 @@ def main():
             "unit": "GB/s", "frac": round(achieved_gbs / HBM_PEAK_GBS, 4), "traffic": traffic,
             "measured_copy_gbs": round(copy_gbs, 1),
             "frac_of_copy": round(achieved_gbs / copy_gbs, 4)}
+    # The sweep keeps its state in LDS, so beside the streaming-model figure
+    # above: the vector ALU issue rate it reaches, from the measured
+    # instruction count (not an algorithmic count) and the live launch time.
+    valu = measured_valu_per_launch(args.workload)
+    if valu is not None:
+        lane_ops = valu * 64 / avg_launch_s
+        roof["alu"] = {"achieved": float(f"{lane_ops:.4g}"), "peak": VALU_PEAK_LANE_OPS,
+                       "unit": "VALU lane-op/s", "frac": round(lane_ops / VALU_PEAK_LANE_OPS, 4),
+                       "source": "measured VALU instructions per launch (rocprofv3 SQ_INSTS_VALU)"}
 
     out = {
         "metric": "spin-flip attempts/s",

@@ -327,6 +327,8 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs a, const int2 *__
     if (tid == 0) {
         misc[0] = a.best_E[0];
         misc[1] = -1;  // no candidate (reads back as ~0ull)
+        misc[12] = 0;  // uphill attempts and accepts of this workgroup
+        misc[13] = 0;
     }
     __syncthreads();
 
@@ -483,12 +485,19 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs a, const int2 *__
         else reinterpret_cast<uint16_t *>(Xg + i)[sub] = (uint16_t)lds_word<W>(off);
     }
     if (tid < W && r0 + tid < a.R) a.E[r0 + tid] = Eblk[tid];
+    // Uphill counters: wave sums gathered in LDS, one global atomic per
+    // workgroup on the two step-wide counters.
     const long long at = wave_sum_ll((long long)att), ac = wave_sum_ll((long long)acc);
     if (lane == 0) {
-        if (at) atomicAdd(&a.counters[0], (unsigned long long)at);
-        if (ac) atomicAdd(&a.counters[1], (unsigned long long)ac);
+        if (at) atomicAdd(reinterpret_cast<unsigned long long *>(&misc[12]), (unsigned long long)at);
+        if (ac) atomicAdd(reinterpret_cast<unsigned long long *>(&misc[13]), (unsigned long long)ac);
     }
-    if (tid == 0) a.cand[blk] = (unsigned long long)misc[1];
+    __syncthreads();
+    if (tid == 0) {
+        if (misc[12]) atomicAdd(&a.counters[0], (unsigned long long)misc[12]);
+        if (misc[13]) atomicAdd(&a.counters[1], (unsigned long long)misc[13]);
+        a.cand[blk] = (unsigned long long)misc[1];
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -687,44 +696,8 @@ __global__ __launch_bounds__(1024) void sweep_bytes_kernel(SweepArgs a, const in
     }
     const bool two = gB - gA <= 1;
     const uint64_t *XA = a.Xin + (size_t)gA * n, *XB = a.Xin + (size_t)gB * n;
-    // Expand the block's spin bits into byte records, 8 loads in flight per lane.
-    for (int base = 0; base < n; base += 8 * nt) {
-        uint64_t va[8], vb[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int i = base + u * nt + tid;
-            va[u] = i < n ? XA[i] : 0ull;
-            vb[u] = i < n && !ident && two ? XB[i] : 0ull;
-        }
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int i = base + u * nt + tid;
-            if (i >= n) break;
-            uint64_t v = 0;
-            if (ident) {
-                v = field_of<W>(va[u], sub);
-            } else if (two) {
-#pragma unroll
-                for (int b = 0; b < W; ++b) {
-                    const uint64_t w = (pr[b] >> 6) == gA ? va[u] : vb[u];
-                    v |= ((w >> (pr[b] & 63)) & 1ull) << b;
-                }
-            } else {
-#pragma unroll
-                for (int b = 0; b < W; ++b)
-                    v |= ((a.Xin[(size_t)(pr[b] >> 6) * n + i] >> (pr[b] & 63)) & 1ull) << b;
-            }
-            Rec<NR> rc;
-#pragma unroll
-            for (int q = 0; q < NR; ++q) rc.v[q] = spread4((uint32_t)(v >> (4 * q)));
-            rec_store<NR>(RB + (uint32_t)i * W, rc);
-            if constexpr (SIGNED) {
-#pragma unroll
-                for (int q = 0; q < NR; ++q) rc.v[q] ^= 0x01010101u;
-                rec_store<NR>(RB + comp + (uint32_t)i * W, rc);
-            }
-        }
-    }
+    // Step tables and block state first, so that their loads overlap the
+    // population loads below.
     if (tid < NR) *(lds_u32 *)(uintptr_t)(zrec + 4 * tid) = 0u;
     const int level = a.as_state[0];
     const uint32_t *trow = a.thr32 + ((size_t)gk * a.lmax1 + level) * (size_t)(a.dmax + 1);
@@ -740,6 +713,84 @@ __global__ __launch_bounds__(1024) void sweep_bytes_kernel(SweepArgs a, const in
     if (tid == 0) {
         misc[0] = a.best_E[0];
         misc[1] = -1;  // no candidate (reads back as ~0ull)
+        misc[12] = 0;  // uphill attempts and accepts of this workgroup
+        misc[13] = 0;
+    }
+    // Expand the block's spin bits into byte records, LB nodes per lane and
+    // pass (their loads in flight together). With resampling parents in two
+    // words, slot b's spin is one bit of one 32-bit half of those words, the
+    // same for every node: the half is picked by a uniform branch per slot,
+    // so a spin costs one bit extract.
+    constexpr int LB = W >= 8 ? 4 : 8;
+    int psel[W];
+#pragma unroll
+    for (int b = 0; b < W; ++b)
+        psel[b] = __builtin_amdgcn_readfirstlane(((pr[b] >> 6) == gA ? 0 : 2) + ((pr[b] & 63) >= 32 ? 1 : 0));
+    for (int base = 0; base < n; base += LB * nt) {
+        uint64_t va[LB], vb[LB];
+#pragma unroll
+        for (int u = 0; u < LB; ++u) {
+            const int i = base + u * nt + tid;
+            va[u] = i < n ? XA[i] : 0ull;
+            vb[u] = i < n && !ident && two ? XB[i] : 0ull;
+        }
+        Rec<NR> rc[LB];
+        if (ident) {
+#pragma unroll
+            for (int u = 0; u < LB; ++u) {
+                const uint64_t v = field_of<W>(va[u], sub);
+#pragma unroll
+                for (int q = 0; q < NR; ++q) rc[u].v[q] = spread4((uint32_t)(v >> (4 * q)));
+            }
+        } else if (two) {
+#pragma unroll
+            for (int u = 0; u < LB; ++u)
+#pragma unroll
+                for (int q = 0; q < NR; ++q) rc[u].v[q] = 0u;
+#pragma unroll
+            for (int b = 0; b < W; ++b) {
+                const uint32_t sh = (uint32_t)__builtin_amdgcn_readfirstlane(pr[b] & 31);
+                const int q = b >> 2, bs = 8 * (b & 3);
+                if (psel[b] == 0) {
+#pragma unroll
+                    for (int u = 0; u < LB; ++u) rc[u].v[q] |= (((uint32_t)va[u] >> sh) & 1u) << bs;
+                } else if (psel[b] == 1) {
+#pragma unroll
+                    for (int u = 0; u < LB; ++u) rc[u].v[q] |= (((uint32_t)(va[u] >> 32) >> sh) & 1u) << bs;
+                } else if (psel[b] == 2) {
+#pragma unroll
+                    for (int u = 0; u < LB; ++u) rc[u].v[q] |= (((uint32_t)vb[u] >> sh) & 1u) << bs;
+                } else {
+#pragma unroll
+                    for (int u = 0; u < LB; ++u) rc[u].v[q] |= (((uint32_t)(vb[u] >> 32) >> sh) & 1u) << bs;
+                }
+            }
+        } else {
+#pragma unroll
+            for (int u = 0; u < LB; ++u) {
+                const int i = base + u * nt + tid;
+                uint64_t v = 0;
+                if (i < n) {
+#pragma unroll
+                    for (int b = 0; b < W; ++b)
+                        v |= ((a.Xin[(size_t)(pr[b] >> 6) * n + i] >> (pr[b] & 63)) & 1ull) << b;
+                }
+#pragma unroll
+                for (int q = 0; q < NR; ++q) rc[u].v[q] = spread4((uint32_t)(v >> (4 * q)));
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < LB; ++u) {
+            const int i = base + u * nt + tid;
+            if (i >= n) break;
+            rec_store<NR>(RB + (uint32_t)i * W, rc[u]);
+            if constexpr (SIGNED) {
+                Rec<NR> cc;
+#pragma unroll
+                for (int q = 0; q < NR; ++q) cc.v[q] = rc[u].v[q] ^ 0x01010101u;
+                rec_store<NR>(RB + comp + (uint32_t)i * W, cc);
+            }
+        }
     }
     // Bytes of real (non-padding) replicas, as 0x80 markers for the counters.
     uint32_t real80[NR];
@@ -1069,12 +1120,19 @@ __global__ __launch_bounds__(1024) void sweep_bytes_kernel(SweepArgs a, const in
         }
     }
     if (tid < W && r0 + tid < a.R) a.E[r0 + tid] = Eblk[tid];
+    // Uphill counters: wave sums gathered in LDS, one global atomic per
+    // workgroup (not per wave) on the two step-wide counters.
     const long long at = wave_sum_ll((long long)att), ac = wave_sum_ll((long long)acc);
     if (lane == 0) {
-        if (at) atomicAdd(&a.counters[0], (unsigned long long)at);
-        if (ac) atomicAdd(&a.counters[1], (unsigned long long)ac);
+        if (at) atomicAdd(reinterpret_cast<unsigned long long *>(&misc[12]), (unsigned long long)at);
+        if (ac) atomicAdd(reinterpret_cast<unsigned long long *>(&misc[13]), (unsigned long long)ac);
     }
-    if (tid == 0) a.cand[blk] = (unsigned long long)misc[1];
+    __syncthreads();
+    if (tid == 0) {
+        if (misc[12]) atomicAdd(&a.counters[0], (unsigned long long)misc[12]);
+        if (misc[13]) atomicAdd(&a.counters[1], (unsigned long long)misc[13]);
+        a.cand[blk] = (unsigned long long)misc[1];
+    }
 }
 
 // ---------------------------------------------------------------------------

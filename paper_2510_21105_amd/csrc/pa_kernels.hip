@@ -716,79 +716,120 @@ __global__ __launch_bounds__(1024) void sweep_bytes_kernel(SweepArgs a, const in
         misc[12] = 0;  // uphill attempts and accepts of this workgroup
         misc[13] = 0;
     }
-    // Expand the block's spin bits into byte records, LB nodes per lane and
-    // pass (their loads in flight together). With resampling parents in two
-    // words, slot b's spin is one bit of one 32-bit half of those words, the
-    // same for every node: the half is picked by a uniform branch per slot,
-    // so a spin costs one bit extract.
-    constexpr int LB = W >= 8 ? 4 : 8;
-    int psel[W];
+    if constexpr (W == 8) {
+        // Expand the block's spin bits into byte records, LB nodes per lane and
+        // pass (their loads in flight together). With resampling parents in two
+        // words, slot b's spin is one bit of one 32-bit half of those words, the
+        // same for every node: the half is picked by a uniform branch per slot,
+        // so a spin costs one bit extract.
+        constexpr int LB = W >= 8 ? 4 : 8;
+        int psel[W];
 #pragma unroll
-    for (int b = 0; b < W; ++b)
-        psel[b] = __builtin_amdgcn_readfirstlane(((pr[b] >> 6) == gA ? 0 : 2) + ((pr[b] & 63) >= 32 ? 1 : 0));
-    for (int base = 0; base < n; base += LB * nt) {
-        uint64_t va[LB], vb[LB];
-#pragma unroll
-        for (int u = 0; u < LB; ++u) {
-            const int i = base + u * nt + tid;
-            va[u] = i < n ? XA[i] : 0ull;
-            vb[u] = i < n && !ident && two ? XB[i] : 0ull;
-        }
-        Rec<NR> rc[LB];
-        if (ident) {
-#pragma unroll
-            for (int u = 0; u < LB; ++u) {
-                const uint64_t v = field_of<W>(va[u], sub);
-#pragma unroll
-                for (int q = 0; q < NR; ++q) rc[u].v[q] = spread4((uint32_t)(v >> (4 * q)));
-            }
-        } else if (two) {
-#pragma unroll
-            for (int u = 0; u < LB; ++u)
-#pragma unroll
-                for (int q = 0; q < NR; ++q) rc[u].v[q] = 0u;
-#pragma unroll
-            for (int b = 0; b < W; ++b) {
-                const uint32_t sh = (uint32_t)__builtin_amdgcn_readfirstlane(pr[b] & 31);
-                const int q = b >> 2, bs = 8 * (b & 3);
-                if (psel[b] == 0) {
-#pragma unroll
-                    for (int u = 0; u < LB; ++u) rc[u].v[q] |= (((uint32_t)va[u] >> sh) & 1u) << bs;
-                } else if (psel[b] == 1) {
-#pragma unroll
-                    for (int u = 0; u < LB; ++u) rc[u].v[q] |= (((uint32_t)(va[u] >> 32) >> sh) & 1u) << bs;
-                } else if (psel[b] == 2) {
-#pragma unroll
-                    for (int u = 0; u < LB; ++u) rc[u].v[q] |= (((uint32_t)vb[u] >> sh) & 1u) << bs;
-                } else {
-#pragma unroll
-                    for (int u = 0; u < LB; ++u) rc[u].v[q] |= (((uint32_t)(vb[u] >> 32) >> sh) & 1u) << bs;
-                }
-            }
-        } else {
+        for (int b = 0; b < W; ++b)
+            psel[b] = __builtin_amdgcn_readfirstlane(((pr[b] >> 6) == gA ? 0 : 2) + ((pr[b] & 63) >= 32 ? 1 : 0));
+        for (int base = 0; base < n; base += LB * nt) {
+            uint64_t va[LB], vb[LB];
 #pragma unroll
             for (int u = 0; u < LB; ++u) {
                 const int i = base + u * nt + tid;
+                va[u] = i < n ? XA[i] : 0ull;
+                vb[u] = i < n && !ident && two ? XB[i] : 0ull;
+            }
+            Rec<NR> rc[LB];
+            if (ident) {
+#pragma unroll
+                for (int u = 0; u < LB; ++u) {
+                    const uint64_t v = field_of<W>(va[u], sub);
+#pragma unroll
+                    for (int q = 0; q < NR; ++q) rc[u].v[q] = spread4((uint32_t)(v >> (4 * q)));
+                }
+            } else if (two) {
+#pragma unroll
+                for (int u = 0; u < LB; ++u)
+#pragma unroll
+                    for (int q = 0; q < NR; ++q) rc[u].v[q] = 0u;
+#pragma unroll
+                for (int b = 0; b < W; ++b) {
+                    const uint32_t sh = (uint32_t)__builtin_amdgcn_readfirstlane(pr[b] & 31);
+                    const int q = b >> 2, bs = 8 * (b & 3);
+                    if (psel[b] == 0) {
+#pragma unroll
+                        for (int u = 0; u < LB; ++u) rc[u].v[q] |= (((uint32_t)va[u] >> sh) & 1u) << bs;
+                    } else if (psel[b] == 1) {
+#pragma unroll
+                        for (int u = 0; u < LB; ++u) rc[u].v[q] |= (((uint32_t)(va[u] >> 32) >> sh) & 1u) << bs;
+                    } else if (psel[b] == 2) {
+#pragma unroll
+                        for (int u = 0; u < LB; ++u) rc[u].v[q] |= (((uint32_t)vb[u] >> sh) & 1u) << bs;
+                    } else {
+#pragma unroll
+                        for (int u = 0; u < LB; ++u) rc[u].v[q] |= (((uint32_t)(vb[u] >> 32) >> sh) & 1u) << bs;
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int u = 0; u < LB; ++u) {
+                    const int i = base + u * nt + tid;
+                    uint64_t v = 0;
+                    if (i < n) {
+#pragma unroll
+                        for (int b = 0; b < W; ++b)
+                            v |= ((a.Xin[(size_t)(pr[b] >> 6) * n + i] >> (pr[b] & 63)) & 1ull) << b;
+                    }
+#pragma unroll
+                    for (int q = 0; q < NR; ++q) rc[u].v[q] = spread4((uint32_t)(v >> (4 * q)));
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < LB; ++u) {
+                const int i = base + u * nt + tid;
+                if (i >= n) break;
+                rec_store<NR>(RB + (uint32_t)i * W, rc[u]);
+                if constexpr (SIGNED) {
+                    Rec<NR> cc;
+#pragma unroll
+                    for (int q = 0; q < NR; ++q) cc.v[q] = rc[u].v[q] ^ 0x01010101u;
+                    rec_store<NR>(RB + comp + (uint32_t)i * W, cc);
+                }
+            }
+        }
+    } else {
+        // Expand the block's spin bits into byte records, 8 loads in flight per lane.
+        for (int base = 0; base < n; base += 8 * nt) {
+            uint64_t va[8], vb[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int i = base + u * nt + tid;
+                va[u] = i < n ? XA[i] : 0ull;
+                vb[u] = i < n && !ident && two ? XB[i] : 0ull;
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int i = base + u * nt + tid;
+                if (i >= n) break;
                 uint64_t v = 0;
-                if (i < n) {
+                if (ident) {
+                    v = field_of<W>(va[u], sub);
+                } else if (two) {
+#pragma unroll
+                    for (int b = 0; b < W; ++b) {
+                        const uint64_t w = (pr[b] >> 6) == gA ? va[u] : vb[u];
+                        v |= ((w >> (pr[b] & 63)) & 1ull) << b;
+                    }
+                } else {
 #pragma unroll
                     for (int b = 0; b < W; ++b)
                         v |= ((a.Xin[(size_t)(pr[b] >> 6) * n + i] >> (pr[b] & 63)) & 1ull) << b;
                 }
+                Rec<NR> rc;
 #pragma unroll
-                for (int q = 0; q < NR; ++q) rc[u].v[q] = spread4((uint32_t)(v >> (4 * q)));
-            }
-        }
+                for (int q = 0; q < NR; ++q) rc.v[q] = spread4((uint32_t)(v >> (4 * q)));
+                rec_store<NR>(RB + (uint32_t)i * W, rc);
+                if constexpr (SIGNED) {
 #pragma unroll
-        for (int u = 0; u < LB; ++u) {
-            const int i = base + u * nt + tid;
-            if (i >= n) break;
-            rec_store<NR>(RB + (uint32_t)i * W, rc[u]);
-            if constexpr (SIGNED) {
-                Rec<NR> cc;
-#pragma unroll
-                for (int q = 0; q < NR; ++q) cc.v[q] = rc[u].v[q] ^ 0x01010101u;
-                rec_store<NR>(RB + comp + (uint32_t)i * W, cc);
+                    for (int q = 0; q < NR; ++q) rc.v[q] ^= 0x01010101u;
+                    rec_store<NR>(RB + comp + (uint32_t)i * W, rc);
+                }
             }
         }
     }

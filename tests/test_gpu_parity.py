@@ -706,3 +706,16 @@ def test_maximum_sizes(pa, name):
         assert info["sweep_kernel"] == 1 and info["lds_bytes"] < 2 * g.n * info["tile_replicas"], info
     if name == "deg4096":
         assert info["sweep_kernel"] == 2, info
+
+
+def test_large_torus_one_workgroup_per_cu(pa):
+    """A 140 x 140 signed torus (19,600 nodes, the size of the largest G-set
+    tori) with a population large enough for sign-bit records: 8-replica
+    tiles of 157 KB, one per CU, run with 1,024 threads. Whole population
+    against the oracle."""
+    base = W.workload("torus100")
+    g = W.torus(140, 81, True, "torus140")
+    wl = dict(base, graph=g, order=W.checkerboard_order(140), R=4096, betas=base["betas"][:2], sweeps=2)
+    s, _ = _compare(pa, g, wl, record=0)
+    info = s.launch_info()
+    assert info["tile_replicas"] == 8 and info["threads"] == 1024, info

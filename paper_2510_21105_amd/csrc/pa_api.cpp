@@ -550,6 +550,11 @@ static pa_status build_plan(pa_solver *s, const pa_schedule *sch, int R, Plan &p
         return fail(PA_EINVAL, "sweep kernel 1 needs max degree <= %d and tile 4, 8 or 16", kMaxBytesDegree);
     if (req != 2 && bytes_ok) {
         W = tile;
+        // A requested tile takes the thread count of the automatic plan for
+        // that tile: 512 (refined by the level rule below) when two
+        // workgroups fit a CU, else 1,024.
+        if (W != 0 && sch->wg_threads == 0)
+            p.threads = 2 * pa::sweep_bytes_lds(W, comp, n, s->dmax) <= max_lds ? 512 : 1024;
         if (W == 0 && s->dmax <= 8 && bytes_fit(8)) {
             // Measured on MI355X: on low-degree graphs (tori) a round's work per
             // node is small and 8-replica tiles spread the per-node cost over

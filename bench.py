@@ -28,6 +28,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+TIMING_STRIDE = 7
 SWEEP_SOURCE = os.path.join(ROOT, "paper_2510_21105_amd", "csrc", "pa_kernels.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_kernel_hbm_traffic_{}.json")
 INSTR_FILE = os.path.join(ROOT, "profiles", "sweep_kernel_instructions_{}.json")
@@ -313,7 +314,11 @@ def main():
     attempts = R * N * S * K
     print(f"[bench] workload {g.name}: N={N} edges={g.n_edges} R={R} K={K} S={S}",
           file=sys.stderr, flush=True)
-    solver.set_timing(True)
+    # HIP events around the sweep launch of every 7th step (7 is coprime to
+    # the cluster-move period of 10, so every phase of it is sampled): the
+    # average launch time for the roofline, with the events' own cost on a
+    # seventh of the steps only.
+    solver.set_timing(TIMING_STRIDE)
     for w in range(args.warmup):
         solver.run(params)
         torch.cuda.synchronize()

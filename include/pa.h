@@ -295,11 +295,15 @@ pa_status pa_get_counts(pa_solver *s, int32_t *out);
  * sweep (kernel 1) or longest wave pass stream (kernel 2), sweep launches}. */
 pa_status pa_get_launch_info(pa_solver *s, int64_t out[8]);
 
-/* Timing mode for measurement: when on, pa_run records HIP events around
- * each sweep-kernel launch on the run's stream; pa_get_sweep_time then
- * returns the summed sweep-kernel time in ms and the number of launches
- * (synchronising the stream). Off by default; results are unchanged. */
-pa_status pa_set_timing(pa_solver *s, int32_t on);
+/* Timing mode for measurement. every = 0: off (the default); every = n >= 1:
+ * runs started after this call record HIP events on the run's stream around
+ * the sweep-kernel launch of every step k with k mod n = 0 (n = 1: every
+ * launch; a larger n keeps the events' own cost out of most steps).
+ * pa_get_sweep_time then returns the summed time of the timed sweep
+ * launches in ms and their number (synchronising the stream). Results are
+ * unchanged. Errors: PA_EINVAL for every < 0; pa_get_sweep_time returns
+ * PA_ESTATE when the run was not timed. */
+pa_status pa_set_timing(pa_solver *s, int32_t every);
 pa_status pa_get_sweep_time(pa_solver *s, double *ms, int64_t *launches);
 
 #ifdef __cplusplus

@@ -120,8 +120,8 @@ struct pa_solver {
     size_t stage_cap = 0;
     hipEvent_t stage_ev = nullptr;
     bool stage_pending = false;
-    // timing
-    int timing = 0;
+    // timing: 0 off, else the sweep launches of every timing-th step are timed
+    int timing = 0, timing_run = 0;
     std::vector<hipEvent_t> ev;
     int ev_first = 0, ev_used = 0;
 };
@@ -982,6 +982,7 @@ static pa_status start_run(pa_solver *s, const pa_schedule *sch, int32_t R, uint
     }
     s->ev_first = 0;
     s->ev_used = 0;
+    s->timing_run = s->timing;
 
     pa_solver::RunCtx &c = s->rc;
     c.valid = fresh;              // a restored run becomes valid once its state is loaded
@@ -1029,7 +1030,9 @@ static pa_status run_range(pa_solver *s, int k0, int k1)
             if (g >= P.K) break;
         }
         sa.k = k;
-        if (s->timing) HIP_TRY(hipEventRecord(s->ev[2 * k], hs));
+        // (the stride fixed when the run started, which sized the events)
+        const bool timed = s->timing_run && k % s->timing_run == 0;
+        if (timed) HIP_TRY(hipEventRecord(s->ev[2 * k], hs));
         if (P.kind == 1) {
             // Kernel 1 reads the previous population through the resampling
             // parents and writes the other buffer (no separate gather).
@@ -1047,10 +1050,8 @@ static pa_status run_range(pa_solver *s, int k0, int k1)
             sa.E = reinterpret_cast<int *>(ws + Ec);
             LAUNCH_TRY(pa::launch_sweep(P.W, P.sgn, P.threads, P.nblk, sa, hs));
         }
-        if (s->timing) {
-            HIP_TRY(hipEventRecord(s->ev[2 * k + 1], hs));
-            s->ev_used = k + 1;
-        }
+        if (timed) HIP_TRY(hipEventRecord(s->ev[2 * k + 1], hs));
+        if (s->timing_run) s->ev_used = k + 1;
         pa::EpiArgs e = ea;
         e.k = k;
         e.E = reinterpret_cast<const int *>(ws + Ec);
@@ -1527,22 +1528,27 @@ extern "C" pa_status pa_checkpoint_load(pa_solver *s, const pa_schedule *sch, in
 extern "C" pa_status pa_set_timing(pa_solver *s, int32_t on)
 {
     if (!s) return fail(PA_EINVAL, "null solver");
-    s->timing = on ? 1 : 0;
+    if (on < 0) return fail(PA_EINVAL, "timing stride must be >= 0");
+    s->timing = on;
     return PA_OK;
 }
 
 extern "C" pa_status pa_get_sweep_time(pa_solver *s, double *ms, int64_t *launches)
 {
     if (!s || !s->has_run) return fail(PA_ESTATE, "no completed pa_run on this solver");
-    if (!s->timing) return fail(PA_ESTATE, "timing mode was off during the run");
+    const int stride = s->timing_run;
+    if (!stride) return fail(PA_ESTATE, "timing mode was off during the run");
     HIP_TRY(hipStreamSynchronize(s->stream));
     double tot = 0.0;
+    int64_t count = 0;
     for (int k = s->ev_first; k < s->ev_used; ++k) {
+        if (k % stride) continue;
         float t = 0.f;
         HIP_TRY(hipEventElapsedTime(&t, s->ev[2 * k], s->ev[2 * k + 1]));
         tot += t;
+        ++count;
     }
     if (ms) *ms = tot;
-    if (launches) *launches = s->ev_used > s->ev_first ? s->ev_used - s->ev_first : 0;
+    if (launches) *launches = count;
     return PA_OK;
 }

@@ -332,8 +332,10 @@ class Solver:
                 "rounds", "sweep_launches")
         return dict(zip(keys, (int(v) for v in out)))
 
-    def set_timing(self, on: bool):
-        _check(lib().pa_set_timing(self._h, 1 if on else 0))
+    def set_timing(self, every):
+        """Time the sweep launches of every ``every``-th step of later runs
+        (True = every step, False/0 = off)."""
+        _check(lib().pa_set_timing(self._h, int(every)))
 
     def sweep_time(self):
         ms = ctypes.c_double()

@@ -359,3 +359,12 @@ def test_checkpoint_header_is_read_back():
     import struct
     hdr = b"PACKPT01" + struct.pack("<QQ8i", 1, 56, 800, 64, 50, 1, 25, 17, 0, 1)
     assert pa.next_step(hdr) == 17
+
+
+def test_timing_stride_validation():
+    s = pa.Solver(W.cycle(10))
+    s.set_timing(3)
+    s.set_timing(0)
+    with pytest.raises(pa.PAError) as e:
+        s.set_timing(-1)
+    assert e.value.status == pa.PA_EINVAL

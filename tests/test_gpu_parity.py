@@ -719,3 +719,23 @@ def test_large_torus_one_workgroup_per_cu(pa):
     s, _ = _compare(pa, g, wl, record=0)
     info = s.launch_info()
     assert info["tile_replicas"] == 8 and info["threads"] == 1024, info
+
+
+def test_sweep_timing_samples_every_nth_step(pa):
+    """Timing mode with stride 3 times the sweep launches of steps 0, 3, 6,
+    ... only, and does not change the results."""
+    wl = dict(W.workload("small800"), betas=W.workload("small800")["betas"][:10])
+    p = pa.params_from_workload(wl, record=0)
+    s = pa.Solver(wl["graph"])
+    s.set_timing(3)
+    s.run(p)
+    ms, n = s.sweep_time()
+    assert n == 4 and ms > 0.0
+    x1, E1 = s.population()
+    s.set_timing(0)
+    s.run(p)
+    x0, E0 = s.population()
+    assert np.array_equal(x0, x1) and np.array_equal(E0, E1)
+    with pytest.raises(pa.PAError) as e:
+        s.sweep_time()
+    assert e.value.status == pa.PA_ESTATE

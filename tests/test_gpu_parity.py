@@ -139,6 +139,17 @@ def test_g63_shape_full_population_first_steps(pa):
     _compare(pa, wl["graph"], wl, record=1)
 
 
+def test_g63_shape_benchmark_configuration_first_twenty_steps(pa):
+    """The benchmark's own workload and launch shape (R = 4,096, 10 sweeps,
+    noise levels, cluster moves every 10 steps) for its first 20 steps, two
+    of them with cluster moves: population, energies, statistics, copy counts
+    and best record equal the oracle's."""
+    wl = W.workload("g63like")
+    wl = dict(wl, betas=wl["betas"][:20])
+    s, ref = _compare(pa, wl["graph"], wl, record=1)
+    assert s.launch_info()["threads"] == 448
+
+
 def test_torus_full_population_first_step(pa):
     wl = W.workload("torus100")
     wl = dict(wl, betas=wl["betas"][:2])

@@ -82,19 +82,25 @@ typedef struct {
                                      activated with probability 1 - exp(-2 beta'), and
                                      the active-bond component of a random node flips. */
     int32_t beta_adapt;       /* 0: step k sweeps at beta[k] (K steps). 1: adaptive steps:
-                                 beta[] is a grid; each step sweeps at the current grid
-                                 point g and then moves to g + j for the largest j in
-                                 [1, min(adapt_jump, K-1-g)] whose resampling weights
-                                 W_r = floor(2^32 exp(-((beta[j] - beta[0])(E_r - E_min))))
-                                 keep (sum W)^2 / (R sum W^2) >= adapt_num / adapt_den
-                                 (decided in exact integers; j = 1 if none), resampling
-                                 with those weights. The run ends after the step at the
-                                 last grid point (at most K steps; later steps are
-                                 empty). The paper adapts the annealing without
-                                 defining how (section 3); this is one definition.
-                                 pa_run then looks every 64 steps, with a stream
-                                 synchronisation, whether the run has ended, and
-                                 enqueues no further steps once it has.           */
+                                 beta[] is an evenly spaced grid; each step sweeps at the
+                                 current grid point g and then moves to g + j for the
+                                 largest j in [1, min(adapt_jump, K-1-g)] whose resampling
+                                 weights W_r = floor(2^32 exp(-((beta[j] - beta[0])
+                                 (E_r - E_min)))) keep (sum W)^2 / (R sum W^2) >=
+                                 adapt_num / adapt_den (decided in exact integers; j = 1
+                                 if none), resampling with those weights. On an evenly
+                                 spaced grid beta[j] - beta[0] is the increase
+                                 beta[g+j] - beta[g] of the jump wherever it starts, so
+                                 the reweighting is the population-annealing one; a grid
+                                 whose spacings differ by more than 1e-9 of the mean
+                                 spacing plus 8 ulps of the largest |beta| is refused
+                                 with PA_EINVAL. The run ends after the step at the last
+                                 grid point (at most K steps; later steps are empty).
+                                 The paper adapts the annealing without defining how
+                                 (section 3); this is one definition. pa_run then looks
+                                 every 64 steps, with a stream synchronisation, whether
+                                 the run has ended, and enqueues no further steps once
+                                 it has.                                          */
     int32_t adapt_jump;       /* 1..64, largest jump in grid points (beta_adapt = 1)  */
     int32_t adapt_num, adapt_den; /* target, 0 <= adapt_num <= adapt_den <= 65536, den >= 1 */
 } pa_schedule;
@@ -279,10 +285,28 @@ pa_status pa_get_population(pa_solver *s, int8_t *x, int32_t *E);
 /* Initial population (R*n int8); needs schedule.record bit 1. */
 pa_status pa_get_initial_population(pa_solver *s, int8_t *x);
 
-/* Per-step records, K*8 int64: E_min (after sweeps and cluster moves, before
- * resampling), E_sum, uphill attempts (m > 0), uphill accepts, noise level
- * used, best E after the step, replicas with at least one copy, weight sum
- * (the last two are 0 on the last step). */
+/* Fields per step in pa_get_step_stats (and per row of the statistics in a
+ * checkpoint). */
+#define PA_STAT_FIELDS 10
+
+/* Per-step records: K * PA_STAT_FIELDS int64, row k = step k, into caller
+ * memory `out` (exactly that many values are written). Fields of a row:
+ *   0  E_min: lowest energy after the step's sweeps and non-local move,
+ *      before resampling
+ *   1  E_sum: sum of the R energies at the same point
+ *   2  uphill attempts (m > 0) during the step's sweeps
+ *   3  uphill accepts
+ *   4  noise level used by the step's sweeps (0 without adaptive
+ *      stochasticity)
+ *   5  best E after the step
+ *   6  replicas with at least one copy in the resampling (0 on the last step)
+ *   7  weight sum S of the resampling (0 on the last step)
+ *   8  grid point g whose inverse temperature the step swept at (= k unless
+ *      beta_adapt)
+ *   9  grid points advanced after the step (1 unless beta_adapt; 0 on the
+ *      last step)
+ * Rows of steps that did not run (an adaptive run that ended early, or a
+ * range not yet run) are 0. Synchronises the run's stream. */
 pa_status pa_get_step_stats(pa_solver *s, int64_t *out);
 
 /* Copy counts n_r of every resampling, K*R int32 (row K-1 is zero); needs

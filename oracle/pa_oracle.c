@@ -58,10 +58,16 @@
  *         frozen_inv * (uphill accepts) < (uphill attempts) during step k
  *         then l <- min(l + 1, l_max) and stall <- 0. The level applies to the
  *         next step's sweeps. Uphill means m > 0.
- *   Adaptive steps (beta_adapt 1): beta[] is a grid of K inverse
- *         temperatures and step k sweeps at the current grid point g_k
- *         (g_0 = 0). After step k (if g_k < K-1) the run moves to
- *         g_k + j for the largest j in [1, min(J, K-1-g_k)] whose weights
+ *   Adaptive steps (beta_adapt 1): beta[] is an evenly spaced grid of K
+ *         inverse temperatures and step k sweeps at the current grid point
+ *         g_k (g_0 = 0). Population annealing reweights a step from beta to
+ *         beta' by exp(-(beta' - beta) E); a jump of j grid points from g
+ *         raises beta by beta_{g+j} - beta_g, which on an evenly spaced grid
+ *         is beta_j - beta_0 wherever the jump starts. Grids whose spacings
+ *         differ (by more than 1e-9 of the mean spacing plus 8 ulps of the
+ *         largest |beta|, the FP64 rounding of a linear grid) are refused.
+ *         After step k (if g_k < K-1) the run moves to g_k + j for the
+ *         largest j in [1, min(J, K-1-g_k)] whose weights
  *         W_r = floor(2^32 exp(-(dbeta_j (E_r - E_min)))), dbeta_j =
  *         beta_j - beta_0, keep the normalised effective population
  *         (sum W)^2 / (R sum W^2) at or above num/den (exact in 128-bit
@@ -80,8 +86,9 @@
  * Parity status: Philox is pinned by the published known-answer vectors;
  * eq. (1), brute force, closed forms, the Boltzmann distribution, the
  * free-energy estimator and the resampling/cluster invariants pin the rest.
- * The adaptive-stochasticity rule has no definition in the paper and is
- * "parity unpinned" beyond its range invariant.
+ * The adaptive-stochasticity rule has no definition in the paper; its
+ * reading above is pinned by an independent replay of (level, stall) from
+ * the per-step statistics (uphill attempts and accepts, best energy).
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -334,6 +341,20 @@ int32_t oracle_adapt_jump(int32_t R, const int32_t *E, int64_t emin, const doubl
 
 /* ------------------------------------------------------------ PA driver */
 
+/* 1 if some spacing beta[k+1] - beta[k] differs from the mean spacing
+ * (beta[K-1] - beta[0]) / (K-1) by more than 1e-9 of it plus 8 ulps of the
+ * largest |beta|. */
+static int grid_uneven(const double *beta, int32_t K)
+{
+    if (K < 3) return 0;
+    double h = (beta[K - 1] - beta[0]) / (double)(K - 1);
+    double big = fabs(beta[0]) > fabs(beta[K - 1]) ? fabs(beta[0]) : fabs(beta[K - 1]);
+    double tol = 1e-9 * fabs(h) + 8.0 * ldexp(big, -52);
+    for (int32_t k = 0; k + 1 < K; ++k)
+        if (fabs((beta[k + 1] - beta[k]) - h) > tol) return 1;
+    return 0;
+}
+
 static void best_check(int32_t R, int32_t n, const int32_t *E, const int8_t *x,
                        int64_t *best, int8_t *best_x, int32_t k, int32_t s, int *improved)
 {
@@ -355,7 +376,8 @@ static void best_check(int32_t R, int32_t n, const int32_t *E, const int8_t *x,
  *   E_out   R     final energies
  *   best    4     {best_E, step, sweep, replica}; step -1 = initial population
  *   best_x  n     best configuration (+-1)
- *   stats   K*8   per-step records (see ORACLE_STAT_FIELDS)
+ *   stats   K*ORACLE_STAT_FIELDS (K*10) per-step records, fields listed at
+ *                 ORACLE_STAT_FIELDS
  *   counts  K*R   copy counts n_r of each resampling (row K-1 unused)
  * Returns 0, or a negative value on invalid arguments.
  */
@@ -381,6 +403,7 @@ int oracle_run(int32_t n, const int32_t *row_ptr, const int32_t *col, const int8
         if (!(beta[k] >= 0.0) || !isfinite(beta[k])) return -1;
         if (k > 0 && beta[k] < beta[k - 1]) return -1;
     }
+    if (beta_adapt && grid_uneven(beta, K)) return -1;
 #ifdef _OPENMP
     if (nthreads > 0) omp_set_num_threads(nthreads);
 #else

@@ -235,6 +235,22 @@ extern "C" pa_status pa_graph_info(const pa_solver *s, int64_t out[4])
 
 // ----------------------------------------------------------------- plan ----
 
+// Adaptive steps reweight a jump of j grid points by beta[j] - beta[0], which
+// is the jump's own increase beta[g + j] - beta[g] only on an evenly spaced
+// grid. Returns the index of the first spacing beta[k + 1] - beta[k] that
+// differs from the mean spacing by more than 1e-9 of it plus 8 ulps of the
+// largest |beta| (the rounding of a linear grid in FP64), or -1 if none does.
+static int uneven_grid(const double *beta, int K)
+{
+    if (K < 3) return -1;
+    const double h = (beta[K - 1] - beta[0]) / (double)(K - 1);
+    const double big = std::max(std::fabs(beta[0]), std::fabs(beta[K - 1]));
+    const double tol = 1e-9 * std::fabs(h) + 8.0 * std::ldexp(big, -52);
+    for (int k = 0; k + 1 < K; ++k)
+        if (std::fabs((beta[k + 1] - beta[k]) - h) > tol) return k;
+    return -1;
+}
+
 static pa_status check_schedule(const pa_solver *s, const pa_schedule *sch, int R)
 {
     if (!s || !sch) return fail(PA_EINVAL, "null solver or schedule");
@@ -264,6 +280,9 @@ static pa_status check_schedule(const pa_solver *s, const pa_schedule *sch, int 
             return fail(PA_EINVAL, "adapt_jump must be in [1, %d]", pa::kMaxJump);
         if (sch->adapt_den < 1 || sch->adapt_den > 65536 || sch->adapt_num < 0 || sch->adapt_num > sch->adapt_den)
             return fail(PA_EINVAL, "adaptive target needs 0 <= adapt_num <= adapt_den <= 65536, den >= 1");
+        const int bad = uneven_grid(sch->beta, sch->n_steps);
+        if (bad >= 0)
+            return fail(PA_EINVAL, "adaptive steps need an evenly spaced beta grid (spacing %d differs)", bad);
     }
     if (sch->nl_period > 0 && sch->nl_kind == 0 && (R & 1))
         return fail(PA_EINVAL, "pair cluster moves pair replicas: R must be even");
@@ -1192,6 +1211,8 @@ extern "C" pa_status pa_build_tables(const pa_schedule *sch, int32_t d_max, int3
     if (sch->as_enable && (sch->as_max_level < 0 || sch->as_max_level > 15 || !(sch->as_gamma > 0) ||
                            sch->as_gamma > 1))
         return fail(PA_EINVAL, "pa_build_tables: noise levels need 0 <= as_max_level <= 15, 0 < gamma <= 1");
+    if (sch->beta_adapt && uneven_grid(sch->beta, sch->n_steps) >= 0)
+        return fail(PA_EINVAL, "pa_build_tables: adaptive steps need an evenly spaced beta grid");
     const int K = sch->n_steps, Lv = sch->as_enable ? sch->as_max_level + 1 : 1, D = d_max + 1;
     const int n_tab = sch->beta_adapt ? std::min(std::max(sch->adapt_jump, 1), K - 1) : K - 1;
     const size_t n_thr = (size_t)K * Lv * D, n_w = (size_t)n_tab * (size_t)(e_span + 1);

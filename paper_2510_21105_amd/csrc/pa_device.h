@@ -14,9 +14,11 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "pa.h"
+
 namespace pa {
 
-constexpr int kStatFields = 10;
+constexpr int kStatFields = PA_STAT_FIELDS;
 constexpr int kMaxJump = 64;     // largest grid jump of an adaptive step
 constexpr int kMaxThreads = 1024;
 // Kernel 1 LDS: the 256-entry u32 threshold table (indexed by a move byte),

@@ -19,8 +19,10 @@ from .workloads import Graph, from_edges
 
 
 def parse(text: str, name: str = "") -> Graph:
-    """Graph of a G-set text. Rejects self loops, repeated edges, zero
-    weights, weights outside int8 and a count of edge lines other than M."""
+    """Graph of a G-set text. The benchmark's weights are binary, +1 or -1
+    (paper section 1), which is also all the solver accepts: other weights
+    are rejected, as are self loops, repeated edges and a count of edge lines
+    other than M."""
     lines = [ln.split() for ln in text.splitlines()]
     lines = [ln for ln in lines if ln and not ln[0].startswith(("#", "%"))]
     if not lines or len(lines[0]) < 2:
@@ -42,8 +44,8 @@ def parse(text: str, name: str = "") -> Graph:
         raise ValueError("variable index outside 1..N")
     if np.any(i == j):
         raise ValueError("self loop")
-    if np.any(w == 0) or np.any(np.abs(w) > 127):
-        raise ValueError("weights must be nonzero and fit int8")
+    if np.any(np.abs(w) != 1):
+        raise ValueError("weights must be +1 or -1 (binary G-set weights)")
     lo, hi = np.minimum(i, j), np.maximum(i, j)
     key = lo * n + hi
     if np.unique(key).shape[0] != m:

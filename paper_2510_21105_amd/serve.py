@@ -41,6 +41,9 @@ class Result:
     best_E: int
     workspace_bytes: int
     cancelled: bool = False
+    best_info: dict | None = None     # {E, step, sweep, replica} of the best
+    best_x: object = None             # best configuration (n int8, +-1)
+    stats: object = None              # per-step statistics (K x PA_STAT_FIELDS int64)
 
     @property
     def latency(self) -> float:
@@ -157,7 +160,9 @@ class Server:
                     t = time.perf_counter() - t0
                     cut = f.solver.best_cut()
                     info = f.solver.best_info()
-                    results.append(Result(rid, f.req.arrival, f.start, t, cut, info["E"], f.nbytes))
+                    results.append(Result(rid, f.req.arrival, f.start, t, cut, info["E"], f.nbytes,
+                                          best_info=info, best_x=f.solver.best_config(),
+                                          stats=f.solver.step_stats()))
                     adm.finish(rid)
                     free.append(f.stream)
                     f.solver.close()

@@ -53,6 +53,24 @@ def test_schedule_layout_matches_header():
         assert getattr(pa.Schedule, f).offset == off, f
 
 
+def test_stat_field_count_matches_header():
+    """pa_get_step_stats writes K * PA_STAT_FIELDS int64: the binding and the
+    oracle read rows of the same width, and the header documents every field."""
+    from oracle import oracle as O
+    prog = '#include <stdio.h>\n#include "pa.h"\nint main(void){printf("%d\\n", PA_STAT_FIELDS);return 0;}\n'
+    with tempfile.TemporaryDirectory() as d:
+        src = os.path.join(d, "f.c")
+        exe = os.path.join(d, "f")
+        open(src, "w").write(prog)
+        subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), src, "-o", exe])
+        nf = int(subprocess.check_output([exe]).strip())
+    assert nf == pa.STAT_FIELDS == O.STAT_FIELDS == len(pa.STAT_NAMES) == 10
+    text = open(HEADER).read()
+    doc = text[text.index("#define PA_STAT_FIELDS"):text.index("pa_get_step_stats(")]
+    for f in range(nf):
+        assert re.search(rf"\n \*\s+{f}\s", doc), f"field {f} undocumented"
+
+
 def _create(n, row_ptr, col, w):
     h = ctypes.c_void_p()
     rp = np.ascontiguousarray(row_ptr, np.int32)
@@ -167,6 +185,29 @@ def test_schedule_validation(bad, status):
     with pytest.raises(pa.PAError) as e:
         _bytes(s, pa.params_from_workload(wl, **bad))
     assert e.value.status == status
+
+
+def test_adaptive_steps_need_an_evenly_spaced_grid():
+    """A jump of j grid points is reweighted by beta_j - beta_0, the jump's own
+    increase only on an evenly spaced grid: uneven grids are refused (here and
+    by pa_build_tables), linear grids in FP64 are accepted, and without
+    adaptive steps any non-decreasing schedule is fine."""
+    wl = W.workload("small800")
+    s = pa.Solver(wl["graph"])
+    geo = 0.1 * 1.05 ** np.arange(60)
+    for betas in (geo, np.r_[W.linear_betas(0.1, 3.0, 50), 3.2],
+                  np.r_[0.0, 0.0, W.linear_betas(0.1, 1.0, 10)]):
+        p = pa.params_from_workload(wl, betas=betas, beta_adapt=1)
+        with pytest.raises(pa.PAError) as e:
+            _bytes(s, p)
+        assert e.value.status == pa.PA_EINVAL and "evenly spaced" in str(e.value)
+        with pytest.raises(pa.PAError) as e:
+            pa.build_tables(p, 4, 10)
+        assert e.value.status == pa.PA_EINVAL
+        assert _bytes(s, pa.params_from_workload(wl, betas=betas)) > 0
+    for lo, hi, K in [(0.1, 5.0, 2000), (0.0, 1.5, 121), (0.2, 3.0, 41), (1e6, 1e6 + 1e-3, 300),
+                      (0.7, 0.7, 9)]:
+        assert _bytes(s, pa.params_from_workload(wl, betas=W.linear_betas(lo, hi, K), beta_adapt=1)) > 0
 
 
 def test_single_replica_cluster_moves_take_odd_populations_and_more_scratch():

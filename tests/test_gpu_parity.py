@@ -150,6 +150,34 @@ def test_g63_shape_benchmark_configuration_first_twenty_steps(pa):
     assert s.launch_info()["threads"] == 448
 
 
+def test_g63_shape_benchmark_configuration_late_schedule(pa):
+    """The benchmark's workload and launch shape (R = 4,096, 448 threads, 10
+    sweeps, cluster moves every 10 steps) over a 20-step window from the end
+    of its schedule (every 10th inverse temperature from 4.51 to 4.98): a
+    quench in which the noise level rises (one stall step) and falls back,
+    with two cluster moves. Everything equals the oracle."""
+    wl = W.workload("g63like")
+    wl = dict(wl, betas=wl["betas"][-200::10], as_stall_steps=1)
+    s, ref = _compare(pa, wl["graph"], wl, record=1)
+    assert s.launch_info()["threads"] == 448 and s.launch_info()["tile_replicas"] == 8
+    lv = ref.stats[:, 4]
+    assert lv.max() >= 1 and np.any(np.diff(lv) < 0)
+
+
+def test_step_stats_fill_exactly_k_rows(pa):
+    """pa_get_step_stats writes K * PA_STAT_FIELDS int64 and nothing past them."""
+    import ctypes
+    wl = dict(W.workload("small800"), betas=W.workload("small800")["betas"][:7])
+    s = _device_run(pa, wl["graph"], pa.params_from_workload(wl))
+    K, F = 7, pa.STAT_FIELDS
+    guard = np.int64(0x5A5A5A5A5A5A5A5A)
+    buf = np.full(K * F + 16, guard, dtype=np.int64)
+    assert pa.lib().pa_get_step_stats(s._h, ctypes.c_void_p(buf.ctypes.data)) == pa.PA_OK
+    assert np.all(buf[K * F:] == guard)
+    assert np.array_equal(buf[:K * F].reshape(K, F), s.step_stats())
+    assert not np.any(buf[:K * F] == guard)
+
+
 def test_torus_full_population_first_step(pa):
     wl = W.workload("torus100")
     wl = dict(wl, betas=wl["betas"][:2])
@@ -333,11 +361,16 @@ def test_batched_runs_equal_solo_runs(pa):
         x1, E1 = s.population()
         x2, E2 = solo.population()
         assert np.array_equal(E1, E2) and np.array_equal(x1, x2)
-    # the first instance also matches the oracle
-    w, p = wls[0], params[0]
-    ref = O.run_workload(dict(w, R=p.R), want_counts=False)
-    assert solvers[0].best_cut() == ref.best_cut
-    assert np.array_equal(solvers[0].step_stats(), ref.stats)
+    # every instance also matches the oracle: statistics, population, best
+    for w, p, s in zip(wls, params, solvers):
+        ref = O.run_workload(dict(w, R=p.R), want_counts=False)
+        assert np.array_equal(s.step_stats(), ref.stats), w["desc"]
+        x, E = s.population()
+        assert np.array_equal(E, ref.E) and np.array_equal(x, ref.x), w["desc"]
+        info = s.best_info()
+        assert (info["E"], info["step"], info["sweep"], info["replica"]) == \
+            (ref.best_E, ref.best_step, ref.best_sweep, ref.best_replica), w["desc"]
+        assert np.array_equal(s.best_config(), ref.best_x), w["desc"]
 
 
 def test_greedy_coloring_order(pa):
@@ -368,6 +401,13 @@ def test_served_requests_equal_solo_runs(pa):
         g, p = items[r.rid]
         solo = pa.Solver(g).run(p)
         assert r.best_cut == solo.best_cut() and r.best_E == solo.best_info()["E"]
+        # and the oracle's run of the same request: statistics, best record, configuration
+        ref = O.run(g, p.betas, p.sweeps, p.R, p.seed, p.inst, p.order, want_population=False,
+                    want_counts=False)
+        assert np.array_equal(r.stats, ref.stats), r.rid
+        assert r.best_info == dict(E=ref.best_E, step=ref.best_step, sweep=ref.best_sweep,
+                                   replica=ref.best_replica), r.rid
+        assert np.array_equal(r.best_x, ref.best_x) and r.best_cut == ref.best_cut, r.rid
     # the last request is still waiting when cancelled; the others are unchanged
     res2 = srv.serve([S.Request(j, g, p, 0.0) for j, (g, p) in enumerate(items)], realtime=False,
                      cancel=[(0.0, len(items) - 1)])

@@ -85,8 +85,10 @@ def test_weights_default_to_one_and_comments_are_skipped():
     ("3 2\n1 2 1\n2 1 1\n", "repeated"),
     ("3 1\n1 4 1\n", "outside"),
     ("3 1\n0 2 1\n", "outside"),
-    ("3 1\n1 2 0\n", "nonzero"),
-    ("3 1\n1 2 200\n", "int8"),
+    ("3 1\n1 2 0\n", "binary"),
+    ("3 1\n1 2 200\n", "binary"),
+    ("3 1\n1 2 2\n", "binary"),
+    ("3 1\n1 2 -3\n", "binary"),
     ("", "start"),
 ])
 def test_bad_files_are_rejected(text, msg):

@@ -119,10 +119,148 @@ def test_weight_matches_high_precision_exp(dbeta):
     assert O.weight(0.0, 10 ** 6) == 2 ** 32
 
 
-def test_level_beta_products():
-    assert O.level_beta(2.0, 0.8, 0) == 2.0
-    assert O.level_beta(2.0, 0.8, 3) == 2.0 * (0.8 * 0.8 * 0.8)
-    assert abs(O.level_beta(1.0, 0.8, 4) - 0.8 ** 4) < 1e-15
+@pytest.mark.parametrize("beta,gamma", [(2.0, 0.8), (0.37, 0.8), (4.9, 0.7), (1e-3, 0.5), (3.0, 1.0)])
+def test_level_beta_against_exact_product(beta, gamma):
+    """A noise level l sweeps at beta * gamma^l. Against the exact rational
+    product of the FP64 inputs: l + 1 roundings leave a relative error of at
+    most (l + 1) 2^-53, and the thresholds at that inverse temperature are
+    the 60-digit floor of 2^32 exp(-2 m beta gamma^l) up to that error."""
+    from fractions import Fraction
+    for level in range(0, 16):
+        exact = Fraction(beta) * Fraction(gamma) ** level
+        got = O.level_beta(beta, gamma, level)
+        assert abs(Fraction(got) - exact) <= exact * Fraction(level + 1, 2 ** 53)
+        if level in (0, 1, 4, 15):
+            b = Decimal(exact.numerator) / Decimal(exact.denominator)
+            getcontext().prec = 60
+            for m in (1, 2, 7, 29):
+                v = (-(b * 2 * m)).exp() * (Decimal(2) ** 32)
+                t = O.threshold(got, m)
+                # the FP64 product can move the exact value by a relative
+                # (l + 1) 2^-53 in beta, i.e. 2 m beta (l + 1) 2^-53 in the exponent
+                slack = v * Decimal(2 * m) * b * Decimal(level + 2) / Decimal(2 ** 52) + Decimal("1e-6")
+                assert int(v - slack) - 1 <= t <= int(v + slack) + 1
+    assert O.level_beta(beta, gamma, 0) == beta
+
+
+# ------------------------------------------ adaptive stochasticity ----
+
+def _replay_levels(stats, best0, stall_steps, frozen_inv, lmax, variant=""):
+    """The noise-level rule written out from its statement, fed only with the
+    per-step statistics: level l_k used by step k's sweeps; after step k, if
+    the best energy fell during the step then l = 0 and the stall count is 0;
+    otherwise the stall count grows by one, and once it reaches stall_steps
+    while frozen_inv * (uphill accepts) < (uphill attempts) the level rises
+    by one (at most lmax) and the stall count restarts. ``variant`` plants
+    one plausible misreading, for the discrimination check."""
+    level, stall, best = 0, 0, best0
+    used = []
+    for row in stats:
+        used.append(level)
+        att, acc, best_after = int(row[2]), int(row[3]), int(row[5])
+        improved = best_after < best
+        best = best_after
+        if improved and variant != "keep_level_on_improvement":
+            level, stall = 0, 0
+            continue
+        if improved:
+            stall = 0
+            continue
+        stall += 1
+        due = stall > stall_steps if variant == "strict_stall" else stall >= stall_steps
+        frozen = (frozen_inv * acc <= att) if variant == "frozen_le" else (frozen_inv * acc < att)
+        if due and frozen:
+            level = min(level + 1, lmax)
+            if variant != "no_stall_reset":
+                stall = 0
+    return np.array(used)
+
+
+AS_RUNS = [
+    dict(graph=(300, 1200, 21), R=16, as_stall_steps=1, as_frozen_inv=4, nl_period=3),
+    dict(graph=(300, 1200, 21), R=32, as_stall_steps=1, as_frozen_inv=8, nl_period=4,
+         as_max_level=3, as_gamma=0.7),
+    dict(graph=(300, 1200, 21), R=24, as_stall_steps=2, as_frozen_inv=32, nl_period=3),
+    dict(graph=(250, 1000, 9), R=16, as_stall_steps=1, as_frozen_inv=16, nl_period=2, nl_kind=1),
+    dict(graph=(250, 1000, 9), R=20, as_stall_steps=3, as_frozen_inv=256, nl_period=5),
+    # beta = 0 accepts every uphill move (accepts == attempts), so the
+    # frozen test 1 * accepts < attempts never holds and the level stays 0
+    dict(graph=(120, 400, 4), R=16, as_stall_steps=1, as_frozen_inv=1, nl_period=3,
+         betas=[0.0] * 40),
+]
+
+
+def _as_run(spec):
+    spec = dict(spec)
+    n, m, gs = spec.pop("graph")
+    R = spec.pop("R")
+    betas = spec.pop("betas", W.linear_betas(0.1, 3.0, 150))
+    g = W.random_graph(n, m, gs)
+    r = _run(g, betas, sweeps=3, R=R, as_enable=1, **spec)
+    best0 = min(O.energy(g, x) for x in r.x_init)      # eq. (1) energy of the initial population
+    return r, best0, spec
+
+
+@pytest.mark.parametrize("idx", range(len(AS_RUNS)))
+def test_noise_levels_replayed_from_step_statistics(idx):
+    """The oracle's noise levels (stats column 4) equal an independent replay
+    of the rule from columns 2, 3 and 5 alone, on runs with cluster moves
+    (either kind) whose level rises at least twice and falls back to 0, and
+    on a beta = 0 run where the frozen test must never pass."""
+    r, best0, spec = _as_run(AS_RUNS[idx])
+    lmax = spec.get("as_max_level", 4)
+    want = _replay_levels(r.stats, best0, spec["as_stall_steps"], spec["as_frozen_inv"], lmax)
+    assert np.array_equal(r.stats[:, 4], want)
+    lv = r.stats[:, 4]
+    if idx == 5:
+        assert not lv.any() and np.array_equal(r.stats[:, 2], r.stats[:, 3])
+        return
+    assert int(np.sum(np.diff(lv) > 0)) >= 2
+    if idx != 4:
+        assert int(np.sum(np.diff(lv) < 0)) >= 1
+        assert lv.max() == lmax
+
+
+@pytest.mark.parametrize("variant", ["strict_stall", "no_stall_reset", "frozen_le",
+                                     "keep_level_on_improvement"])
+def test_noise_level_replay_discriminates_misreadings(variant):
+    """Each planted misreading of the rule disagrees with the oracle's levels
+    on at least one of the runs, so the replay above can tell them apart."""
+    differs = False
+    for spec in AS_RUNS:
+        r, best0, sp = _as_run(spec)
+        alt = _replay_levels(r.stats, best0, sp["as_stall_steps"], sp["as_frozen_inv"],
+                             sp.get("as_max_level", 4), variant)
+        differs |= not np.array_equal(alt, r.stats[:, 4])
+    assert differs, variant
+
+
+def test_noise_level_lowers_the_sweep_temperature():
+    """Once the level sits at l_max the sweeps sample exp(-beta gamma^lmax E):
+    an 8-node signed graph whose ground state is in the initial population
+    (32,768 replicas over 256 states) never improves, so with one stall step
+    and frozen_inv 1 the level climbs 0, 1, 2 and stays; 62 more sweeps at a
+    fixed beta (identity resampling) leave the population at the reduced
+    inverse temperature, not at beta or beta gamma."""
+    g = W.from_edges(8, [0, 0, 1, 2, 3, 4, 5, 6, 1, 2, 0, 3],
+                     [1, 2, 3, 4, 5, 6, 7, 7, 5, 6, 7, 6],
+                     [1, -1, 1, 1, -1, 1, 1, -1, 1, 1, -1, 1])
+    beta, gamma, K, R = 1.2, 0.5, 64, 32768
+    r = _run(g, [beta] * K, sweeps=1, R=R, seed=9, as_enable=1, as_stall_steps=1,
+             as_frozen_inv=1, as_max_level=2, as_gamma=gamma)
+    assert r.stats[:, 4].tolist() == [0, 1] + [2] * (K - 2)
+    E = refs.all_energies(g)
+    assert int(E.min()) == r.best_E and r.best_step == -1
+    obs = np.bincount(refs.state_index(r.x), minlength=E.shape[0])
+
+    def chi2(b):
+        p = np.exp(-b * (E - E.min()))
+        p /= p.sum()
+        return float(((obs - R * p) ** 2 / (R * p)).sum())
+
+    assert chi2(beta * gamma ** 2) < 400.0      # 255 dof
+    assert chi2(beta * gamma) > 2000.0
+    assert chi2(beta) > 2000.0
 
 
 # ------------------------------------------------------- objective (1) ----
@@ -520,6 +658,26 @@ def test_adaptive_steps_reproduce_free_energy_by_enumeration():
     b = betas[-1]
     exact = float(np.log(np.exp(-b * (E - E.min())).sum()) - b * E.min())
     assert abs(est - exact) < 0.03
+
+
+def test_adaptive_steps_refuse_uneven_grids():
+    """Reweighting a jump by beta_j - beta_0 is exact population annealing
+    only on an evenly spaced grid (the jump from g raises beta by
+    beta_{g+j} - beta_g): the oracle refuses a geometric grid with adaptive
+    steps, takes it without, and takes FP64 linear grids."""
+    g = W.random_graph(40, 120, 2)
+    geo = 0.1 * 1.05 ** np.arange(30)
+    with pytest.raises(ValueError):
+        _run(g, geo, sweeps=1, R=16, beta_adapt=1)
+    _run(g, geo, sweeps=1, R=16)
+    r = _run(g, W.linear_betas(0.1, 5.0, 2000)[:1000:10], sweeps=1, R=16, beta_adapt=1)
+    assert r.stats[0, 8] == 0
+    # on a linear grid every jump's own increase equals beta_j - beta_0 to
+    # within the FP64 rounding of the grid
+    b = W.linear_betas(0.1, 5.0, 2000)
+    for j in (1, 2, 7, 64):
+        inc = b[j:] - b[:-j]
+        assert np.max(np.abs(inc - (b[j] - b[0]))) < 1e-12 * j
 
 
 def test_adaptive_target_one_steps_one_grid_point_while_energies_differ():

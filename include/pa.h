@@ -170,6 +170,33 @@ pa_status pa_workspace_bytes(const pa_solver *s, const pa_schedule *sch, int32_t
 pa_status pa_run(pa_solver *s, const pa_schedule *sch, int32_t R, uint64_t seed,
                  uint32_t instance, void *workspace, size_t workspace_bytes, void *stream);
 
+/* Bytes of the static device workspace of pa_run_static (64 MiB). */
+#define PA_STATIC_SCRATCH_BYTES (64u << 20)
+
+/*
+ * pa_run for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * run, with the same results, enqueued on `stream`, but inside a workspace
+ * the library holds as a static device array of PA_STATIC_SCRATCH_BYTES per
+ * GPU (kept until the process ends) instead of one the caller passes. It
+ * calls no hipMalloc, hipHostMalloc, hipFree or other allocating device
+ * routine: the host inputs are copied from pageable host memory, and run
+ * timing (pa_set_timing) is not recorded. The first call on a device looks
+ * up the array's address there (hipGetSymbolAddress).
+ * Every call on a GPU shares that GPU's array, which keeps the last call's
+ * contents: the results of this run stay readable through the pa_best_* /
+ * pa_get_* / pa_checkpoint_save calls of this solver only until the next
+ * pa_run_static on the same GPU (from any solver) starts, and calls that
+ * overlap on one GPU (other streams, other threads, or this run still in
+ * flight) race on the array; the caller orders them. pa_run_steps cannot
+ * continue such a run.
+ * Errors: as pa_run; PA_EWORKSPACE when the run needs more than
+ * PA_STATIC_SCRATCH_BYTES (pa_workspace_bytes gives the need), PA_EDEVICE
+ * when the array's address cannot be taken.
+ */
+pa_status pa_run_static(pa_solver *s, const pa_schedule *sch, int32_t R, uint64_t seed,
+                        uint32_t instance, void *stream);
+
 /*
  * Steps [k_begin, k_end) of the same run as pa_run (0 <= k_begin <= k_end <=
  * K), for schedules too long for one call and for checkpoints. k_begin = 0

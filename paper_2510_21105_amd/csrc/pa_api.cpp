@@ -120,6 +120,9 @@ struct pa_solver {
     size_t stage_cap = 0;
     hipEvent_t stage_ev = nullptr;
     bool stage_pending = false;
+    // Pageable host copy of the inputs for runs that allocate no pinned or
+    // device memory (pa_run_static).
+    std::vector<unsigned char> stage_host;
     // timing: 0 off, else the sweep launches of every timing-th step are timed
     int timing = 0, timing_run = 0;
     std::vector<hipEvent_t> ev;
@@ -804,9 +807,12 @@ static uint64_t run_key(const pa_solver *s, const pa_schedule *sch, int32_t R, u
 // Plan the run, upload the graph and tables into the workspace and set up the
 // launch arguments. A fresh run also clears the state, draws the initial
 // population and takes its best; a restored one leaves the state to the caller.
+// `pinned`: the host inputs go through the solver's pinned staging buffer
+// (allocated on first use); otherwise from a pageable host buffer, so that no
+// pinned or device memory is allocated.
 static pa_status start_run(pa_solver *s, const pa_schedule *sch, int32_t R, uint64_t seed,
                            uint32_t instance, void *workspace, size_t workspace_bytes, void *stream,
-                           bool fresh)
+                           bool fresh, bool pinned = true)
 {
     g_error[0] = 0;
     pa_status st = check_schedule(s, sch, R);
@@ -835,22 +841,30 @@ static pa_status start_run(pa_solver *s, const pa_schedule *sch, int32_t R, uint
     HIP_TRY(hipGetDevice(&s->device));
     const int n = s->n;
 
-    // All host inputs go through the pinned staging buffer in one copy.
-    if (s->stage_pending) {
-        HIP_TRY(hipEventSynchronize(s->stage_ev));
-        s->stage_pending = false;
+    // All host inputs go to the device in one copy, through the pinned
+    // staging buffer or a pageable one.
+    unsigned char *stage = nullptr;
+    if (pinned) {
+        if (s->stage_pending) {
+            HIP_TRY(hipEventSynchronize(s->stage_ev));
+            s->stage_pending = false;
+        }
+        if (s->stage_cap < L.inputs_end) {
+            if (s->stage) HIP_TRY(hipHostFree(s->stage));
+            s->stage = nullptr;
+            s->stage_cap = 0;
+            HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&s->stage), L.inputs_end, hipHostMallocDefault));
+            std::memset(s->stage, 0, L.inputs_end);
+            s->stage_cap = L.inputs_end;
+        }
+        if (!s->stage_ev) HIP_TRY(hipEventCreateWithFlags(&s->stage_ev, hipEventDisableTiming));
+        stage = s->stage;
+    } else {
+        s->stage_host.assign(L.inputs_end, 0);
+        stage = s->stage_host.data();
     }
-    if (s->stage_cap < L.inputs_end) {
-        if (s->stage) HIP_TRY(hipHostFree(s->stage));
-        s->stage = nullptr;
-        s->stage_cap = 0;
-        HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&s->stage), L.inputs_end, hipHostMallocDefault));
-        std::memset(s->stage, 0, L.inputs_end);
-        s->stage_cap = L.inputs_end;
-    }
-    if (!s->stage_ev) HIP_TRY(hipEventCreateWithFlags(&s->stage_ev, hipEventDisableTiming));
     auto put = [&](size_t off, const void *src, size_t bytes) {
-        if (bytes) std::memcpy(s->stage + off, src, bytes);
+        if (bytes) std::memcpy(stage + off, src, bytes);
     };
     put(L.row_ptr, s->row_ptr.data(), sizeof(int) * (n + 1));
     put(L.col, s->col.data(), sizeof(int) * s->nnz);
@@ -871,9 +885,11 @@ static pa_status start_run(pa_solver *s, const pa_schedule *sch, int32_t R, uint
     put(L.wtab, P.wtab.data(), sizeof(uint64_t) * P.wtab.size());
     put(L.wtab_off, P.wtab_off.data(), sizeof(int) * P.K);
     put(L.wtab_len, P.wtab_len.data(), sizeof(int) * P.K);
-    HIP_TRY(hipMemcpyAsync(ws, s->stage, L.inputs_end, hipMemcpyHostToDevice, hs));
-    HIP_TRY(hipEventRecord(s->stage_ev, hs));
-    s->stage_pending = true;
+    HIP_TRY(hipMemcpyAsync(ws, stage, L.inputs_end, hipMemcpyHostToDevice, hs));
+    if (pinned) {
+        HIP_TRY(hipEventRecord(s->stage_ev, hs));
+        s->stage_pending = true;
+    }
 
     auto U64 = [&](size_t off) { return reinterpret_cast<unsigned long long *>(ws + off); };
     if (fresh) {
@@ -991,7 +1007,7 @@ static pa_status start_run(pa_solver *s, const pa_schedule *sch, int32_t R, uint
     sa.Ein = nullptr;
     sa.parent = nullptr;
 
-    if (s->timing) {
+    if (s->timing && pinned) {
         const size_t need = 2 * (size_t)P.K;
         while (s->ev.size() < need) {
             hipEvent_t e;
@@ -1001,7 +1017,7 @@ static pa_status start_run(pa_solver *s, const pa_schedule *sch, int32_t R, uint
     }
     s->ev_first = 0;
     s->ev_used = 0;
-    s->timing_run = s->timing;
+    s->timing_run = pinned ? s->timing : 0;
 
     pa_solver::RunCtx &c = s->rc;
     c.valid = fresh;              // a restored run becomes valid once its state is loaded
@@ -1171,6 +1187,27 @@ extern "C" pa_status pa_run(pa_solver *s, const pa_schedule *sch, int32_t R, uin
         return fail(PA_EINVAL, "null schedule");
     }
     return pa_run_steps(s, sch, R, seed, instance, 0, sch->n_steps, workspace, workspace_bytes, stream);
+}
+
+extern "C" pa_status pa_run_static(pa_solver *s, const pa_schedule *sch, int32_t R, uint64_t seed,
+                                   uint32_t instance, void *stream)
+{
+    g_error[0] = 0;
+    pa_status st = check_schedule(s, sch, R);
+    if (st != PA_OK) return st;
+    if (instance > 65535) return fail(PA_ERANGE, "instance=%u outside [0, 65535]", instance);
+    Plan p;
+    st = build_plan(s, sch, R, p, false);
+    if (st != PA_OK) return st;
+    if (p.L.total > pa::kStaticScratchBytes)
+        return fail(PA_EWORKSPACE, "run needs %zu workspace bytes, more than the %zu of the static "
+                                   "workspace: use pa_run with a workspace", p.L.total,
+                    (size_t)pa::kStaticScratchBytes);
+    void *ws = nullptr;
+    if (pa::static_scratch(&ws) != 0) return fail(PA_EDEVICE, "%s", pa::last_hip_error());
+    st = start_run(s, sch, R, seed, instance, ws, pa::kStaticScratchBytes, stream, true, false);
+    if (st != PA_OK) return st;
+    return run_range(s, 0, sch->n_steps);
 }
 
 // -------------------------------------------------------------- results ----

@@ -24,6 +24,8 @@ constexpr int kMaxThreads = 1024;
 // Kernel 1 LDS: the 256-entry u32 threshold table (indexed by a move byte),
 // then the byte records.
 constexpr int kBytesRecBase = 1024;
+// Size of the static device workspace of pa_run_static.
+constexpr size_t kStaticScratchBytes = PA_STATIC_SCRATCH_BYTES;
 
 struct GraphDev {
     int n;
@@ -139,5 +141,9 @@ int launch_icm(const IcmArgs &a, void *stream);
 int icm_lds_bytes(int n, int nw32);
 int launch_fill_u64(unsigned long long *p, unsigned long long v, long long count, void *stream);
 const char *last_hip_error();
+// Device address of the static workspace on the current device (taken once
+// per device with hipGetSymbolAddress); 0 on success, else -1 with the error
+// in last_hip_error().
+int static_scratch(void **ptr);
 
 }  // namespace pa

@@ -2048,4 +2048,41 @@ int launch_icm(const IcmArgs &a, void *stream)
     return check("icm_apply_kernel");
 }
 
+// ---------------------------------------------------------------------------
+// Static device workspace for callers that cannot allocate device memory
+// (pa_run_static). Every device the library runs on holds one copy until the
+// process ends. In host code `scratch` names a host-side stand-in, not device
+// memory: its device address on the current device comes from
+// hipGetSymbolAddress, taken once per device and kept, and only that address
+// is ever handed to kernels or copies.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[kMaxDevices] = {};
+
+int static_scratch(void **ptr)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return check("hipGetDevice(static scratch)");
+    if (dev < 0 || dev >= kMaxDevices) {
+        snprintf(g_err, sizeof g_err, "static scratch: device %d beyond the %d supported", dev, kMaxDevices);
+        return -1;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            snprintf(g_err, sizeof g_err, "hipGetSymbolAddress(static scratch) on device %d: %s", dev,
+                     hipGetErrorString(e));
+            (void)hipGetLastError();
+            return -1;
+        }
+        g_scratch_ptr[dev] = p;
+    }
+    *ptr = g_scratch_ptr[dev];
+    return 0;
+}
+
 }  // namespace pa

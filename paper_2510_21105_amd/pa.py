@@ -27,7 +27,9 @@ EXPORTS = ("pa_last_error", "pa_create", "pa_destroy", "pa_graph_info", "pa_work
            "pa_run", "pa_run_batch", "pa_build_tables", "pa_best_cut", "pa_best_info", "pa_best_config", "pa_best_config_hex",
            "pa_get_population", "pa_get_initial_population", "pa_get_step_stats",
            "pa_get_counts", "pa_get_launch_info", "pa_set_timing", "pa_get_sweep_time",
-           "pa_run_steps", "pa_checkpoint_bytes", "pa_checkpoint_save", "pa_checkpoint_load")
+           "pa_run_steps", "pa_checkpoint_bytes", "pa_checkpoint_save", "pa_checkpoint_load",
+           "pa_run_static")
+STATIC_SCRATCH_BYTES = 64 << 20     # PA_STATIC_SCRATCH_BYTES
 
 
 class PAError(RuntimeError):
@@ -94,6 +96,7 @@ def lib():
             "pa_workspace_bytes": [P, ctypes.POINTER(Schedule), i32, ctypes.POINTER(ctypes.c_size_t)],
             "pa_run": [P, ctypes.POINTER(Schedule), i32, u64, u32, P, ctypes.c_size_t, P],
             "pa_run_batch": [ctypes.POINTER(BatchRun), i32, ctypes.POINTER(P), i32],
+            "pa_run_static": [P, ctypes.POINTER(Schedule), i32, u64, u32, P],
             "pa_build_tables": [ctypes.POINTER(Schedule), i32, i32, P, ctypes.POINTER(ctypes.c_size_t)],
             "pa_best_cut": [P, ctypes.POINTER(i64), ctypes.POINTER(i32)],
             "pa_best_info": [P, P],
@@ -247,6 +250,18 @@ class Solver:
         _check(lib().pa_run(self._h, ctypes.byref(sch), p.R, p.seed, p.inst,
                             ctypes.c_void_p(aligned), avail, ctypes.c_void_p(st.cuda_stream)))
         self._started(p, sch, keep, workspace)
+        return self
+
+    def run_static(self, p: RunParams, stream=None):
+        """Enqueue a run inside the library's static device workspace
+        (pa_run_static: no device allocation; results valid until the next
+        such run on this GPU)."""
+        import torch
+        sch, keep = self._schedule(p)
+        st = torch.cuda.current_stream() if stream is None else stream
+        _check(lib().pa_run_static(self._h, ctypes.byref(sch), p.R, p.seed, p.inst,
+                                   ctypes.c_void_p(st.cuda_stream)))
+        self._started(p, sch, keep, None)
         return self
 
     def run_steps(self, p: RunParams, k_begin: int, k_end: int, stream=None, workspace=None):

@@ -402,6 +402,27 @@ def test_checkpoint_header_is_read_back():
     assert pa.next_step(hdr) == 17
 
 
+def test_static_workspace_run_refuses_oversized_runs_without_device_calls():
+    """pa_run_static works inside the library's fixed static workspace: a run
+    needing more than PA_STATIC_SCRATCH_BYTES is refused before any device
+    call, and so is a bad schedule."""
+    L = pa.lib()
+    text = open(HEADER).read()
+    assert re.search(r"#define PA_STATIC_SCRATCH_BYTES \(64u << 20\)", text)
+    assert pa.STATIC_SCRATCH_BYTES == 64 << 20
+    wl = W.workload("torus100")
+    s = pa.Solver(wl["graph"])
+    p = pa.params_from_workload(wl, R=32768, betas=wl["betas"][:2])
+    assert s.workspace_bytes(p) > pa.STATIC_SCRATCH_BYTES
+    sch, keep = s._schedule(p)
+    assert L.pa_run_static(s._h, ctypes.byref(sch), p.R, p.seed, p.inst, None) == pa.PA_EWORKSPACE
+    assert "static workspace" in L.pa_last_error().decode()
+    bad = pa.params_from_workload(wl, betas=[0.5, 0.4])
+    sch, keep = s._schedule(bad)
+    assert L.pa_run_static(s._h, ctypes.byref(sch), bad.R, bad.seed, bad.inst, None) == pa.PA_EINVAL
+    assert L.pa_run_static(None, ctypes.byref(sch), 4, 0, 0, None) == pa.PA_EINVAL
+
+
 def test_timing_stride_validation():
     s = pa.Solver(W.cycle(10))
     s.set_timing(3)

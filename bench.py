@@ -101,23 +101,42 @@ def cpu_baseline(wl, sample_steps: int):
 
 
 def batch_bench(args, count: int):
-    """Instances/s of a mix of uneven runs: one after another on one stream,
-    then as one batch over several streams (pa_run_batch)."""
+    """Instances/s of a mix of uneven runs: one after another, one launch
+    sequence per instance on one stream (the baseline); the same runs over
+    several streams (pa_run_batch); and as a fused batch sharing launches
+    (pa_fused_*: autotuned shapes, step loop as a HIP graph), the reported
+    value. Every instance's statistics, population and best record must be
+    identical across the three."""
     import torch
     from paper_2510_21105_amd import pa, workloads as W
 
     wls = W.batch_workloads(count)
     params = [pa.params_from_workload(w) for w in wls]
     solvers = [pa.Solver(w["graph"]) for w in wls]
+    fused_solvers = [pa.Solver(w["graph"]) for w in wls]
     attempts = sum(p.R * w["graph"].n * p.sweeps * len(p.betas) for w, p in zip(wls, params))
     streams = [torch.cuda.Stream() for _ in range(args.streams)]
     print(f"[bench] {count} instances, {attempts:.3e} attempts per batch, {args.streams} streams",
           file=sys.stderr, flush=True)
+    fb = pa.FusedBatch(fused_solvers, params)
+    t0 = time.perf_counter()
+    shapes = fb.tune(probe_steps=3)
+    tune_s = time.perf_counter() - t0
+    print(f"[bench] fused batch tuned in {tune_s:.2f} s: {shapes}", file=sys.stderr, flush=True)
     for w in range(args.warmup):
         pa.run_batch(solvers, params, streams)
+        fb.run()
         torch.cuda.synchronize()
         print(f"[bench] warmup {w + 1}/{args.warmup} done", file=sys.stderr, flush=True)
-    seq, bat = [], []
+
+    def results(sv):
+        return [(s.step_stats(), s.best_info(), s.population()[1]) for s in sv]
+
+    def same(a, b):
+        return all(np.array_equal(x[0], y[0]) and x[1] == y[1] and np.array_equal(x[2], y[2])
+                   for x, y in zip(a, b))
+
+    seq, bat, fus = [], [], []
     for step in range(args.steps):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -125,18 +144,25 @@ def batch_bench(args, count: int):
             s.run(p, stream=streams[0])
         torch.cuda.synchronize()
         seq.append(time.perf_counter() - t0)
-        cuts_seq = [s.best_cut() for s in solvers]
+        r_seq = results(solvers)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         pa.run_batch(solvers, params, streams)
         torch.cuda.synchronize()
         bat.append(time.perf_counter() - t0)
-        cuts_bat = [s.best_cut() for s in solvers]
-        if cuts_seq != cuts_bat:
-            raise RuntimeError("batched and sequential runs disagree")
+        r_bat = results(solvers)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fb.run()
+        torch.cuda.synchronize()
+        fus.append(time.perf_counter() - t0)
+        r_fus = results(fused_solvers)
+        if not (same(r_seq, r_bat) and same(r_seq, r_fus)):
+            raise RuntimeError("fused, streamed and sequential runs disagree")
         print(f"[bench] timed batch {step + 1}/{args.steps}: sequential {seq[-1]:.2f} s, "
-              f"batched {bat[-1]:.2f} s", file=sys.stderr, flush=True)
-    t_seq, t_bat = sum(seq) / len(seq), sum(bat) / len(bat)
+              f"streams {bat[-1]:.2f} s, fused {fus[-1]:.2f} s", file=sys.stderr, flush=True)
+    t_seq, t_str, t_bat = sum(seq) / len(seq), sum(bat) / len(bat), sum(fus) / len(fus)
+    cuts_bat = [s.best_cut() for s in fused_solvers]
     out = {
         "metric": "instances/s",
         "value": count / t_bat,
@@ -152,12 +178,16 @@ def batch_bench(args, count: int):
         "data": "synthetic",
         "config": {"workload": f"batch{count}: {count} uneven instances (even: random "
                                "G(N, N d/2), d ~ U[4,12]; odd: +-1 torus), N ~ U[800,7000], "
-                               "R ~ U[256,4096], K=500, plain population annealing",
-                   "instances": count, "streams": args.streams,
-                   "attempts_per_batch": attempts},
+                               "R ~ U[256,4096], K=500, plain population annealing; fused "
+                               "launches, autotuned shapes, HIP-graph step loop",
+                   "instances": count, "attempts_per_batch": attempts},
         "sequential_instances_per_s": count / t_seq,
+        "streams_instances_per_s": count / t_str,
+        "streams": args.streams,
         "speedup_vs_sequential": t_seq / t_bat,
         "attempts_per_s": attempts / t_bat,
+        "fused_groups": shapes,
+        "tune_s": tune_s,
         "best_cuts_first8": cuts_bat[:8],
     }
     print(json.dumps(out), flush=True)

@@ -273,6 +273,76 @@ typedef struct {
 pa_status pa_run_batch(const pa_batch_run *runs, int32_t count, void *const *streams,
                        int32_t n_streams);
 
+/* One run of a fused batch: the arguments of pa_run without workspace and
+ * stream. */
+typedef struct {
+    pa_solver *solver;                /* distinct solver per run */
+    const pa_schedule *schedule;      /* launch-shape fields are ignored */
+    int32_t R;
+    uint64_t seed;
+    uint32_t instance;
+} pa_fused_entry;
+
+/* Opaque fused batch: runs planned to share kernel launches. */
+typedef struct pa_fused pa_fused;
+
+/*
+ * Many runs sharing kernel launches (for instance dozens of uneven graphs and
+ * population sizes, most of which alone leave compute units idle). Runs whose
+ * graphs have only +1 weights form one group, runs with -1 weights another;
+ * step k of a whole group is one sweep launch, whose workgroups each take one
+ * replica tile of one run from a work list, and one epilogue launch with one
+ * workgroup per run. Groups run concurrently. Every run gives exactly the
+ * results of pa_run with the same arguments (any launch shape), and after
+ * pa_fused_run its solver answers the pa_best_* / pa_get_* /
+ * pa_checkpoint_save calls as after pa_run; pa_run_steps cannot continue it.
+ *
+ *   pa_fused_create   validates and plans the runs (host only; the schedules,
+ *                     orders and arrays are copied). Each run must be a valid
+ *                     pa_run on its solver with nl_period = 0 and beta_adapt =
+ *                     0, maximum degree <= 127 and no inverse temperature whose
+ *                     acceptance rounds to 1 for some uphill moves only.
+ *                     Solvers must be distinct and outlive the batch.
+ *   pa_fused_workspace_bytes  device bytes the batch needs (every run's state
+ *                     and the batch's own argument and work-list tables).
+ *   pa_fused_tune     measures, per group, each candidate launch shape (4, 8
+ *                     or 16 replicas per workgroup; 256 or 512 threads) on
+ *                     the first probe_steps (1..64) steps of the group's runs
+ *                     inside `workspace`, and keeps the fastest. Synchronous
+ *                     (it waits for the probes); leaves no valid results.
+ *                     Without it a default shape is used (8 replicas and 512
+ *                     threads where they fit).
+ *   pa_fused_run      enqueues the whole batch on `stream`: each run's setup
+ *                     (inputs, initial population), then the step loop of
+ *                     every group, captured once into a HIP graph (for this
+ *                     workspace address and these shapes) and launched on
+ *                     `stream`. Asynchronous; the results live in `workspace`
+ *                     (256-byte aligned, at least pa_fused_workspace_bytes),
+ *                     which must stay untouched until the last result call.
+ *   pa_fused_set_graph  1 (default): step loop as a HIP graph; 0: the same
+ *                     launches enqueued directly (for comparison).
+ *   pa_fused_info     per group 8 int64 {record mode (0 +1 weights, 2 signed
+ *                     graphs with sign-bit entries), runs, replicas per
+ *                     workgroup, threads, offset entries (1) or record
+ *                     indices (0), sweep workgroups per step, sweep LDS bytes,
+ *                     measured femtoseconds per attempt (0 untuned)} for up to
+ *                     max_groups groups into `out` (NULL: count only), and
+ *                     the number of groups into *groups.
+ *   pa_fused_destroy  releases the batch (NULL accepted); the solvers keep
+ *                     their results.
+ * Errors: PA_EINVAL (null arguments, a run that cannot share launches, a
+ * solver used twice, a bad probe count), the errors of pa_run for each run
+ * (the run index is in pa_last_error), PA_EWORKSPACE, PA_EDEVICE.
+ */
+pa_status pa_fused_create(pa_fused **out, const pa_fused_entry *runs, int32_t count);
+pa_status pa_fused_workspace_bytes(const pa_fused *f, size_t *bytes);
+pa_status pa_fused_tune(pa_fused *f, void *workspace, size_t workspace_bytes, void *stream,
+                        int32_t probe_steps);
+pa_status pa_fused_run(pa_fused *f, void *workspace, size_t workspace_bytes, void *stream);
+pa_status pa_fused_set_graph(pa_fused *f, int32_t on);
+pa_status pa_fused_info(const pa_fused *f, int64_t *out, int32_t max_groups, int32_t *groups);
+pa_status pa_fused_destroy(pa_fused *f);
+
 /*
  * Test hook: the fixed-point tables a run with this schedule uses, dense, as
  * little-endian u64 into caller memory `out` (NULL: only *bytes is set):

@@ -19,8 +19,9 @@
 
 #include "pa.h"
 #include "pa_device.h"
+#include "pa_host.h"
 
-namespace {
+namespace pa_host {
 
 thread_local char g_error[512] = "";
 
@@ -38,96 +39,9 @@ pa_status hip_fail(hipError_t e, const char *what)
     return fail(PA_EDEVICE, "%s: %s", what, hipGetErrorString(e));
 }
 
-#define HIP_TRY(call)                                                    \
-    do {                                                                 \
-        hipError_t _e = (call);                                          \
-        if (_e != hipSuccess) return hip_fail(_e, #call);                \
-    } while (0)
+}  // namespace pa_host
 
-#define LAUNCH_TRY(call)                                                 \
-    do {                                                                 \
-        if ((call) != 0) return fail(PA_EDEVICE, "%s", pa::last_hip_error()); \
-    } while (0)
-
-constexpr int kMaxN = 32767;   // node ids and LDS word indices fit 16 bits
-constexpr int kMaxDegree = 4096;
-constexpr int kMaxBytesDegree = 127;   // byte counters of kernel 1 (2u must fit a byte)
-constexpr int kMaxR = 32768;
-constexpr size_t kAlign = 256;
-
-size_t align_up(size_t b, size_t a = kAlign) { return (b + a - 1) / a * a; }
-
-struct Layout {
-    // Host inputs, uploaded together: [0, inputs_end).
-    size_t row_ptr, col, npos, edges, qtab, sched, level_off, blocks, stream, thr, wtab, wtab_off,
-        wtab_len, inputs_end;
-    size_t vout;
-    size_t X0, X1, E0, E1, cand, snap, counters, as_state, best, best_x, stats, parent;
-    size_t counts, xinit, total;
-};
-
-struct Plan {
-    int K = 0, S = 0, R = 0, G = 0, Rp = 0, W = 0, threads = 0, nblk = 0, nw32 = 0;
-    int lmax1 = 1, n_levels = 0, record = 0;
-    int kind = 2, sgn = 0, block_bytes = 0, qpad = 0, n_rounds = 0, flush_every = 1;
-    int direct = 0;   // kernel 1: block entries are LDS byte offsets (else record indices)
-    int bsg = 0;      // kernel 1 records: 0 unsigned, 1 complemented copies, 2 sign bits in entries
-    std::vector<int> sched, level_off;
-    std::vector<uint32_t> blocks;   // [n][block_bytes / 4] + 128 B
-    std::vector<int> stream;        // kernel 2: [waves][qpad][2]
-    std::vector<int> rounds;        // kernel 1: [n_rounds][4]
-    std::vector<uint64_t> thr, wtab;
-    std::vector<uint32_t> thr32;   // kernel 1: [K][lmax1][dmax + 1] = T[1..dmax], saturation flag
-    std::vector<uint64_t> qtab;    // single-replica cluster moves: [K][lmax1] bond thresholds
-    std::vector<int> wtab_off, wtab_len;
-    Layout L{};
-};
-
-}  // namespace
-
-struct pa_solver {
-    int n = 0;
-    long long nnz = 0;
-    int dmax = 0;
-    long long w_tot = 0;
-    int has_neg = 0;
-    std::vector<int> row_ptr, col, npos;
-    std::vector<uint32_t> edges;   // each edge once (i < j): i | j << 15 | negative << 30
-    // last run
-    bool has_run = false;
-    Plan plan;
-    unsigned char *ws = nullptr;
-    hipStream_t stream = nullptr;
-    size_t final_x = 0, final_E = 0;
-    int device = 0;
-    // State carried from one pa_run_steps call to the next.
-    struct RunCtx {
-        bool valid = false;
-        uint64_t key = 0;               // run_key of the run in the workspace
-        int next_step = 0;              // first step not run yet
-        bool parents_pending = false;   // kernel 1: the next population is Xc read through the parents
-        size_t Xc = 0, Xn = 0, Ec = 0, En = 0;
-        uint32_t seed_lo = 0, seed_hi = 0, instance = 0;
-        int nl_period = 0, nl_kind = 0;
-        int adapt = 0;                  // adaptive steps: the run may end before step K
-        pa::GraphDev gd{};
-        pa::SweepArgs sa{};
-        pa::EpiArgs ea{};
-    } rc;
-    // Pinned host copy of a run's inputs in workspace layout, uploaded with one
-    // copy; the event marks the end of the last upload from it.
-    unsigned char *stage = nullptr;
-    size_t stage_cap = 0;
-    hipEvent_t stage_ev = nullptr;
-    bool stage_pending = false;
-    // Pageable host copy of the inputs for runs that allocate no pinned or
-    // device memory (pa_run_static).
-    std::vector<unsigned char> stage_host;
-    // timing: 0 off, else the sweep launches of every timing-th step are timed
-    int timing = 0, timing_run = 0;
-    std::vector<hipEvent_t> ev;
-    int ev_first = 0, ev_used = 0;
-};
+using namespace pa_host;
 
 extern "C" const char *pa_last_error(void) { return g_error; }
 
@@ -254,7 +168,7 @@ static int uneven_grid(const double *beta, int K)
     return -1;
 }
 
-static pa_status check_schedule(const pa_solver *s, const pa_schedule *sch, int R)
+pa_status pa_host::check_schedule(const pa_solver *s, const pa_schedule *sch, int R)
 {
     if (!s || !sch) return fail(PA_EINVAL, "null solver or schedule");
     if (sch->n_steps < 1) return fail(PA_EINVAL, "n_steps must be >= 1");
@@ -351,7 +265,9 @@ static void build_levels(const pa_solver *s, const int32_t *order, Plan &p)
 // the complemented copy of its spin word (word n + j), so every entry counts
 // "w_ij x_j = +1" by a plain bit read. Each wave's pass stream lists
 // {first slot, largest degree among the pass's slots}.
-static void build_blocks(const pa_solver *s, Plan &p)
+// direct: 1 or 0 imposes the entry form of kernel 1's blocks, -1 takes
+// offsets whenever they fit 16 bits.
+static void build_blocks(const pa_solver *s, Plan &p, int direct)
 {
     const int n = s->n;
     if (p.kind == 1) {
@@ -369,7 +285,7 @@ static void build_blocks(const pa_solver *s, Plan &p)
         const int zrec = p.bsg == 1 ? 2 * n : n;    // index of the zero record
         // Entries are LDS byte offsets when every record's offset fits in 16
         // bits (one instruction to decode), else record indices.
-        p.direct = pa::kBytesRecBase + zrec * p.W <= 0xFFFF;
+        p.direct = direct >= 0 ? direct : pa::kBytesRecBase + zrec * p.W <= 0xFFFF;
         auto enc = [&](int rec) {
             return (uint16_t)(p.direct ? pa::kBytesRecBase + rec * p.W : rec + rb);
         };
@@ -492,7 +408,8 @@ static uint64_t weight_fixed(double dbeta, long long n)
     return (uint64_t)std::floor(std::ldexp(x, 32));
 }
 
-static pa_status build_plan(pa_solver *s, const pa_schedule *sch, int R, Plan &p, bool tables)
+pa_status pa_host::build_plan(pa_solver *s, const pa_schedule *sch, int R, Plan &p, bool tables,
+                              const Shape *force)
 {
     const int n = s->n;
     p.K = sch->n_steps;
@@ -570,7 +487,32 @@ static pa_status build_plan(pa_solver *s, const pa_schedule *sch, int R, Plan &p
     bool bytes_ok = s->dmax <= kMaxBytesDegree && (tile == 0 || tile <= 16) && !partial_sat && idx_fit;
     if (req == 1 && !bytes_ok)
         return fail(PA_EINVAL, "sweep kernel 1 needs max degree <= %d and tile 4, 8 or 16", kMaxBytesDegree);
-    if (req != 2 && bytes_ok) {
+    if (force) {
+        // A shape imposed by a multi-run launch: kernel 1 with the given tile,
+        // threads, record mode and entry form, or an error.
+        if (s->dmax > kMaxBytesDegree || partial_sat)
+            return fail(PA_EINVAL, "runs sharing a launch need max degree <= %d and no partly saturated "
+                                   "threshold row", kMaxBytesDegree);
+        if (force->W != 4 && force->W != 8 && force->W != 16)
+            return fail(PA_EINVAL, "shared launch tile %d is not 4, 8 or 16", force->W);
+        if (force->threads < 64 || force->threads > 1024 || force->threads % 64)
+            return fail(PA_EINVAL, "shared launch threads %d", force->threads);
+        if ((force->bsg != 0 && force->bsg != 2) || (force->bsg == 0 && p.sgn) ||
+            (force->bsg == 2 && n + pa::kBytesRecBase / 4 > 0x7FFF))
+            return fail(PA_EINVAL, "shared launch record mode %d does not suit this graph", force->bsg);
+        p.bsg = force->bsg;
+        if (pa::sweep_bytes_lds(force->W, 0, n, s->dmax) > max_lds)
+            return fail(PA_ERANGE, "graph of %d nodes does not fit LDS with %d replicas per workgroup", n,
+                        force->W);
+        if (force->direct && pa::kBytesRecBase + (size_t)(n + 1) * force->W > 0xFFFF)
+            return fail(PA_ERANGE, "graph of %d nodes too large for offset entries at tile %d", n, force->W);
+        p.kind = 1;
+        p.W = force->W;
+        p.threads = force->threads;
+        p.nblk = (R + p.W - 1) / p.W;
+        build_levels(s, sch->order, p);
+        build_blocks(s, p, force->direct);
+    } else if (req != 2 && bytes_ok) {
         W = tile;
         // A requested tile takes the thread count of the automatic plan for
         // that tile: 512 (refined by the level rule below) when two
@@ -612,7 +554,7 @@ static pa_status build_plan(pa_solver *s, const pa_schedule *sch, int R, Plan &p
             p.kind = 1;
         }
     }
-    if (W == 0) {
+    if (!force && W == 0) {
         if (req == 2 && tile != 0 && tile < 16) return fail(PA_EINVAL, "sweep kernel 2 takes tile 16, 32 or 64");
         p.kind = 2;
         W = tile >= 16 ? tile : 0;
@@ -623,6 +565,7 @@ static pa_status build_plan(pa_solver *s, const pa_schedule *sch, int R, Plan &p
         if (!words_fit(W))
             return fail(PA_ERANGE, "graph of %d nodes does not fit LDS with %d replicas per workgroup", n, W);
     }
+    if (!force) {
     p.W = W;
     p.nblk = (R + W - 1) / W;
 
@@ -645,7 +588,8 @@ static pa_status build_plan(pa_solver *s, const pa_schedule *sch, int R, Plan &p
                 break;
             }
     }
-    build_blocks(s, p);
+    build_blocks(s, p, -1);
+    }
 
     // Weight-table sizes (needed for the workspace size even without tables).
     const long long span = s->nnz;  // E_r - E_min <= sum |w_ij| over both directions
@@ -783,8 +727,8 @@ static uint64_t fnv(uint64_t h, const void *p, size_t n)
     return h;
 }
 
-static uint64_t run_key(const pa_solver *s, const pa_schedule *sch, int32_t R, uint64_t seed,
-                        uint32_t instance)
+uint64_t pa_host::run_key(const pa_solver *s, const pa_schedule *sch, int32_t R, uint64_t seed,
+                          uint32_t instance)
 {
     uint64_t h = 0xCBF29CE484222325ull;
     h = fnv(h, &s->n, sizeof s->n);
@@ -810,9 +754,9 @@ static uint64_t run_key(const pa_solver *s, const pa_schedule *sch, int32_t R, u
 // `pinned`: the host inputs go through the solver's pinned staging buffer
 // (allocated on first use); otherwise from a pageable host buffer, so that no
 // pinned or device memory is allocated.
-static pa_status start_run(pa_solver *s, const pa_schedule *sch, int32_t R, uint64_t seed,
-                           uint32_t instance, void *workspace, size_t workspace_bytes, void *stream,
-                           bool fresh, bool pinned = true)
+pa_status pa_host::start_run(pa_solver *s, const pa_schedule *sch, int32_t R, uint64_t seed,
+                             uint32_t instance, void *workspace, size_t workspace_bytes, void *stream,
+                             bool fresh, bool pinned, const Shape *force)
 {
     g_error[0] = 0;
     pa_status st = check_schedule(s, sch, R);
@@ -826,7 +770,7 @@ static pa_status start_run(pa_solver *s, const pa_schedule *sch, int32_t R, uint
     s->has_run = false;
     s->rc.valid = false;          // until this run's state is complete in the workspace
     Plan p;
-    st = build_plan(s, sch, R, p, true);
+    st = build_plan(s, sch, R, p, true, force);
     if (st != PA_OK) return st;
     if (workspace_bytes < p.L.total)
         return fail(PA_EWORKSPACE, "workspace of %zu bytes < %zu needed", workspace_bytes, p.L.total);

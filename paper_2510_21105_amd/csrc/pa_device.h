@@ -97,6 +97,19 @@ struct EpiArgs {
     int *counts_rec;            // [K][R] or null
 };
 
+// One run of a multi-run launch (several runs' steps in one sweep launch and
+// one epilogue launch): its sweep and epilogue arguments without the per-step
+// fields (step, population buffers, resampling parents), which the kernels
+// derive from the step index.
+struct MultiRun {
+    SweepArgs sweep;
+    EpiArgs epi;                // epi.parent: the resampling parents the next sweep reads
+    uint64_t *X0, *X1;          // population ping-pong; the initial population is in X0
+    int *E0, *E1;
+    int steps;                  // K: steps at or past it do nothing
+    int nblk;                   // sweep tiles of this run
+};
+
 struct GatherArgs {
     int n, R, G;
     const int *parent;
@@ -136,6 +149,12 @@ int launch_sweep(int W, int sgn, int threads, int nblk, const SweepArgs &a, void
 int sweep_bytes_lds(int W, int sgn, int n, int dmax);
 int launch_sweep_bytes(int W, int sgn, int threads, int nblk, const SweepArgs &a, void *stream);
 int launch_epilogue(const EpiArgs &a, void *stream);
+// Multi-run launches: `blocks` workgroups over the work list {run, tile}
+// (sgn 0 unsigned records, 2 sign bits; `lds` the largest run's sweep LDS),
+// and one epilogue workgroup per run (max_R: the largest population).
+int launch_sweep_multi(int W, int sgn, bool direct, int threads, int blocks, int lds, const MultiRun *runs,
+                       const int2 *work, int k, void *stream);
+int launch_epilogue_multi(int runs_count, int max_R, const MultiRun *runs, int k, void *stream);
 int launch_gather(const GatherArgs &a, void *stream);
 int launch_icm(const IcmArgs &a, void *stream);
 int icm_lds_bytes(int n, int nw32);

@@ -629,9 +629,12 @@ __device__ __forceinline__ int wave_sum_dpp(int v)
 // the neighbour's record (records twice as many); 2 = negative edges carry a
 // sign bit in their block entry and the record is complemented on reading
 // (half the LDS of mode 1, one XOR per neighbour).
+// One workgroup's step: tile `blk` (replicas blk*W .. blk*W + W - 1) of a run
+// whose sweep launch has `nblk` tiles.
 template <int W, int SG, bool DIRECT>
-__global__ __launch_bounds__(1024) void sweep_bytes_kernel(SweepArgs a, const int4 *__restrict__ rounds,
-                                                          const uint4 *__restrict__ blocks)
+__device__ __forceinline__ void sweep_bytes_tile(const SweepArgs &a, const int4 *__restrict__ rounds,
+                                                 const uint4 *__restrict__ blocks, const int blk,
+                                                 const int nblk)
 {
     constexpr bool SIGNED = SG == 1;     // complemented records in LDS
     constexpr bool SBIT = SG == 2;       // sign bits in the block entries
@@ -641,11 +644,11 @@ __global__ __launch_bounds__(1024) void sweep_bytes_kernel(SweepArgs a, const in
         // population over to the output buffer unchanged (the parent list is
         // the identity then), each workgroup a slice.
         const size_t words = (size_t)((a.R + 63) >> 6) * a.n;
-        const size_t per = (words + gridDim.x - 1) / gridDim.x;
-        const size_t w0 = (size_t)blockIdx.x * per, w1 = w0 + per < words ? w0 + per : words;
+        const size_t per = (words + nblk - 1) / nblk;
+        const size_t w0 = (size_t)blk * per, w1 = w0 + per < words ? w0 + per : words;
         for (size_t w = w0 + threadIdx.x; w < w1; w += blockDim.x) a.X[w] = a.Xin[w];
-        const int rper = (a.R + (int)gridDim.x - 1) / (int)gridDim.x;
-        const int e0 = (int)blockIdx.x * rper, e1 = e0 + rper < a.R ? e0 + rper : a.R;
+        const int rper = (a.R + nblk - 1) / nblk;
+        const int e0 = blk * rper, e1 = e0 + rper < a.R ? e0 + rper : a.R;
         for (int r = e0 + (int)threadIdx.x; r < e1; r += blockDim.x) a.E[r] = a.Ein[r];
         return;
     }
@@ -655,17 +658,6 @@ __global__ __launch_bounds__(1024) void sweep_bytes_kernel(SweepArgs a, const in
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int nt = blockDim.x;
-    // Workgroups are dispatched round-robin over the 8 XCDs. For 8- and
-    // 16-replica tiles (plain byte stores) each XCD takes a contiguous range
-    // of tiles, so tiles sharing a 64-replica word share an L2; 4-replica
-    // tiles keep the plain order (their nibble stores are atomic XORs, which
-    // would then contend within one XCD).
-    const int blk = [] {
-        const int b = blockIdx.x;
-        if constexpr (W < 8) return b;
-        const int nb = gridDim.x, x = b & 7, q = nb >> 3, rem = nb & 7;
-        return x * q + (x < rem ? x : rem) + (b >> 3);
-    }();
     const int r0 = blk * W;
     const int grp = r0 >> 6;
     const int sub = (r0 & 63) / W;
@@ -1176,6 +1168,49 @@ __global__ __launch_bounds__(1024) void sweep_bytes_kernel(SweepArgs a, const in
     }
 }
 
+template <int W, int SG, bool DIRECT>
+__global__ __launch_bounds__(1024) void sweep_bytes_kernel(SweepArgs a, const int4 *__restrict__ rounds,
+                                                          const uint4 *__restrict__ blocks)
+{
+    // Workgroups are dispatched round-robin over the 8 XCDs. For 8- and
+    // 16-replica tiles (plain byte stores) each XCD takes a contiguous range
+    // of tiles, so tiles sharing a 64-replica word share an L2; 4-replica
+    // tiles keep the plain order (their nibble stores are atomic XORs, which
+    // would then contend within one XCD).
+    const int nb = gridDim.x;
+    const int blk = [nb] {
+        const int b = blockIdx.x;
+        if constexpr (W < 8) return b;
+        const int x = b & 7, q = nb >> 3, rem = nb & 7;
+        return x * q + (x < rem ? x : rem) + (b >> 3);
+    }();
+    sweep_bytes_tile<W, SG, DIRECT>(a, rounds, blocks, blk, nb);
+}
+
+// Step k of many runs in one launch: workgroup b takes the tile work[b] =
+// {run, tile} (run < 0: an empty slot), with the run's arguments from
+// runs[run]; the step's population buffers follow from the parity of k (the
+// initial population is in X0/E0), and step 0 reads no resampling parents.
+// Runs whose schedule ended before step k do nothing.
+template <int W, int SG, bool DIRECT>
+__global__ __launch_bounds__(1024) void sweep_bytes_multi_kernel(const MultiRun *__restrict__ runs,
+                                                                const int2 *__restrict__ work, int k)
+{
+    const int2 wk = work[blockIdx.x];
+    if (wk.x < 0) return;
+    const MultiRun &m = runs[wk.x];
+    if (k >= m.steps) return;
+    SweepArgs a = m.sweep;
+    const bool even = (k & 1) == 0;
+    a.k = k;
+    a.Xin = even ? m.X0 : m.X1;
+    a.X = even ? m.X1 : m.X0;
+    a.Ein = even ? m.E0 : m.E1;
+    a.E = even ? m.E1 : m.E0;
+    a.parent = k == 0 ? nullptr : m.epi.parent;
+    sweep_bytes_tile<W, SG, DIRECT>(a, a.rounds, a.blocks, wk.y, m.nblk);
+}
+
 // ---------------------------------------------------------------------------
 // Step epilogue (one workgroup): best-candidate reduction, population best
 // check, noise-level update, statistics, reweighting and systematic
@@ -1187,7 +1222,7 @@ __device__ __forceinline__ uint64_t sys_f(uint64_t c, uint64_t R, uint64_t u, ui
     return rc <= u ? 0 : (rc - u + S - 1) / S;
 }
 
-__global__ __launch_bounds__(1024) void epilogue_kernel(EpiArgs a)
+__device__ __forceinline__ void epilogue_body(const EpiArgs &a)
 {
     extern __shared__ int Esh[];       // [R] energies (when the population is read)
     __shared__ unsigned long long w_cand[16], w_key[16], w_scan[16];
@@ -1460,6 +1495,25 @@ __global__ __launch_bounds__(1024) void epilogue_kernel(EpiArgs a)
         for (int q = 0; q < 5; ++q) a.best[q] = brec[q];
         a.as_state[2] = a.do_rest ? 0 : simp;
     }
+}
+
+__global__ __launch_bounds__(1024) void epilogue_kernel(EpiArgs a) { epilogue_body(a); }
+
+// The epilogue of step k of many runs in one launch, one workgroup per run
+// (the population after step k's sweeps is in X1/E1 for even k).
+__global__ __launch_bounds__(1024) void epilogue_multi_kernel(const MultiRun *__restrict__ runs, int k)
+{
+    const MultiRun &m = runs[blockIdx.x];
+    if (k >= m.steps) return;
+    EpiArgs a = m.epi;
+    const bool even = (k & 1) == 0;
+    a.k = k;
+    a.E = even ? m.E1 : m.E0;
+    a.X = even ? m.X1 : m.X0;
+    a.do_cand = 1;
+    a.do_pop = 0;
+    a.do_rest = 1;
+    epilogue_body(a);
 }
 
 // ---------------------------------------------------------------------------
@@ -2009,6 +2063,58 @@ int launch_sweep_bytes(int W, int sgn, int threads, int nblk, const SweepArgs &a
         snprintf(g_err, sizeof g_err, "unsupported byte-tile width %d", W);
         return -1;
     }
+}
+
+template <int W, int SG, bool D>
+static int launch_multi_t(int threads, int blocks, int lds, const MultiRun *runs, const int2 *work, int k,
+                          void *stream)
+{
+    static int configured[kMaxDevices] = {};
+    if (allow_lds(reinterpret_cast<const void *>(&sweep_bytes_multi_kernel<W, SG, D>), configured, lds,
+                  "hipFuncSetAttribute(sweep_bytes_multi)"))
+        return -1;
+    hipLaunchKernelGGL((sweep_bytes_multi_kernel<W, SG, D>), dim3(blocks), dim3(threads), lds,
+                       (hipStream_t)stream, runs, work, k);
+    return check("sweep_bytes_multi_kernel");
+}
+
+template <int W>
+static int launch_multi_w(int sgn, bool direct, int threads, int blocks, int lds, const MultiRun *runs,
+                          const int2 *work, int k, void *stream)
+{
+    if (sgn == 2) return direct ? launch_multi_t<W, 2, true>(threads, blocks, lds, runs, work, k, stream)
+                                : launch_multi_t<W, 2, false>(threads, blocks, lds, runs, work, k, stream);
+    return direct ? launch_multi_t<W, 0, true>(threads, blocks, lds, runs, work, k, stream)
+                  : launch_multi_t<W, 0, false>(threads, blocks, lds, runs, work, k, stream);
+}
+
+int launch_sweep_multi(int W, int sgn, bool direct, int threads, int blocks, int lds, const MultiRun *runs,
+                       const int2 *work, int k, void *stream)
+{
+    if (sgn == 1) {
+        snprintf(g_err, sizeof g_err, "multi-run sweeps take unsigned records or sign bits");
+        return -1;
+    }
+    switch (W) {
+    case 4: return launch_multi_w<4>(sgn, direct, threads, blocks, lds, runs, work, k, stream);
+    case 8: return launch_multi_w<8>(sgn, direct, threads, blocks, lds, runs, work, k, stream);
+    case 16: return launch_multi_w<16>(sgn, direct, threads, blocks, lds, runs, work, k, stream);
+    default:
+        snprintf(g_err, sizeof g_err, "unsupported byte-tile width %d", W);
+        return -1;
+    }
+}
+
+int launch_epilogue_multi(int runs_count, int max_R, const MultiRun *runs, int k, void *stream)
+{
+    const int lds = max_R * 4;
+    static int configured[kMaxDevices] = {};
+    if (allow_lds(reinterpret_cast<const void *>(&epilogue_multi_kernel), configured, lds,
+                  "hipFuncSetAttribute(epilogue_multi)"))
+        return -1;
+    hipLaunchKernelGGL(epilogue_multi_kernel, dim3(runs_count), dim3(kMaxThreads), lds, (hipStream_t)stream,
+                       runs, k);
+    return check("epilogue_multi_kernel");
 }
 
 int launch_epilogue(const EpiArgs &a, void *stream)

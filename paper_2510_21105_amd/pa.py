@@ -28,7 +28,8 @@ EXPORTS = ("pa_last_error", "pa_create", "pa_destroy", "pa_graph_info", "pa_work
            "pa_get_population", "pa_get_initial_population", "pa_get_step_stats",
            "pa_get_counts", "pa_get_launch_info", "pa_set_timing", "pa_get_sweep_time",
            "pa_run_steps", "pa_checkpoint_bytes", "pa_checkpoint_save", "pa_checkpoint_load",
-           "pa_run_static")
+           "pa_run_static", "pa_fused_create", "pa_fused_workspace_bytes", "pa_fused_tune",
+           "pa_fused_run", "pa_fused_set_graph", "pa_fused_info", "pa_fused_destroy")
 STATIC_SCRATCH_BYTES = 64 << 20     # PA_STATIC_SCRATCH_BYTES
 
 
@@ -74,6 +75,16 @@ class BatchRun(ctypes.Structure):
     ]
 
 
+class FusedEntry(ctypes.Structure):
+    _fields_ = [
+        ("solver", ctypes.c_void_p),
+        ("schedule", ctypes.POINTER(Schedule)),
+        ("R", ctypes.c_int32),
+        ("seed", ctypes.c_uint64),
+        ("instance", ctypes.c_uint32),
+    ]
+
+
 _lib = None
 
 
@@ -97,6 +108,13 @@ def lib():
             "pa_run": [P, ctypes.POINTER(Schedule), i32, u64, u32, P, ctypes.c_size_t, P],
             "pa_run_batch": [ctypes.POINTER(BatchRun), i32, ctypes.POINTER(P), i32],
             "pa_run_static": [P, ctypes.POINTER(Schedule), i32, u64, u32, P],
+            "pa_fused_create": [ctypes.POINTER(P), ctypes.POINTER(FusedEntry), i32],
+            "pa_fused_workspace_bytes": [P, ctypes.POINTER(ctypes.c_size_t)],
+            "pa_fused_tune": [P, P, ctypes.c_size_t, P, i32],
+            "pa_fused_run": [P, P, ctypes.c_size_t, P],
+            "pa_fused_set_graph": [P, i32],
+            "pa_fused_info": [P, P, i32, ctypes.POINTER(i32)],
+            "pa_fused_destroy": [P],
             "pa_build_tables": [ctypes.POINTER(Schedule), i32, i32, P, ctypes.POINTER(ctypes.c_size_t)],
             "pa_best_cut": [P, ctypes.POINTER(i64), ctypes.POINTER(i32)],
             "pa_best_info": [P, P],
@@ -393,6 +411,79 @@ def run_batch(solvers, params, streams):
         s._started(p, sch, keep, workspace)
     _check(st)
     return solvers
+
+
+class FusedBatch:
+    """Runs sharing kernel launches (pa_fused_*): one solver per run; after
+    ``run`` each solver answers the result calls as after ``Solver.run``."""
+
+    def __init__(self, solvers, params):
+        if len(solvers) != len(params):
+            raise ValueError("one RunParams per solver")
+        self.solvers = list(solvers)
+        self.params = list(params)
+        self._keep = [Solver._schedule(p) for p in self.params]
+        entries = (FusedEntry * len(self.solvers))()
+        for i, (s, p, (sch, _)) in enumerate(zip(self.solvers, self.params, self._keep)):
+            entries[i] = FusedEntry(s._h.value, ctypes.pointer(sch), p.R, p.seed, p.inst)
+        h = ctypes.c_void_p()
+        _check(lib().pa_fused_create(ctypes.byref(h), entries, len(self.solvers)))
+        self._h = h
+        self._workspace = None
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().pa_fused_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def workspace_bytes(self) -> int:
+        b = ctypes.c_size_t()
+        _check(lib().pa_fused_workspace_bytes(self._h, ctypes.byref(b)))
+        return int(b.value)
+
+    def _ws(self):
+        import torch
+        need = self.workspace_bytes()
+        if self._workspace is None or self._workspace.numel() < need + 256:
+            self._workspace = torch.empty(need + 256, dtype=torch.uint8, device="cuda")
+        base = self._workspace.data_ptr()
+        aligned = (base + 255) // 256 * 256
+        return aligned, self._workspace.numel() - (aligned - base)
+
+    def tune(self, probe_steps: int = 3, stream=None):
+        import torch
+        ws, n = self._ws()
+        st = torch.cuda.current_stream() if stream is None else stream
+        _check(lib().pa_fused_tune(self._h, ctypes.c_void_p(ws), n, ctypes.c_void_p(st.cuda_stream),
+                                   probe_steps))
+        return self.info()
+
+    def set_graph(self, on: bool):
+        _check(lib().pa_fused_set_graph(self._h, 1 if on else 0))
+
+    def run(self, stream=None):
+        import torch
+        ws, n = self._ws()
+        st = torch.cuda.current_stream() if stream is None else stream
+        _check(lib().pa_fused_run(self._h, ctypes.c_void_p(ws), n, ctypes.c_void_p(st.cuda_stream)))
+        for s, p, (sch, keep) in zip(self.solvers, self.params, self._keep):
+            s._started(p, sch, keep, self._workspace)
+        return self
+
+    def info(self):
+        ng = ctypes.c_int32()
+        _check(lib().pa_fused_info(self._h, None, 0, ctypes.byref(ng)))
+        out = np.zeros((max(ng.value, 1), 8), dtype=np.int64)
+        _check(lib().pa_fused_info(self._h, _p(out), ng.value, ctypes.byref(ng)))
+        keys = ("record_mode", "runs", "tile_replicas", "threads", "offset_entries", "workgroups",
+                "lds_bytes", "fs_per_attempt")
+        return [dict(zip(keys, (int(v) for v in row))) for row in out[:ng.value]]
 
 
 def params_from_workload(wl: dict, **over) -> RunParams:

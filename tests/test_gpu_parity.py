@@ -373,6 +373,88 @@ def test_batched_runs_equal_solo_runs(pa):
         assert np.array_equal(s.best_config(), ref.best_x), w["desc"]
 
 
+def _fused_mix():
+    wls = W.batch_workloads(6, steps=12)
+    wls[2] = dict(wls[2], as_enable=1, as_stall_steps=1, as_frozen_inv=8)   # noise levels too
+    return wls, [pa_params(w) for w in wls]
+
+
+def pa_params(w):
+    from paper_2510_21105_amd import pa as _pa
+    return _pa.params_from_workload(w, R=min(w["R"], 700), record=3)
+
+
+def _check_against_oracle(s, w, p):
+    ref = O.run_workload(dict(w, R=p.R), want_counts=True)
+    assert np.array_equal(s.step_stats(), ref.stats), w["desc"]
+    x, E = s.population()
+    assert np.array_equal(E, ref.E) and np.array_equal(x, ref.x), w["desc"]
+    info = s.best_info()
+    assert (info["E"], info["step"], info["sweep"], info["replica"]) == \
+        (ref.best_E, ref.best_step, ref.best_sweep, ref.best_replica), w["desc"]
+    assert np.array_equal(s.best_config(), ref.best_x), w["desc"]
+    assert np.array_equal(s.counts()[:-1], ref.counts[:-1]), w["desc"]
+    assert np.array_equal(s.initial_population(), ref.x_init), w["desc"]
+
+
+def test_fused_batch_equals_oracle(pa):
+    """Uneven random graphs and signed tori sharing launches (one sweep launch
+    and one epilogue launch per step for each record mode): every run equals
+    the oracle in statistics, population, best record, configuration, copy
+    counts and initial population."""
+    wls, params = _fused_mix()
+    solvers = [pa.Solver(w["graph"]) for w in wls]
+    fb = pa.FusedBatch(solvers, params)
+    info = fb.info()
+    _say(f"fused groups {info}")
+    assert {g["record_mode"] for g in info} == {0, 2}
+    assert sum(g["runs"] for g in info) == len(wls)
+    fb.run()
+    for w, p, s in zip(wls, params, solvers):
+        _check_against_oracle(s, w, p)
+
+
+def test_fused_batch_tuned_graph_replays_equal_eager(pa):
+    """After the autotuner picks each group's shape, the HIP-graph step loop
+    replayed three times (with eager runs and synchronisations between) and
+    the same launches enqueued directly all give identical results, equal to
+    each run alone."""
+    import torch
+    wls, params = _fused_mix()
+    solvers = [pa.Solver(w["graph"]) for w in wls]
+    fb = pa.FusedBatch(solvers, params)
+    info = fb.tune(probe_steps=2)
+    _say(f"tuned groups {info}")
+    assert all(g["fs_per_attempt"] > 0 for g in info)
+    solo = [pa.Solver(w["graph"]).run(p) for w, p in zip(wls, params)]
+    want = [(s.step_stats(), s.population(), s.best_info()) for s in solo]
+
+    def same():
+        for s, (st, (x, E), bi) in zip(solvers, want):
+            assert np.array_equal(s.step_stats(), st)
+            x2, E2 = s.population()
+            assert np.array_equal(E2, E) and np.array_equal(x2, x)
+            assert s.best_info() == bi
+
+    for rep in range(3):
+        fb.run()
+        torch.cuda.synchronize()
+        same()
+        pa.Solver(wls[0]["graph"]).run(params[0])      # unrelated eager work in between
+        torch.cuda.synchronize()
+    fb.set_graph(False)
+    fb.run()
+    same()
+
+
+def test_fused_batch_rejects_runs_it_cannot_share(pa):
+    wl = dict(W.workload("small800"), nl_period=3)
+    s = pa.Solver(wl["graph"])
+    with pytest.raises(pa.PAError) as e:
+        pa.FusedBatch([s], [pa.params_from_workload(wl)])
+    assert e.value.status == pa.PA_EINVAL and "non-local" in str(e.value)
+
+
 def test_greedy_coloring_order(pa):
     """Colour-class order (few dependency levels) on a signed and an unsigned graph."""
     g = W.random_graph(800, 4000, 1, "small800")

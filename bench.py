@@ -78,15 +78,24 @@ def measured_valu_per_launch(workload: str):
 
 
 def cpu_baseline(wl, sample_steps: int):
+    """The oracle, built for this host (-O3 -march=native, OpenMP over
+    replicas), on the first `sample_steps` steps of the workload with a
+    quarter of its replicas (the oracle's cost is linear in the replica
+    count), scaled to attempts/s; plus one thread on the first 2 steps. The
+    first steps sweep at the hottest inverse temperatures, where the most
+    moves are accepted, so the figure leans slow against the whole anneal."""
     from oracle import oracle as O
+    O.use_native_build()
     betas = wl["betas"][:sample_steps]
+    R = max(1, wl["R"] // 4)
+    if wl.get("nl_period", 0) and wl.get("nl_kind", 0) == 0:
+        R += R & 1
     cores = O.num_threads()       # before the one-thread sample below changes it
     t0 = time.perf_counter()
-    O.run_workload(wl, betas=betas, want_population=False, want_counts=False)
+    O.run_workload(wl, betas=betas, R=R, want_population=False, want_counts=False)
     dt = time.perf_counter() - t0
-    attempts = wl["R"] * wl["graph"].n * wl["sweeps"] * len(betas)
-    # One host thread on a shorter sample (the first steps, a quarter of the replicas).
-    one = dict(wl, R=max(1, wl["R"] // 4), betas=wl["betas"][:2], nthreads=1)
+    attempts = R * wl["graph"].n * wl["sweeps"] * len(betas)
+    one = dict(wl, R=R, betas=wl["betas"][:2], nthreads=1)
     t1 = time.perf_counter()
     O.run_workload(one, want_population=False, want_counts=False)
     dt1 = time.perf_counter() - t1
@@ -94,8 +103,10 @@ def cpu_baseline(wl, sample_steps: int):
     return {"value": attempts / dt, "unit": "attempts/s", "cores": cores,
             "kind": "oracle",
             "sample": f"first {len(betas)} of {len(wl['betas'])} temperature steps of the same "
-                      f"workload (R={wl['R']}, N={wl['graph'].n}, S={wl['sweeps']}), "
-                      f"{dt:.1f} s on the host",
+                      f"workload with R={R} of its {wl['R']} replicas (N={wl['graph'].n}, "
+                      f"S={wl['sweeps']}), {dt:.1f} s on the host, oracle built -O3 -march=native; "
+                      f"the whole solve at this rate: {wl['R'] * wl['graph'].n * wl['sweeps'] * len(wl['betas']) / (attempts / dt):.0f} s "
+                      f"(a linear extrapolation)",
             "value_1thread": attempts1 / dt1,
             "sample_1thread": f"first 2 steps with R={one['R']} on one thread, {dt1:.1f} s"}
 
@@ -295,7 +306,7 @@ def main():
                     help="0 automatic, 1 node-per-lane byte records, 2 replica-per-lane bit words")
     ap.add_argument("--tile", type=int, default=0, help="replicas per workgroup (0 automatic)")
     ap.add_argument("--threads", type=int, default=0, help="threads per sweep workgroup (0 automatic)")
-    ap.add_argument("--cpu-sample-steps", type=int, default=20)
+    ap.add_argument("--cpu-sample-steps", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain int32 elementwise kernel of known size "
@@ -380,19 +391,40 @@ def main():
     achieved_gbs = b_alg * per_launch_attempts / avg_launch_s / 1e9
     traffic = measured_traffic_per_launch(args.workload)
     copy_gbs = copy_bandwidth_gbs()
-    roof = {"bound": "hbm", "achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": round(achieved_gbs / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "measured_copy_gbs": round(copy_gbs, 1),
-            "frac_of_copy": round(achieved_gbs / copy_gbs, 4)}
-    # The sweep keeps its state in LDS, so beside the streaming-model figure
-    # above: the vector ALU issue rate it reaches, from the measured
-    # instruction count (not an algorithmic count) and the live launch time.
+    # The sweep keeps a step's spins in LDS and reads HBM only to load and
+    # store the population once per step, so the roof that binds it is
+    # vector-ALU issue (with LDS latency), not HBM: `roofline` is the VALU
+    # issue rate the kernel reaches -- its measured VALU wave instructions
+    # per launch (rocprofv3 SQ_INSTS_VALU, committed under profiles/ and used
+    # only while the kernel source matches) x 64 lanes / the live average
+    # launch time -- against 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz. Beside
+    # it: the method's own integer operations per attempt (an algorithmic
+    # count: one add per neighbour for the local field, 6 for the test,
+    # flip and bookkeeping, and a quarter of a Philox4x32-10 call, 25
+    # operations, per uphill attempt), the measured HBM bytes per launch, and
+    # the streaming model of int8 spins and int16 fields the survey prices
+    # the sweep with.
+    f_up = att_up / attempts
+    alg_ops = dbar + 6.0 + 25.0 * f_up
+    roof = {"bound": "alu", "achieved": None, "peak": VALU_PEAK_LANE_OPS, "unit": "VALU lane-op/s",
+            "frac": None, "traffic": traffic,
+            "basis": "issued VALU lane-ops (rocprofv3 SQ_INSTS_VALU per launch x 64) / live launch time",
+            "algorithmic": {"ops_per_attempt": round(alg_ops, 2), "uphill_fraction": round(f_up, 4),
+                            "achieved": float(f"{alg_ops * per_launch_attempts / avg_launch_s:.4g}"),
+                            "frac": round(alg_ops * per_launch_attempts / avg_launch_s /
+                                          VALU_PEAK_LANE_OPS, 4)},
+            "hbm_model": {"achieved_gbs": round(achieved_gbs, 1), "peak_gbs": HBM_PEAK_GBS,
+                          "frac": round(achieved_gbs / HBM_PEAK_GBS, 4),
+                          "bytes_per_attempt": round(b_alg, 3),
+                          "measured_copy_gbs": round(copy_gbs, 1),
+                          "measured_gbs": (round(traffic / avg_launch_s / 1e9, 1)
+                                           if traffic is not None else None)}}
     valu = measured_valu_per_launch(args.workload)
     if valu is not None:
         lane_ops = valu * 64 / avg_launch_s
-        roof["alu"] = {"achieved": float(f"{lane_ops:.4g}"), "peak": VALU_PEAK_LANE_OPS,
-                       "unit": "VALU lane-op/s", "frac": round(lane_ops / VALU_PEAK_LANE_OPS, 4),
-                       "source": "measured VALU instructions per launch (rocprofv3 SQ_INSTS_VALU)"}
+        roof["achieved"] = float(f"{lane_ops:.4g}")
+        roof["frac"] = round(lane_ops / VALU_PEAK_LANE_OPS, 4)
+        roof["issued_ops_per_attempt"] = round(valu * 64 / per_launch_attempts, 2)
 
     out = {
         "metric": "spin-flip attempts/s",

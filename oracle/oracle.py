@@ -35,6 +35,29 @@ def build(force: bool = False) -> str:
     return LIB
 
 
+def use_native_build() -> str:
+    """Switch this process to a build of the same source for the host it runs
+    on (-O3 -march=native; no fast-math, so results are unchanged), compiled
+    into a per-host file on first use. Timing only: the tests use the
+    portable build."""
+    global _lib, LIB
+    import platform
+    import tempfile
+    tag = platform.node().replace("/", "_") or "host"
+    path = os.path.join(tempfile.gettempdir(), f"liboracle_native_{tag}_{os.getuid()}.so")
+    if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(SRC):
+        tmp = path + f".tmp{os.getpid()}"
+        subprocess.check_call(["gcc", "-O3", "-march=native", "-std=c11", "-Wall", "-fopenmp",
+                               "-shared", "-fPIC", "-o", tmp, SRC, "-lm"])
+        os.replace(tmp, path)
+    if _lib is not None and LIB == path:
+        return path
+    LIB = path
+    _lib = None
+    lib()
+    return path
+
+
 def lib():
     global _lib
     if _lib is None:

@@ -205,8 +205,12 @@ def batch_bench(args, count: int):
 
 
 def serve_bench(args, count: int):
-    """Serving: capacity with every request present, then Poisson arrivals at
-    0.5x and 0.9x that capacity (p50/p99 latency), and FIFO on one stream."""
+    """Serving with continuous batching (the resident pool, pa_pool_*: each
+    iteration one step of every admitted request in shared launches):
+    capacity with every request present, then Poisson arrivals at 0.5x and
+    0.9x that capacity (p50/p99 latency); beside it the stream-per-request
+    server's capacity and FIFO sequential plain PA (one request at a time) at
+    0.5x. Results must equal across all of them."""
     import torch
     from paper_2510_21105_amd import pa, serve as S, workloads as W
 
@@ -220,10 +224,9 @@ def serve_bench(args, count: int):
 
     budget = int(args.hbm_budget_gb * (1 << 30))
 
-    def run(rate, streams):
-        srv = S.Server(budget, n_streams=streams)
+    def run(rate, server):
         t0 = time.perf_counter()
-        res = srv.serve(requests(rate), realtime=rate is not None)
+        res = server.serve(requests(rate), realtime=rate is not None)
         torch.cuda.synchronize()
         span_s = time.perf_counter() - t0
         lat = [r.latency for r in res]
@@ -231,21 +234,31 @@ def serve_bench(args, count: int):
         return dict(requests_per_s=count / span_s, p50_s=S.percentile(lat, 50),
                     p99_s=S.percentile(lat, 99), makespan_s=span_s), cuts
 
-    print(f"[bench] serving {count} requests, {args.streams} streams", file=sys.stderr, flush=True)
-    run(None, args.streams)                                   # warm-up (allocator, tables)
-    cap, cuts0 = run(None, args.streams)
-    print(f"[bench] capacity {cap['requests_per_s']:.2f} requests/s", file=sys.stderr, flush=True)
+    pool = S.PoolServer(budget)
+    print(f"[bench] serving {count} requests, pool of {args.hbm_budget_gb} GB", file=sys.stderr,
+          flush=True)
+    run(None, pool)                                           # warm-up (allocator, tables)
+    cap, cuts0 = run(None, pool)
+    print(f"[bench] pool capacity {cap['requests_per_s']:.2f} requests/s", file=sys.stderr, flush=True)
     out_loads = {}
     for f in (0.5, 0.9):
-        m, cuts = run(f * cap["requests_per_s"], args.streams)
+        m, cuts = run(f * cap["requests_per_s"], pool)
         if cuts != cuts0:
             raise RuntimeError("served results depend on the mix")
         out_loads[f"{f:.1f}x"] = m
-        print(f"[bench] offered {f:.1f}x: {m}", file=sys.stderr, flush=True)
-    fifo, cuts = run(0.5 * cap["requests_per_s"], 1)
+        print(f"[bench] pool offered {f:.1f}x: {m}", file=sys.stderr, flush=True)
+    streams_cap, cuts = run(None, S.Server(budget, n_streams=args.streams))
+    if cuts != cuts0:
+        raise RuntimeError("served results depend on the server")
+    print(f"[bench] stream server capacity: {streams_cap}", file=sys.stderr, flush=True)
+    seq_cap, cuts = run(None, S.Server(budget, n_streams=1))
+    if cuts != cuts0:
+        raise RuntimeError("served results depend on the server")
+    print(f"[bench] sequential plain PA (one at a time) capacity: {seq_cap}", file=sys.stderr, flush=True)
+    fifo, cuts = run(0.5 * cap["requests_per_s"], S.Server(budget, n_streams=1))
     if cuts != cuts0:
         raise RuntimeError("served results depend on the mix")
-    print(f"[bench] FIFO one stream at 0.5x: {fifo}", file=sys.stderr, flush=True)
+    print(f"[bench] FIFO one at a time at 0.5x: {fifo}", file=sys.stderr, flush=True)
     out = {
         "metric": "requests/s",
         "value": cap["requests_per_s"],
@@ -261,12 +274,16 @@ def serve_bench(args, count: int):
         "data": "synthetic",
         "config": {"workload": f"serve{count}: N log-uniform [800, 20000] (half random "
                                "G(N, N d/2) with d ~ U[2,12], half +-1 tori), R log-uniform "
-                               "[512, 8192], K=500, S=5, Poisson arrivals",
-                   "requests": count, "streams": args.streams,
-                   "hbm_budget_gb": args.hbm_budget_gb},
+                               "[512, 8192], K=500, S=5, Poisson arrivals; continuous batching "
+                               "in a resident pool",
+                   "requests": count, "hbm_budget_gb": args.hbm_budget_gb},
         "capacity": cap,
         "offered": out_loads,
-        "fifo_one_stream_0.5x": fifo,
+        "stream_server_capacity": streams_cap,
+        "streams": args.streams,
+        "sequential_capacity": seq_cap,
+        "speedup_vs_sequential": cap["requests_per_s"] / seq_cap["requests_per_s"],
+        "fifo_one_at_a_time_0.5x": fifo,
     }
     print(json.dumps(out), flush=True)
 

@@ -343,6 +343,61 @@ pa_status pa_fused_set_graph(pa_fused *f, int32_t on);
 pa_status pa_fused_info(const pa_fused *f, int64_t *out, int32_t max_groups, int32_t *groups);
 pa_status pa_fused_destroy(pa_fused *f);
 
+/* Opaque pool of resident runs advanced together (continuous batching). */
+typedef struct pa_pool pa_pool;
+
+/*
+ * A pool of runs sharing the device as they come and go (serving): the pool
+ * works inside a caller-owned device region (its HBM budget) and admits
+ * submitted runs in arrival order, without overtaking, as their state fits
+ * the memory left. Admitted runs of one launch shape (record mode, tile
+ * width, entry form, threads, LDS occupancy class) form a lane with a stream
+ * of its own; each iteration of a lane advances all its runs by one
+ * temperature step, each at its own step: one sweep launch over the replica
+ * tiles of those runs and one epilogue launch with a workgroup per run.
+ * Lanes progress independently. A run's population stays resident on the
+ * device from admission to release. Every run gives exactly the results of
+ * pa_run with the same arguments (GPU tests compare with the oracle).
+ *
+ *   pa_pool_create    over `workspace` (256-byte aligned device memory,
+ *                     kept by the caller until pa_pool_destroy); about 10 MB
+ *                     of it hold the lanes' argument tables, the rest the
+ *                     runs. Host only.
+ *   pa_pool_submit    queues a run (a valid pa_run with nl_period = 0 and
+ *                     beta_adapt = 0, maximum degree <= 127; inputs copied)
+ *                     and returns its ticket. PA_EWORKSPACE if it can never
+ *                     fit the pool; PA_EINVAL if its solver already has an
+ *                     unreleased run in the pool.
+ *   pa_pool_cancel    drops a run that is still waiting (PA_ESTATE if it was
+ *                     admitted).
+ *   pa_pool_advance   admits what fits (setting it up on `stream`, always
+ *                     the same stream for a pool), then enqueues up to
+ *                     `iterations` (1..1024) iterations of every lane on the
+ *                     lane's stream, rebuilding a lane's argument tables only
+ *                     when runs join or leave it; a lane with two batches
+ *                     still in flight is skipped this call. *done = lane
+ *                     iterations enqueued (0: nothing to step now).
+ *                     Asynchronous; never waits for a busy lane.
+ *   pa_pool_poll      tickets of runs that have finished since the last poll
+ *                     (up to cap); their solvers answer the pa_best_* /
+ *                     pa_get_* calls as after pa_run, until released.
+ *   pa_pool_release   returns a finished run's memory to the pool; its
+ *                     solver's results are gone afterwards (PA_ESTATE before
+ *                     its last step was enqueued).
+ *   pa_pool_info      {waiting, stepping, finished and not released, bytes
+ *                     in use, bytes for runs, iterations so far}.
+ *   pa_pool_destroy   waits for the pool's stream and releases the pool.
+ * Solvers must outlive their runs in the pool.
+ */
+pa_status pa_pool_create(pa_pool **out, void *workspace, size_t workspace_bytes);
+pa_status pa_pool_submit(pa_pool *p, const pa_fused_entry *run, int64_t *ticket);
+pa_status pa_pool_cancel(pa_pool *p, int64_t ticket);
+pa_status pa_pool_advance(pa_pool *p, void *stream, int32_t iterations, int32_t *done);
+pa_status pa_pool_poll(pa_pool *p, int64_t *tickets, int32_t cap, int32_t *count);
+pa_status pa_pool_release(pa_pool *p, int64_t ticket);
+pa_status pa_pool_info(const pa_pool *p, int64_t out[6]);
+pa_status pa_pool_destroy(pa_pool *p);
+
 /*
  * Test hook: the fixed-point tables a run with this schedule uses, dense, as
  * little-endian u64 into caller memory `out` (NULL: only *bytes is set):

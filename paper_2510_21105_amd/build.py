@@ -8,7 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 SOURCES = [os.path.join(CSRC, "pa_kernels.hip"), os.path.join(CSRC, "pa_api.cpp"),
-           os.path.join(CSRC, "pa_fused.cpp")]
+           os.path.join(CSRC, "pa_fused.cpp"), os.path.join(CSRC, "pa_pool.cpp")]
 HEADERS = [os.path.join(CSRC, "pa_device.h"), os.path.join(CSRC, "pa_host.h"),
            os.path.join(ROOT, "include", "pa.h")]
 LIB = os.path.join(HERE, "libpa.so")

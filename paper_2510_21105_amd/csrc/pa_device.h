@@ -108,6 +108,7 @@ struct MultiRun {
     int *E0, *E1;
     int steps;                  // K: steps at or past it do nothing
     int nblk;                   // sweep tiles of this run
+    int k_off;                  // launch index of the run's step 0
 };
 
 struct GatherArgs {

@@ -65,6 +65,62 @@ struct pa_fused {
     int use_graph = 1;
 };
 
+// The work list of a multi-run sweep launch: the tiles of the runs (run q
+// has nblk[q] tiles of W replicas), taken in 64-replica words (64/W tiles
+// that share spin words), the words dealt round-robin over the 8 XCDs in run
+// order, so that tiles sharing a word meet in one L2 and every XCD gets a
+// like mix. Empty slots are {-1, 0}.
+std::vector<int2> pa_host::multi_work_list(const std::vector<int> &nblk, int W)
+{
+    const int per = 64 / W;
+    std::vector<int2> words;                      // {run, first tile}
+    for (int q = 0; q < (int)nblk.size(); ++q)
+        for (int t = 0; t < nblk[q]; t += per) words.push_back(int2{q, t});
+    const int nw = (int)words.size();
+    const int rows = (nw + 7) / 8;
+    std::vector<int2> w((size_t)rows * 8 * per, int2{-1, 0});
+    for (int b = 0; b < (int)w.size(); ++b) {
+        const int x = b & 7, slot = b >> 3;
+        const int wi = x + 8 * (slot / per), t = slot % per;
+        if (wi >= nw) continue;
+        const int q = words[wi].x;
+        const int tile = words[wi].y + t;
+        if (tile < nblk[q]) w[b] = int2{q, tile};
+    }
+    return w;
+}
+
+// After its last step is enqueued on `hs`: the solver holds the finished
+// run, as after pa_run (the population of step k is written to X1 for even
+// k, so the last step's output is X(K & 1)).
+void pa_host::finish_run(pa_solver *s, hipStream_t hs)
+{
+    pa_solver::RunCtx &c = s->rc;
+    const int K = s->plan.K;
+    const bool odd = (K & 1) != 0;
+    c.Xc = odd ? s->plan.L.X1 : s->plan.L.X0;
+    c.Xn = odd ? s->plan.L.X0 : s->plan.L.X1;
+    c.Ec = odd ? s->plan.L.E1 : s->plan.L.E0;
+    c.En = odd ? s->plan.L.E0 : s->plan.L.E1;
+    c.parents_pending = false;
+    c.next_step = K;
+    c.valid = true;
+    s->final_x = c.Xc;
+    s->final_E = c.Ec;
+    s->stream = hs;
+    s->has_run = true;
+}
+
+int pa_host::device_max_lds()
+{
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && v > 0)
+        return v;
+    (void)hipGetLastError();
+    return 160 * 1024;
+}
+
 namespace {
 
 // Tile widths the autotuner tries (threads: the group's count, half and double).
@@ -103,31 +159,11 @@ void drop_graph(pa_fused *f)
     f->graph_ws = nullptr;
 }
 
-// The work list of a group for its current shape: the tiles of its runs,
-// taken in 64-replica words (64/W tiles that share spin words), the words
-// dealt round-robin over the 8 XCDs in run order (most work first), so that
-// tiles sharing a word meet in one L2 and every XCD gets a like mix.
 std::vector<int2> work_list(const pa_fused *f, const pa_fused::Group &g)
 {
-    const int per = 64 / g.shape.W;
-    std::vector<int2> words;                      // {member, first tile}
-    for (int q = 0; q < (int)g.members.size(); ++q) {
-        const int nblk = (f->runs[g.members[q]].R + g.shape.W - 1) / g.shape.W;
-        for (int t = 0; t < nblk; t += per) words.push_back(int2{q, t});
-    }
-    const int nw = (int)words.size();
-    const int rows = (nw + 7) / 8;
-    std::vector<int2> w((size_t)rows * 8 * per, int2{-1, 0});
-    for (int b = 0; b < (int)w.size(); ++b) {
-        const int x = b & 7, slot = b >> 3;
-        const int wi = x + 8 * (slot / per), t = slot % per;
-        if (wi >= nw) continue;
-        const int q = words[wi].x;
-        const int tile = words[wi].y + t;
-        const int nblk = (f->runs[g.members[q]].R + g.shape.W - 1) / g.shape.W;
-        if (tile < nblk) w[b] = int2{q, tile};
-    }
-    return w;
+    std::vector<int> nblk;
+    for (int i : g.members) nblk.push_back((f->runs[i].R + g.shape.W - 1) / g.shape.W);
+    return multi_work_list(nblk, g.shape.W);
 }
 
 // Work-list length and sweep LDS of a group's current shape.
@@ -237,24 +273,7 @@ pa_status enqueue_all_steps(pa_fused *f, unsigned char *ws, hipStream_t hs)
 // After the step loop: each solver holds its finished run, as after pa_run.
 void finish_runs(pa_fused *f, hipStream_t hs)
 {
-    for (auto &r : f->runs) {
-        pa_solver *s = r.s;
-        pa_solver::RunCtx &c = s->rc;
-        const int K = s->plan.K;
-        // Step k writes X1 for even k: the last step's output is X(K & 1).
-        const bool odd = (K & 1) != 0;
-        c.Xc = odd ? s->plan.L.X1 : s->plan.L.X0;
-        c.Xn = odd ? s->plan.L.X0 : s->plan.L.X1;
-        c.Ec = odd ? s->plan.L.E1 : s->plan.L.E0;
-        c.En = odd ? s->plan.L.E0 : s->plan.L.E1;
-        c.parents_pending = false;
-        c.next_step = K;
-        c.valid = true;
-        s->final_x = c.Xc;
-        s->final_E = c.Ec;
-        s->stream = hs;
-        s->has_run = true;
-    }
+    for (auto &r : f->runs) finish_run(r.s, hs);
 }
 
 }  // namespace
@@ -267,14 +286,7 @@ extern "C" pa_status pa_fused_create(pa_fused **out, const pa_fused_entry *runs,
     pa_fused *f = new (std::nothrow) pa_fused;
     if (!f) return fail(PA_ERANGE, "pa_fused_create: out of host memory");
     std::vector<const pa_solver *> seen;
-    int dev = 0;
-    if (hipGetDevice(&dev) == hipSuccess) {
-        int v = 0;
-        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && v > 0)
-            f->max_lds = v;
-    } else {
-        (void)hipGetLastError();
-    }
+    f->max_lds = device_max_lds();
     auto bail = [&](pa_status st) {
         delete f;
         return st;

@@ -81,6 +81,13 @@ pa_status start_run(pa_solver *s, const pa_schedule *sch, int32_t R, uint64_t se
                     void *workspace, size_t workspace_bytes, void *stream, bool fresh, bool pinned = true,
                     const Shape *force = nullptr);
 
+// Work list {run, tile} of a multi-run sweep launch (pa_fused.cpp).
+std::vector<int2> multi_work_list(const std::vector<int> &nblk, int W);
+// Mark a run whose last step has been enqueued on `hs` as finished.
+void finish_run(pa_solver *s, hipStream_t hs);
+// The largest dynamic LDS of a workgroup on the current device.
+int device_max_lds();
+
 }  // namespace pa_host
 
 struct pa_solver {

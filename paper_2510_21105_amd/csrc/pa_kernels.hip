@@ -1187,19 +1187,21 @@ __global__ __launch_bounds__(1024) void sweep_bytes_kernel(SweepArgs a, const in
     sweep_bytes_tile<W, SG, DIRECT>(a, rounds, blocks, blk, nb);
 }
 
-// Step k of many runs in one launch: workgroup b takes the tile work[b] =
+// One step of many runs in one launch: workgroup b takes the tile work[b] =
 // {run, tile} (run < 0: an empty slot), with the run's arguments from
-// runs[run]; the step's population buffers follow from the parity of k (the
-// initial population is in X0/E0), and step 0 reads no resampling parents.
-// Runs whose schedule ended before step k do nothing.
+// runs[run]. Launch index t is step t - k_off of a run; its population
+// buffers follow from the parity of that step (the initial population is in
+// X0/E0), and step 0 reads no resampling parents. Runs outside their steps
+// do nothing.
 template <int W, int SG, bool DIRECT>
 __global__ __launch_bounds__(1024) void sweep_bytes_multi_kernel(const MultiRun *__restrict__ runs,
-                                                                const int2 *__restrict__ work, int k)
+                                                                const int2 *__restrict__ work, int t)
 {
     const int2 wk = work[blockIdx.x];
     if (wk.x < 0) return;
     const MultiRun &m = runs[wk.x];
-    if (k >= m.steps) return;
+    const int k = t - m.k_off;
+    if (k < 0 || k >= m.steps) return;
     SweepArgs a = m.sweep;
     const bool even = (k & 1) == 0;
     a.k = k;
@@ -1499,12 +1501,14 @@ __device__ __forceinline__ void epilogue_body(const EpiArgs &a)
 
 __global__ __launch_bounds__(1024) void epilogue_kernel(EpiArgs a) { epilogue_body(a); }
 
-// The epilogue of step k of many runs in one launch, one workgroup per run
-// (the population after step k's sweeps is in X1/E1 for even k).
-__global__ __launch_bounds__(1024) void epilogue_multi_kernel(const MultiRun *__restrict__ runs, int k)
+// The epilogue of one step of many runs in one launch, one workgroup per run
+// (launch index t is step t - k_off of a run; the population after step k's
+// sweeps is in X1/E1 for even k).
+__global__ __launch_bounds__(1024) void epilogue_multi_kernel(const MultiRun *__restrict__ runs, int t)
 {
     const MultiRun &m = runs[blockIdx.x];
-    if (k >= m.steps) return;
+    const int k = t - m.k_off;
+    if (k < 0 || k >= m.steps) return;
     EpiArgs a = m.epi;
     const bool even = (k & 1) == 0;
     a.k = k;

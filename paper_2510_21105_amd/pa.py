@@ -29,7 +29,9 @@ EXPORTS = ("pa_last_error", "pa_create", "pa_destroy", "pa_graph_info", "pa_work
            "pa_get_counts", "pa_get_launch_info", "pa_set_timing", "pa_get_sweep_time",
            "pa_run_steps", "pa_checkpoint_bytes", "pa_checkpoint_save", "pa_checkpoint_load",
            "pa_run_static", "pa_fused_create", "pa_fused_workspace_bytes", "pa_fused_tune",
-           "pa_fused_run", "pa_fused_set_graph", "pa_fused_info", "pa_fused_destroy")
+           "pa_fused_run", "pa_fused_set_graph", "pa_fused_info", "pa_fused_destroy",
+           "pa_pool_create", "pa_pool_submit", "pa_pool_cancel", "pa_pool_advance", "pa_pool_poll",
+           "pa_pool_release", "pa_pool_info", "pa_pool_destroy")
 STATIC_SCRATCH_BYTES = 64 << 20     # PA_STATIC_SCRATCH_BYTES
 
 
@@ -115,6 +117,14 @@ def lib():
             "pa_fused_set_graph": [P, i32],
             "pa_fused_info": [P, P, i32, ctypes.POINTER(i32)],
             "pa_fused_destroy": [P],
+            "pa_pool_create": [ctypes.POINTER(P), P, ctypes.c_size_t],
+            "pa_pool_submit": [P, ctypes.POINTER(FusedEntry), ctypes.POINTER(i64)],
+            "pa_pool_cancel": [P, i64],
+            "pa_pool_advance": [P, P, i32, ctypes.POINTER(i32)],
+            "pa_pool_poll": [P, P, i32, ctypes.POINTER(i32)],
+            "pa_pool_release": [P, i64],
+            "pa_pool_info": [P, P],
+            "pa_pool_destroy": [P],
             "pa_build_tables": [ctypes.POINTER(Schedule), i32, i32, P, ctypes.POINTER(ctypes.c_size_t)],
             "pa_best_cut": [P, ctypes.POINTER(i64), ctypes.POINTER(i32)],
             "pa_best_info": [P, P],
@@ -484,6 +494,79 @@ class FusedBatch:
         keys = ("record_mode", "runs", "tile_replicas", "threads", "offset_entries", "workgroups",
                 "lds_bytes", "fs_per_attempt")
         return [dict(zip(keys, (int(v) for v in row))) for row in out[:ng.value]]
+
+
+class Pool:
+    """A resident pool of runs advanced together, one step per iteration
+    (pa_pool_*), inside a device region of ``budget`` bytes; or, with
+    ``workspace=(address, bytes)``, inside caller memory."""
+
+    def __init__(self, budget: int = 0, workspace=None):
+        if workspace is None:
+            import torch
+            self._mem = torch.empty(int(budget) + 256, dtype=torch.uint8, device="cuda")
+            base = self._mem.data_ptr()
+            addr = (base + 255) // 256 * 256
+            size = self._mem.numel() - (addr - base)
+        else:
+            self._mem = None
+            addr, size = workspace
+        h = ctypes.c_void_p()
+        _check(lib().pa_pool_create(ctypes.byref(h), ctypes.c_void_p(addr), size))
+        self._h = h
+        self._keep = {}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().pa_pool_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def submit(self, solver: "Solver", p: RunParams) -> int:
+        sch, keep = Solver._schedule(p)
+        e = FusedEntry(solver._h.value, ctypes.pointer(sch), p.R, p.seed, p.inst)
+        t = ctypes.c_int64()
+        _check(lib().pa_pool_submit(self._h, ctypes.byref(e), ctypes.byref(t)))
+        self._keep[t.value] = (solver, p, sch, keep)
+        return int(t.value)
+
+    def cancel(self, ticket: int):
+        _check(lib().pa_pool_cancel(self._h, ticket))
+        self._keep.pop(ticket, None)
+
+    def advance(self, stream=None, iterations: int = 1) -> int:
+        """Enqueue up to ``iterations`` iterations; return how many were."""
+        import torch
+        st = torch.cuda.current_stream() if stream is None else stream
+        n = ctypes.c_int32()
+        _check(lib().pa_pool_advance(self._h, ctypes.c_void_p(st.cuda_stream), iterations,
+                                     ctypes.byref(n)))
+        return int(n.value)
+
+    def poll(self, cap: int = 256):
+        out = np.zeros(cap, dtype=np.int64)
+        n = ctypes.c_int32()
+        _check(lib().pa_pool_poll(self._h, _p(out), cap, ctypes.byref(n)))
+        done = [int(t) for t in out[:n.value]]
+        for t in done:
+            solver, p, sch, keep = self._keep[t]
+            solver._started(p, sch, keep, self._mem)
+        return done
+
+    def release(self, ticket: int):
+        _check(lib().pa_pool_release(self._h, ticket))
+        self._keep.pop(ticket, None)
+
+    def info(self):
+        out = np.zeros(6, dtype=np.int64)
+        _check(lib().pa_pool_info(self._h, _p(out)))
+        keys = ("waiting", "stepping", "finished", "bytes_in_use", "bytes_for_runs", "iterations")
+        return dict(zip(keys, (int(v) for v in out)))
 
 
 def params_from_workload(wl: dict, **over) -> RunParams:

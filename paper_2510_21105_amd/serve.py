@@ -1,6 +1,10 @@
-"""Serving loop for population-annealing requests on one GPU.
+"""Serving loops for population-annealing requests on one GPU.
 
-Requests (a graph and its run parameters) arrive over time. The server admits
+``PoolServer`` batches continuously: admitted requests share each
+iteration's kernel launches (one step of every request per iteration) inside
+a resident device pool. ``Server`` runs each request on its own stream.
+
+Requests (a graph and its run parameters) arrive over time. ``Server`` admits
 them in arrival order whenever a stream is free and the device workspaces of
 the runs in flight, plus the new one (``pa_workspace_bytes``), fit an HBM
 budget; each admitted run is enqueued with ``pa_run`` on its own HIP stream,
@@ -180,6 +184,72 @@ class Server:
                 flights[rid] = _Flight(req, solver, stream, ev, start, need)
             if not started:
                 time.sleep(self.poll_s)
+        return results
+
+
+@dataclass
+class PoolServer:
+    """Continuous batching: requests join a resident pool (``pa_pool_*``)
+    whose device region is ``hbm_budget`` bytes; each iteration advances
+    every admitted request by one temperature step in shared launches, and a
+    request that finishes leaves, freeing its memory for the next in arrival
+    order. One stream for the pool; argument marshalling and scheduling only
+    -- all annealing work runs in the library's kernels."""
+    hbm_budget: int
+    poll_s: float = 2e-4
+    iterations: int = 8       # iterations enqueued per advance call (two calls in flight)
+
+    def serve(self, requests, realtime: bool = True, cancel=()) -> list:
+        """Serve ``requests`` (arrival times honoured when ``realtime``, else
+        all present at once); return one Result per request in completion
+        order. ``cancel`` holds (time, rid) pairs: a request still waiting at
+        that time is dropped (reported with ``cancelled``)."""
+        import torch
+        pool = pa.Pool(self.hbm_budget)
+        stream = torch.cuda.Stream()
+        pending = deque(sorted(requests, key=lambda r: (r.arrival, r.rid)))
+        cancels = deque(sorted(cancel))
+        live = {}           # ticket -> (request, solver, submit time)
+        waiting = {}        # rid -> ticket, until admitted or finished
+        results = []
+        t0 = time.perf_counter()
+        try:
+            while pending or live:
+                now = time.perf_counter() - t0
+                while pending and (not realtime or pending[0].arrival <= now):
+                    req = pending.popleft()
+                    solver = pa.Solver(req.graph)
+                    t = pool.submit(solver, req.params)
+                    live[t] = (req, solver, now)
+                    waiting[req.rid] = t
+                while cancels and (not realtime or cancels[0][0] <= now):
+                    _, rid = cancels.popleft()
+                    t = waiting.get(rid)
+                    if t is None:
+                        continue
+                    try:
+                        pool.cancel(t)
+                    except pa.PAError:
+                        continue            # already admitted: it runs
+                    req, solver, ts = live.pop(t)
+                    del waiting[rid]
+                    tc = time.perf_counter() - t0
+                    results.append(Result(req.rid, req.arrival, ts, tc, 0, 0, 0, cancelled=True))
+                stepped = pool.advance(stream, self.iterations)
+                for t in pool.poll():
+                    req, solver, ts = live.pop(t)
+                    waiting.pop(req.rid, None)
+                    info = solver.best_info()
+                    tf = time.perf_counter() - t0
+                    results.append(Result(req.rid, req.arrival, ts, tf, solver.best_cut(), info["E"],
+                                          0, best_info=info, best_x=solver.best_config(),
+                                          stats=solver.step_stats()))
+                    pool.release(t)
+                if stepped == 0:
+                    time.sleep(self.poll_s)
+            torch.cuda.synchronize()
+        finally:
+            pool.close()
         return results
 
 

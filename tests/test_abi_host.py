@@ -423,6 +423,46 @@ def test_static_workspace_run_refuses_oversized_runs_without_device_calls():
     assert L.pa_run_static(None, ctypes.byref(sch), 4, 0, 0, None) == pa.PA_EINVAL
 
 
+def test_pool_admission_errors_without_device_calls():
+    """pa_pool_*: the region must be aligned and hold more than the argument
+    tables; submissions are validated (no cluster moves or adaptive steps, one
+    run per solver, a run must fit the pool); cancel and release follow the
+    run's state. No device work happens before the first advance."""
+    L = pa.lib()
+    h = ctypes.c_void_p()
+    assert L.pa_pool_create(ctypes.byref(h), ctypes.c_void_p(4096 + 8), 1 << 30) == pa.PA_EWORKSPACE
+    assert L.pa_pool_create(ctypes.byref(h), ctypes.c_void_p(4096), 1 << 20) == pa.PA_EWORKSPACE
+    pool = pa.Pool(workspace=(1 << 20, 64 << 20))     # never dereferenced here
+    wl = W.workload("small800")
+    s = pa.Solver(wl["graph"])
+    t = pool.submit(s, pa.params_from_workload(wl))
+    assert pool.info()["waiting"] == 1
+    with pytest.raises(pa.PAError) as e:
+        pool.submit(s, pa.params_from_workload(wl))
+    assert e.value.status == pa.PA_EINVAL
+    s2 = pa.Solver(wl["graph"])
+    for bad, status in [(dict(nl_period=2), pa.PA_EINVAL), (dict(beta_adapt=1), pa.PA_EINVAL),
+                        (dict(R=32768, betas=wl["betas"]), pa.PA_EWORKSPACE)]:
+        if status == pa.PA_EWORKSPACE:
+            big = pa.Pool(workspace=(1 << 20, 16 << 20))
+            with pytest.raises(pa.PAError) as e:
+                big.submit(s2, pa.params_from_workload(wl, **bad))
+            big.close()
+        else:
+            with pytest.raises(pa.PAError) as e:
+                pool.submit(s2, pa.params_from_workload(wl, **bad))
+        assert e.value.status == status
+    with pytest.raises(pa.PAError) as e:
+        pool.release(t)                         # waiting, not finished
+    assert e.value.status == pa.PA_ESTATE
+    pool.cancel(t)
+    with pytest.raises(pa.PAError) as e:
+        pool.cancel(t)
+    assert e.value.status == pa.PA_ESTATE
+    assert pool.info()["waiting"] == 0 and pool.poll() == []
+    pool.close()
+
+
 def test_timing_stride_validation():
     s = pa.Solver(W.cycle(10))
     s.set_timing(3)

@@ -500,6 +500,85 @@ def test_served_requests_equal_solo_runs(pa):
             assert not got[r.rid].cancelled and got[r.rid].best_cut == r.best_cut
 
 
+def test_pool_server_continuous_batching_equals_oracle(pa):
+    """Requests served by the resident pool (each iteration one step of every
+    admitted request in shared launches; a budget that holds about two of
+    them, so requests wait, join as others leave, and run at different steps
+    side by side): every result equals the oracle's run of the request, with
+    a cancellation of a request that is still waiting."""
+    from paper_2510_21105_amd import serve as S
+    reqs = W.serve_requests(7, steps=9)
+    items = []
+    for j, r in enumerate(reqs):
+        if j % 2:
+            L = 10 + 3 * j
+            g = W.torus(L, 40 + j, True, f"torus{L}")
+            order = W.checkerboard_order(L)
+        else:
+            g = W.random_graph(min(r["graph"].n, 1500), min(r["graph"].n_edges, 4000), 300 + j)
+            order = None
+        items.append((g, pa.params_from_workload(dict(r, graph=g, order=order), R=min(r["R"], 600))))
+    needs = [pa.Solver(g).workspace_bytes(p) for g, p in items]
+    budget = int(2.3 * max(needs)) + (11 << 20)      # runs + the lanes' argument tables
+    srv = S.PoolServer(hbm_budget=budget)
+    res = srv.serve([S.Request(j, g, p, 0.0) for j, (g, p) in enumerate(items)], realtime=False,
+                    cancel=[(0.0, len(items) - 1)])
+    got = {r.rid: r for r in res}
+    assert sorted(got) == list(range(len(items)))
+    assert got[len(items) - 1].cancelled
+    for rid, r in got.items():
+        if r.cancelled:
+            continue
+        g, p = items[rid]
+        ref = O.run(g, p.betas, p.sweeps, p.R, p.seed, p.inst, p.order, want_population=False,
+                    want_counts=False)
+        assert np.array_equal(r.stats, ref.stats), rid
+        assert r.best_info == dict(E=ref.best_E, step=ref.best_step, sweep=ref.best_sweep,
+                                   replica=ref.best_replica), rid
+        assert np.array_equal(r.best_x, ref.best_x) and r.best_cut == ref.best_cut, rid
+
+
+def test_pool_runs_at_different_steps_share_launches(pa):
+    """Two runs of one launch shape (one lane) admitted three iterations apart
+    advance in the same launches at different steps, beside a signed torus in
+    a lane of its own; each equals the oracle, population included."""
+    import torch
+    wl = W.workload("small800")
+    a = dict(wl, R=96, betas=wl["betas"][:8])
+    b = dict(wl, R=70, betas=W.linear_betas(0.2, 2.0, 6), sweeps=3, inst=5, seed=7)
+    c = dict(wl, graph=W.torus(12, 3, True, "torus12"), order=W.checkerboard_order(12), R=70,
+             betas=W.linear_betas(0.2, 2.0, 5), sweeps=3, inst=6)
+    pool = pa.Pool(64 << 20)
+    st = torch.cuda.Stream()
+    sa, sb, sc = pa.Solver(a["graph"]), pa.Solver(b["graph"]), pa.Solver(c["graph"])
+    ta = pool.submit(sa, pa.params_from_workload(a))
+    assert pool.advance(st, 3) == 3
+    torch.cuda.synchronize()
+    tb = pool.submit(sb, pa.params_from_workload(b))
+    tc = pool.submit(sc, pa.params_from_workload(c))
+    steps = 3
+    while pool.info()["stepping"] or pool.info()["waiting"]:
+        n = pool.advance(st, 2)
+        steps += n
+        if n == 0:
+            time.sleep(0.001)
+    torch.cuda.synchronize()
+    done = set(pool.poll())
+    # lane of a and b: a's 8 steps from lane iteration 0, b's 6 from 3 -> 9
+    # iterations; the torus lane: 5
+    assert done == {ta, tb, tc} and steps == 9 + 5
+    for s, w in ((sa, a), (sb, b), (sc, c)):
+        ref = O.run_workload(w)
+        assert np.array_equal(s.step_stats(), ref.stats)
+        x, E = s.population()
+        assert np.array_equal(E, ref.E) and np.array_equal(x, ref.x)
+        assert np.array_equal(s.best_config(), ref.best_x)
+    for t in (ta, tb, tc):
+        pool.release(t)
+    assert pool.info()["bytes_in_use"] == 0
+    pool.close()
+
+
 def test_cluster_moves_on_a_collapsing_population(pa):
     """Cold schedule with strong resampling: replica pairs soon differ in few
     spins, so the cluster move runs on small disagreement sets (adjacency-row

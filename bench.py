@@ -32,9 +32,12 @@ TIMING_STRIDE = 7
 SWEEP_SOURCE = os.path.join(ROOT, "paper_2510_21105_amd", "csrc", "pa_kernels.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_kernel_hbm_traffic_{}.json")
 INSTR_FILE = os.path.join(ROOT, "profiles", "sweep_kernel_instructions_{}.json")
-# Vector ALU issue peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (a wave64
-# instruction occupies a 16-lane SIMD for 4 cycles).
-VALU_PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
+# 32-bit vector ALU peak: 256 CUs x 128 lanes x 2.4 GHz = 7.86e13 lane-op/s,
+# the lane rate of the 157.3 TFLOP/s FP32 vector figure (128 FMA lanes per
+# CU per cycle). Measured on this MI355X: a chain of independent 32-bit
+# xor/add instructions issues 0.45 wave64 instructions per SIMD per cycle
+# (90 % of it); 32-bit multiplies issue at half that rate.
+VALU_PEAK_LANE_OPS = 256 * 128 * 2.4e9
 
 
 def kernel_source_hash() -> str:
@@ -409,27 +412,27 @@ def main():
     traffic = measured_traffic_per_launch(args.workload)
     copy_gbs = copy_bandwidth_gbs()
     # The sweep keeps a step's spins in LDS and reads HBM only to load and
-    # store the population once per step, so the roof that binds it is
-    # vector-ALU issue (with LDS latency), not HBM: `roofline` is the VALU
-    # issue rate the kernel reaches -- its measured VALU wave instructions
-    # per launch (rocprofv3 SQ_INSTS_VALU, committed under profiles/ and used
-    # only while the kernel source matches) x 64 lanes / the live average
-    # launch time -- against 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz. Beside
-    # it: the method's own integer operations per attempt (an algorithmic
-    # count: one add per neighbour for the local field, 6 for the test,
-    # flip and bookkeeping, and a quarter of a Philox4x32-10 call, 25
-    # operations, per uphill attempt), the measured HBM bytes per launch, and
-    # the streaming model of int8 spins and int16 fields the survey prices
-    # the sweep with.
+    # store the population once per step, so the roof above it is the
+    # vector ALU (with LDS latency), not HBM. `achieved` counts the method's
+    # own integer operations per attempt (algorithmic, whatever the
+    # implementation packs into one instruction): one add per neighbour for
+    # the local field, 6 for the test, flip, energy and counters, and a
+    # quarter of a Philox4x32-10 call (10 rounds of 2 multiply-high, 2
+    # multiply-low, 4 xor and 2 key adds: 25 operations per draw) for every
+    # uphill attempt, the uphill fraction from the kernel's own counters;
+    # times attempts per launch / the live average launch time. Beside it:
+    # the issued VALU rate (rocprofv3 SQ_INSTS_VALU per launch, committed
+    # under profiles/ and used only while the kernel source matches, x 64
+    # lanes), the measured HBM bytes per launch, and the streaming model of
+    # int8 spins and int16 fields the survey prices the sweep with.
     f_up = att_up / attempts
     alg_ops = dbar + 6.0 + 25.0 * f_up
-    roof = {"bound": "alu", "achieved": None, "peak": VALU_PEAK_LANE_OPS, "unit": "VALU lane-op/s",
-            "frac": None, "traffic": traffic,
-            "basis": "issued VALU lane-ops (rocprofv3 SQ_INSTS_VALU per launch x 64) / live launch time",
-            "algorithmic": {"ops_per_attempt": round(alg_ops, 2), "uphill_fraction": round(f_up, 4),
-                            "achieved": float(f"{alg_ops * per_launch_attempts / avg_launch_s:.4g}"),
-                            "frac": round(alg_ops * per_launch_attempts / avg_launch_s /
-                                          VALU_PEAK_LANE_OPS, 4)},
+    alg_rate = alg_ops * per_launch_attempts / avg_launch_s
+    roof = {"bound": "alu", "achieved": float(f"{alg_rate:.4g}"), "peak": VALU_PEAK_LANE_OPS,
+            "unit": "int32 lane-op/s", "frac": round(alg_rate / VALU_PEAK_LANE_OPS, 4),
+            "traffic": traffic,
+            "ops_per_attempt": round(alg_ops, 2), "uphill_fraction": round(f_up, 4),
+            "issued": None,
             "hbm_model": {"achieved_gbs": round(achieved_gbs, 1), "peak_gbs": HBM_PEAK_GBS,
                           "frac": round(achieved_gbs / HBM_PEAK_GBS, 4),
                           "bytes_per_attempt": round(b_alg, 3),
@@ -439,9 +442,10 @@ def main():
     valu = measured_valu_per_launch(args.workload)
     if valu is not None:
         lane_ops = valu * 64 / avg_launch_s
-        roof["achieved"] = float(f"{lane_ops:.4g}")
-        roof["frac"] = round(lane_ops / VALU_PEAK_LANE_OPS, 4)
-        roof["issued_ops_per_attempt"] = round(valu * 64 / per_launch_attempts, 2)
+        roof["issued"] = {"achieved": float(f"{lane_ops:.4g}"),
+                          "frac": round(lane_ops / VALU_PEAK_LANE_OPS, 4),
+                          "ops_per_attempt": round(valu * 64 / per_launch_attempts, 2),
+                          "basis": "rocprofv3 SQ_INSTS_VALU per launch x 64 lanes / live launch time"}
 
     out = {
         "metric": "spin-flip attempts/s",

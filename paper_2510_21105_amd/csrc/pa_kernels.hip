@@ -1002,20 +1002,27 @@ __device__ __forceinline__ void sweep_bytes_tile(const SweepArgs &a, const int4 
             if (active) {
                 const uint32_t Dm = __builtin_amdgcn_perm(0u, (uint32_t)d, 0u);   // d in every byte
                 Rec<NR> Xn;
+                // Every byte's threshold is requested before any is compared,
+                // so the reads of all NR words are in flight together.
+                uint32_t Uq[NR], wq[NR], th[NR][4];
 #pragma unroll
                 for (int q = 0; q < NR; ++q) {
                     // u = x ? c : d - c  (edges with w_ij x_i x_j = +1), per byte
                     const uint32_t msk = byte_mask(X.v[q]);
-                    const uint32_t U = (C[q] & msk) | ((Dm - C[q]) & ~msk);
+                    Uq[q] = (C[q] & msk) | ((Dm - C[q]) & ~msk);
                     // w = 0x80 + (m - 1) per byte with m = d - 2u
-                    const uint32_t w = (0x7F7F7F7Fu + Dm) - 2u * U;
+                    wq[q] = (0x7F7F7F7Fu + Dm) - 2u * Uq[q];
+#pragma unroll
+                    for (int b = 0; b < 4; ++b)
+                        // T[m] sits at LDS word 0x80 + (m - 1): the move byte itself.
+                        th[q][b] = *(lds_u32 *)(uintptr_t)(((wq[q] >> (8 * b)) & 0xFFu) << 2);
+                }
+#pragma unroll
+                for (int q = 0; q < NR; ++q) {
+                    const uint32_t U = Uq[q], w = wq[q];
                     uint32_t A = ((~w >> 7) & 0x01010101u) | allm;   // m <= 0 always accepts
 #pragma unroll
-                    for (int b = 0; b < 4; ++b) {
-                        // T[m] sits at LDS word 0x80 + (m - 1): the move byte itself.
-                        const uint32_t th = *(lds_u32 *)(uintptr_t)(((w >> (8 * b)) & 0xFFu) << 2);
-                        A |= (dr[q][b] < th ? 1u : 0u) << (8 * b);
-                    }
+                    for (int b = 0; b < 4; ++b) A |= (dr[q][b] < th[q][b] ? 1u : 0u) << (8 * b);
                     Xn.v[q] = X.v[q] ^ A;
                     const uint32_t up = w & real80[q];           // uphill markers
                     att += __builtin_popcount(up);

@@ -40,7 +40,8 @@ typedef enum {
     PA_ERANGE = -2,     /* a size or count outside the supported range    */
     PA_EWORKSPACE = -3, /* workspace missing, too small or misaligned     */
     PA_EDEVICE = -4,    /* HIP runtime error (text in pa_last_error)      */
-    PA_ESTATE = -5      /* call out of order, e.g. results before a run   */
+    PA_ESTATE = -5,     /* call out of order, e.g. results before a run   */
+    PA_EABORTED = -6    /* the run stopped at the step set by pa_set_fault_step */
 } pa_status;
 
 /* Opaque solver: one validated graph. Owned by the caller from pa_create
@@ -480,6 +481,20 @@ pa_status pa_get_launch_info(pa_solver *s, int64_t out[8]);
  * unchanged. Errors: PA_EINVAL for every < 0; pa_get_sweep_time returns
  * PA_ESTATE when the run was not timed. */
 pa_status pa_set_timing(pa_solver *s, int32_t every);
+
+/*
+ * Fault injection for tests of failure handling and recovery. k >= 0: the
+ * next call on this solver that would enqueue step k (pa_run, pa_run_steps,
+ * pa_run_static) stops before it:
+ * steps before k are enqueued as usual, the call synchronises its stream and
+ * returns PA_EABORTED, and the solver holds the run after k steps, as if
+ * pa_run_steps had been called for [0, k) -- pa_checkpoint_save and
+ * pa_run_steps from step k work on it, and continuing gives the results of
+ * an uninterrupted run. The hook fires once, then clears itself; k = -1
+ * clears it. Batched, fused and pooled runs ignore it. Errors: PA_EINVAL for
+ * k < -1 or a null solver.
+ */
+pa_status pa_set_fault_step(pa_solver *s, int32_t k);
 pa_status pa_get_sweep_time(pa_solver *s, double *ms, int64_t *launches);
 
 #ifdef __cplusplus

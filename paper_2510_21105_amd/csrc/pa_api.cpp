@@ -998,7 +998,9 @@ static pa_status run_range(pa_solver *s, int k0, int k1)
     if (s->ev_used < k0) s->ev_first = k0;     // steps before k0 ran in another call or process
     c.valid = false;                           // until every step of the range is enqueued
 
-    for (int k = k0; k < k1; ++k) {
+    int stop = k1;
+    if (s->fault_step >= k0 && s->fault_step < k1) stop = s->fault_step;
+    for (int k = k0; k < stop; ++k) {
         if (c.adapt && k > 0 && (k - k0) % 64 == 0) {
             // Adaptive steps end at the last grid point, usually well before
             // step K: look every 64 steps and enqueue no more once it is done
@@ -1085,11 +1087,27 @@ static pa_status run_range(pa_solver *s, int k0, int k1)
         }
     }
     c.Xc = Xc; c.Xn = Xn; c.Ec = Ec; c.En = En;
-    c.next_step = k1;
+    c.next_step = stop;
     c.valid = true;
     s->final_x = Xc;
     s->final_E = Ec;
     s->has_run = true;
+    if (stop < k1) {
+        // Injected fault: the steps before it are enqueued and the run can
+        // continue from it.
+        s->fault_step = -1;
+        HIP_TRY(hipStreamSynchronize(hs));
+        return fail(PA_EABORTED, "run stopped before step %d by pa_set_fault_step", stop);
+    }
+    return PA_OK;
+}
+
+extern "C" pa_status pa_set_fault_step(pa_solver *s, int32_t k)
+{
+    g_error[0] = 0;
+    if (!s) return fail(PA_EINVAL, "null solver");
+    if (k < -1) return fail(PA_EINVAL, "fault step %d < -1", k);
+    s->fault_step = k;
     return PA_OK;
 }
 

@@ -130,6 +130,8 @@ struct pa_solver {
     std::vector<unsigned char> stage_host;
     // timing: 0 off, else the sweep launches of every timing-th step are timed
     int timing = 0, timing_run = 0;
+    // fault injection: the next run stops before enqueuing this step (-1: off)
+    int fault_step = -1;
     std::vector<hipEvent_t> ev;
     int ev_first = 0, ev_used = 0;
 };

@@ -19,9 +19,9 @@ STAT_FIELDS = 10
 STAT_NAMES = ("E_min", "E_sum", "uphill_attempts", "uphill_accepts", "level",
               "best_E", "parents", "weight_sum", "grid_index", "jump")
 
-PA_OK, PA_EINVAL, PA_ERANGE, PA_EWORKSPACE, PA_EDEVICE, PA_ESTATE = 0, -1, -2, -3, -4, -5
+PA_OK, PA_EINVAL, PA_ERANGE, PA_EWORKSPACE, PA_EDEVICE, PA_ESTATE, PA_EABORTED = 0, -1, -2, -3, -4, -5, -6
 _STATUS = {PA_EINVAL: "PA_EINVAL", PA_ERANGE: "PA_ERANGE", PA_EWORKSPACE: "PA_EWORKSPACE",
-           PA_EDEVICE: "PA_EDEVICE", PA_ESTATE: "PA_ESTATE"}
+           PA_EDEVICE: "PA_EDEVICE", PA_ESTATE: "PA_ESTATE", PA_EABORTED: "PA_EABORTED"}
 
 EXPORTS = ("pa_last_error", "pa_create", "pa_destroy", "pa_graph_info", "pa_workspace_bytes",
            "pa_run", "pa_run_batch", "pa_build_tables", "pa_best_cut", "pa_best_info", "pa_best_config", "pa_best_config_hex",
@@ -31,7 +31,7 @@ EXPORTS = ("pa_last_error", "pa_create", "pa_destroy", "pa_graph_info", "pa_work
            "pa_run_static", "pa_fused_create", "pa_fused_workspace_bytes", "pa_fused_tune",
            "pa_fused_run", "pa_fused_set_graph", "pa_fused_info", "pa_fused_destroy",
            "pa_pool_create", "pa_pool_submit", "pa_pool_cancel", "pa_pool_advance", "pa_pool_poll",
-           "pa_pool_release", "pa_pool_info", "pa_pool_destroy")
+           "pa_pool_release", "pa_pool_info", "pa_pool_destroy", "pa_set_fault_step")
 STATIC_SCRATCH_BYTES = 64 << 20     # PA_STATIC_SCRATCH_BYTES
 
 
@@ -136,6 +136,7 @@ def lib():
             "pa_get_counts": [P, P],
             "pa_get_launch_info": [P, P],
             "pa_set_timing": [P, i32],
+            "pa_set_fault_step": [P, i32],
             "pa_get_sweep_time": [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)],
             "pa_run_steps": [P, ctypes.POINTER(Schedule), i32, u64, u32, i32, i32, P, ctypes.c_size_t, P],
             "pa_checkpoint_bytes": [P, ctypes.POINTER(ctypes.c_size_t)],
@@ -270,15 +271,22 @@ class Solver:
         self._R = p.R
         self._K = int(sch.n_steps)
 
+    def _enqueued(self, st: int, p: RunParams, sch, keep, workspace):
+        """Record the run a call started; a run stopped by the fault hook
+        (PA_EABORTED) still holds its workspace and can continue."""
+        if st in (PA_OK, PA_EABORTED):
+            self._started(p, sch, keep, workspace)
+        _check(st)
+        return self
+
     def run(self, p: RunParams, stream=None, workspace=None):
         """Enqueue a run on ``stream`` (torch.cuda stream; current one by default)."""
         import torch
         sch, keep, workspace, aligned, avail = self._prepare(p, workspace)
         st = torch.cuda.current_stream() if stream is None else stream
-        _check(lib().pa_run(self._h, ctypes.byref(sch), p.R, p.seed, p.inst,
-                            ctypes.c_void_p(aligned), avail, ctypes.c_void_p(st.cuda_stream)))
-        self._started(p, sch, keep, workspace)
-        return self
+        return self._enqueued(lib().pa_run(self._h, ctypes.byref(sch), p.R, p.seed, p.inst,
+                                           ctypes.c_void_p(aligned), avail, ctypes.c_void_p(st.cuda_stream)),
+                              p, sch, keep, workspace)
 
     def run_static(self, p: RunParams, stream=None):
         """Enqueue a run inside the library's static device workspace
@@ -287,10 +295,9 @@ class Solver:
         import torch
         sch, keep = self._schedule(p)
         st = torch.cuda.current_stream() if stream is None else stream
-        _check(lib().pa_run_static(self._h, ctypes.byref(sch), p.R, p.seed, p.inst,
-                                   ctypes.c_void_p(st.cuda_stream)))
-        self._started(p, sch, keep, None)
-        return self
+        return self._enqueued(lib().pa_run_static(self._h, ctypes.byref(sch), p.R, p.seed, p.inst,
+                                                  ctypes.c_void_p(st.cuda_stream)),
+                              p, sch, keep, None)
 
     def run_steps(self, p: RunParams, k_begin: int, k_end: int, stream=None, workspace=None):
         """Enqueue steps [k_begin, k_end) of the run (k_begin > 0 continues the
@@ -300,10 +307,10 @@ class Solver:
             workspace = self._keep[1]
         sch, keep, workspace, aligned, avail = self._prepare(p, workspace)
         st = torch.cuda.current_stream() if stream is None else stream
-        _check(lib().pa_run_steps(self._h, ctypes.byref(sch), p.R, p.seed, p.inst, k_begin, k_end,
-                                  ctypes.c_void_p(aligned), avail, ctypes.c_void_p(st.cuda_stream)))
-        self._started(p, sch, keep, workspace)
-        return self
+        return self._enqueued(lib().pa_run_steps(self._h, ctypes.byref(sch), p.R, p.seed, p.inst, k_begin,
+                                                 k_end, ctypes.c_void_p(aligned), avail,
+                                                 ctypes.c_void_p(st.cuda_stream)),
+                              p, sch, keep, workspace)
 
     def checkpoint(self) -> bytes:
         """The run's state between steps as bytes (synchronises its stream)."""
@@ -374,6 +381,13 @@ class Solver:
         keys = ("sweep_kernel", "tile_replicas", "threads", "workgroups", "lds_bytes", "levels",
                 "rounds", "sweep_launches")
         return dict(zip(keys, (int(v) for v in out)))
+
+    def set_fault_step(self, k: int):
+        """Fault injection (pa_set_fault_step): the next run that would
+        enqueue step ``k`` stops before it and raises PAError with status
+        PA_EABORTED, keeping the run's first ``k`` steps; -1 clears it."""
+        _check(lib().pa_set_fault_step(self._h, int(k)))
+        return self
 
     def set_timing(self, every):
         """Time the sweep launches of every ``every``-th step of later runs

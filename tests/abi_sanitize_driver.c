@@ -68,6 +68,9 @@ int main(void)
         expect(pa_create(&s, N, rp, col, w), PA_OK, "pa_create");
         int64_t info[4];
         expect(pa_graph_info(s, info), PA_OK, "pa_graph_info");
+        expect(pa_set_fault_step(s, 5), PA_OK, "pa_set_fault_step");
+        expect(pa_set_fault_step(s, -2), PA_EINVAL, "fault step -2");
+        expect(pa_set_fault_step(s, -1), PA_OK, "fault step off");
         size_t bytes = 0;
         for (int variant = 0; variant < 6; ++variant) {
             pa_schedule v = sch;

@@ -470,3 +470,24 @@ def test_timing_stride_validation():
     with pytest.raises(pa.PAError) as e:
         s.set_timing(-1)
     assert e.value.status == pa.PA_EINVAL
+
+
+def test_fault_step_validation_and_status_codes():
+    """pa_set_fault_step takes -1 (off) or a step index; the binding's status
+    codes equal the header's enum, PA_EABORTED included."""
+    s = pa.Solver(W.cycle(10))
+    s.set_fault_step(3).set_fault_step(0).set_fault_step(-1)
+    with pytest.raises(pa.PAError) as e:
+        s.set_fault_step(-2)
+    assert e.value.status == pa.PA_EINVAL
+    assert pa.lib().pa_set_fault_step(None, 1) == pa.PA_EINVAL
+    prog = ('#include <stdio.h>\n#include "pa.h"\nint main(void){printf("%d %d %d %d %d %d %d\\n", '
+            'PA_OK, PA_EINVAL, PA_ERANGE, PA_EWORKSPACE, PA_EDEVICE, PA_ESTATE, PA_EABORTED);return 0;}\n')
+    with tempfile.TemporaryDirectory() as d:
+        src = os.path.join(d, "f.c")
+        exe = os.path.join(d, "f")
+        open(src, "w").write(prog)
+        subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), src, "-o", exe])
+        codes = [int(v) for v in subprocess.check_output([exe]).split()]
+    assert codes == [pa.PA_OK, pa.PA_EINVAL, pa.PA_ERANGE, pa.PA_EWORKSPACE, pa.PA_EDEVICE,
+                     pa.PA_ESTATE, pa.PA_EABORTED]

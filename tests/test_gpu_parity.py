@@ -777,6 +777,37 @@ def test_checkpoint_resume_in_new_solver_and_other_launch_shape(pa, kind):
         pa.Solver(wl["graph"]).restore(pa.params_from_workload(dict(wl, sweeps=3), record=3), blob)
 
 
+def test_injected_fault_stops_the_run_and_it_resumes(pa):
+    """A fault injected at step 6 stops pa_run there with PA_EABORTED; the
+    solver holds the first 6 steps, which continue in place, or through a
+    checkpoint in a new solver, to the uninterrupted run's results and the
+    oracle's. The hook fires once."""
+    wl = W.workload("g63like")
+    wl = dict(wl, R=160, betas=W.linear_betas(0.5, 5.0, 12), sweeps=2, as_stall_steps=1,
+              as_frozen_inv=8, nl_period=3)
+    p = pa.params_from_workload(wl, record=3)
+    _say("fault injection at step 6")
+    full = _results(pa.Solver(wl["graph"]).run(p))
+    a = pa.Solver(wl["graph"]).set_fault_step(6)
+    with pytest.raises(pa.PAError) as e:
+        a.run(p)
+    assert e.value.status == pa.PA_EABORTED
+    blob = a.checkpoint()
+    assert pa.next_step(blob) == 6
+    ref6 = _results(pa.Solver(wl["graph"]).run_steps(p, 0, 6))
+    got6 = _results(a)
+    assert np.array_equal(got6["x"], ref6["x"]) and np.array_equal(got6["E"], ref6["E"])
+    a.run_steps(p, 6, 12)
+    _assert_same(_results(a), full)
+    b = pa.Solver(wl["graph"]).restore(p, blob).run_steps(p, 6, 12)
+    _assert_same(_results(b), full)
+    a.run(p)                                             # the hook has cleared itself
+    _assert_same(_results(a), full)
+    ref = O.run_workload(wl, want_counts=False)
+    assert np.array_equal(full["stats"], ref.stats) and np.array_equal(full["x"], ref.x)
+    assert full["best"] == (ref.best_E, ref.best_step, ref.best_sweep, ref.best_replica)
+
+
 def test_command_line_checkpoint_and_resume(pa, tmp_path):
     """The solve command with checkpoints every 7 steps, and resumed from a
     checkpoint taken after step 9, both give the uninterrupted run's result."""

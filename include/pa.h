@@ -262,14 +262,19 @@ typedef struct {
 /*
  * Many independent runs sharing the device (for instance a mix of graphs and
  * population sizes whose single runs leave compute units idle): run i is
- * enqueued exactly as pa_run would on streams[i % n_streams], so runs on
- * different streams overlap on the device while each keeps the results of
- * the same run alone, bit for bit. Asynchronous like pa_run; the per-solver
- * result calls synchronise the run's stream. Solvers must be distinct and
- * each run needs its own workspace. Returns PA_OK, or the status of the
- * first run that fails (its index is in pa_last_error); the runs before it
- * stay enqueued and valid. PA_EINVAL for a null array, count < 1,
- * n_streams < 1 or a solver used twice.
+ * enqueued as pa_run would on streams[i % n_streams], so runs on different
+ * streams overlap on the device while each keeps the results of the same run
+ * alone, bit for bit. When a run has adaptive steps (beta_adapt = 1, whose
+ * host waits for the device every 64 steps), every run is started first and
+ * the steps are then enqueued in chunks of 64, one chunk of each run in turn,
+ * so that no run's wait holds back the others. Asynchronous like pa_run
+ * (apart from those waits); the per-solver result calls synchronise the
+ * run's stream. Solvers must be distinct and each run needs its own
+ * workspace. Returns PA_OK, or the status of the first run that fails (its
+ * index is in pa_last_error); the runs before it stay enqueued and valid (in
+ * a chunked batch the others stay valid part-way, resumable with
+ * pa_run_steps). PA_EINVAL for a null array, count < 1, n_streams < 1 or a
+ * solver used twice.
  */
 pa_status pa_run_batch(const pa_batch_run *runs, int32_t count, void *const *streams,
                        int32_t n_streams);

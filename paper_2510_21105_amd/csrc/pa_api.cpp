@@ -1256,16 +1256,45 @@ extern "C" pa_status pa_run_batch(const pa_batch_run *runs, int32_t count, void 
     std::sort(seen.begin(), seen.end());
     if (std::adjacent_find(seen.begin(), seen.end()) != seen.end())
         return fail(PA_EINVAL, "pa_run_batch: a solver appears in two runs");
+    auto failed = [&](int i, pa_status st) {
+        char msg[sizeof g_error];
+        std::snprintf(msg, sizeof msg, "%s", g_error);
+        return fail(st, "pa_run_batch: run %d: %s", i, msg);
+    };
+    bool adaptive = false;
+    for (int i = 0; i < count; ++i) adaptive |= runs[i].schedule && runs[i].schedule->beta_adapt;
+    if (!adaptive) {
+        for (int i = 0; i < count; ++i) {
+            const pa_batch_run &r = runs[i];
+            const pa_status st = pa_run(r.solver, r.schedule, r.R, r.seed, r.instance, r.workspace,
+                                        r.workspace_bytes, streams[i % n_streams]);
+            if (st != PA_OK) return failed(i, st);
+        }
+        return PA_OK;
+    }
+    // An adaptive run's host looks at its grid point every 64 steps and waits
+    // for the device there. Every run is started first, then the steps go in
+    // chunks of 64, one chunk of each run in turn, so that while the host
+    // waits on one run the chunks of the others are already queued.
+    int kmax = 0;
     for (int i = 0; i < count; ++i) {
         const pa_batch_run &r = runs[i];
-        const pa_status st = pa_run(r.solver, r.schedule, r.R, r.seed, r.instance, r.workspace,
-                                    r.workspace_bytes, streams[i % n_streams]);
-        if (st != PA_OK) {
-            char msg[sizeof g_error];
-            std::snprintf(msg, sizeof msg, "%s", g_error);
-            return fail(st, "pa_run_batch: run %d: %s", i, msg);
-        }
+        const pa_status st = pa_run_steps(r.solver, r.schedule, r.R, r.seed, r.instance, 0, 0, r.workspace,
+                                          r.workspace_bytes, streams[i % n_streams]);
+        if (st != PA_OK) return failed(i, st);
+        kmax = std::max(kmax, r.schedule->n_steps);
     }
+    constexpr int kChunk = 64;
+    for (int k0 = 0; k0 < kmax; k0 += kChunk)
+        for (int i = 0; i < count; ++i) {
+            const pa_batch_run &r = runs[i];
+            const int K = r.schedule->n_steps;
+            if (k0 >= K) continue;
+            const pa_status st = pa_run_steps(r.solver, r.schedule, r.R, r.seed, r.instance, k0,
+                                              std::min(k0 + kChunk, K), r.workspace, r.workspace_bytes,
+                                              streams[i % n_streams]);
+            if (st != PA_OK) return failed(i, st);
+        }
     return PA_OK;
 }
 

@@ -373,6 +373,40 @@ def test_batched_runs_equal_solo_runs(pa):
         assert np.array_equal(s.best_config(), ref.best_x), w["desc"]
 
 
+def test_batch_with_adaptive_runs_interleaves_and_equals_oracle(pa):
+    """A batch holding adaptive-step runs is enqueued in 64-step chunks, one
+    chunk of each run in turn: every run, adaptive (ending at different steps)
+    or plain (K = 150, three chunks), equals the same run alone and the
+    oracle."""
+    import torch
+    mk = []
+    for j, (n, m, jump, num, den) in enumerate([(500, 2500, 16, 1, 4), (700, 2100, 8, 1, 2),
+                                                (400, 2000, 64, 0, 1)]):
+        g = W.random_graph(n, m, 40 + j)
+        mk.append(dict(W.workload("small800"), graph=g, R=96 + 32 * j, betas=W.linear_betas(0.1, 3.0, 200),
+                       sweeps=2, order=W.natural_order(g.n), beta_adapt=1, adapt_jump=jump,
+                       adapt_num=num, adapt_den=den, inst=j, desc=f"adaptive {j}"))
+    g = W.random_graph(600, 2400, 44)
+    mk.append(dict(W.workload("small800"), graph=g, R=80, betas=W.linear_betas(0.1, 3.0, 150), sweeps=2,
+                   order=W.natural_order(g.n), inst=3, desc="plain K=150"))
+    params = [pa.params_from_workload(w) for w in mk]
+    solvers = [pa.Solver(w["graph"]) for w in mk]
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    _say("batch with adaptive runs")
+    pa.run_batch(solvers, params, streams)
+    for w, p, s in zip(mk, params, solvers):
+        solo = pa.Solver(w["graph"]).run(p)
+        assert np.array_equal(s.step_stats(), solo.step_stats()), w["desc"]
+        assert s.best_info() == solo.best_info(), w["desc"]
+        ref = O.run_workload(dict(w, R=p.R), want_counts=False)
+        assert np.array_equal(s.step_stats(), ref.stats), w["desc"]
+        x, E = s.population()
+        assert np.array_equal(E, ref.E) and np.array_equal(x, ref.x), w["desc"]
+        info = s.best_info()
+        assert (info["E"], info["step"], info["sweep"], info["replica"]) == \
+            (ref.best_E, ref.best_step, ref.best_sweep, ref.best_replica), w["desc"]
+
+
 def _fused_mix():
     wls = W.batch_workloads(6, steps=12)
     wls[2] = dict(wls[2], as_enable=1, as_stall_steps=1, as_frozen_inv=8)   # noise levels too

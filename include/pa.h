@@ -294,11 +294,13 @@ typedef struct pa_fused pa_fused;
 
 /*
  * Many runs sharing kernel launches (for instance dozens of uneven graphs and
- * population sizes, most of which alone leave compute units idle). Runs whose
- * graphs have only +1 weights form one group, runs with -1 weights another;
+ * population sizes, most of which alone leave compute units idle). Runs are
+ * grouped by record mode (graphs with only +1 weights, graphs with -1
+ * weights) and graph size (below 1,500, 3,000 and 5,000 nodes, and larger);
  * step k of a whole group is one sweep launch, whose workgroups each take one
  * replica tile of one run from a work list, and one epilogue launch with one
- * workgroup per run. Groups run concurrently. Every run gives exactly the
+ * workgroup per run. Groups run concurrently, each on a stream of its own
+ * forked from and joined back to the caller's. Every run gives exactly the
  * results of pa_run with the same arguments (any launch shape), and after
  * pa_fused_run its solver answers the pa_best_* / pa_get_* /
  * pa_checkpoint_save calls as after pa_run; pa_run_steps cannot continue it.
@@ -312,12 +314,14 @@ typedef struct pa_fused pa_fused;
  *   pa_fused_workspace_bytes  device bytes the batch needs (every run's state
  *                     and the batch's own argument and work-list tables).
  *   pa_fused_tune     measures, per group, each candidate launch shape (4, 8
- *                     or 16 replicas per workgroup; 256 or 512 threads) on
- *                     the first probe_steps (1..64) steps of the group's runs
- *                     inside `workspace`, and keeps the fastest. Synchronous
- *                     (it waits for the probes); leaves no valid results.
- *                     Without it a default shape is used (8 replicas and 512
- *                     threads where they fit).
+ *                     or 16 replicas per workgroup x 64, 128, 256 or 512
+ *                     threads, where the group's graphs fit LDS) on the
+ *                     first probe_steps (1..64) steps of the group's runs
+ *                     inside `workspace` (two probes each), and keeps the
+ *                     fastest. Synchronous (it waits for the probes); leaves
+ *                     no valid results. Without it a default shape is used:
+ *                     8 replicas per workgroup and the smallest thread count
+ *                     that needs no more rounds per sweep than 512 threads.
  *   pa_fused_run      enqueues the whole batch on `stream`: each run's setup
  *                     (inputs, initial population), then the step loop of
  *                     every group, captured once into a HIP graph (for this

@@ -2,8 +2,8 @@
 // pa_fused_* calls of include/pa.h).
 //
 // Runs of one record mode (unsigned graphs, or signed graphs with sign-bit
-// entries) form a group that shares one launch shape of the node-per-lane
-// sweep kernel. Step k of the whole group is one sweep launch over a work
+// entries) and one graph-size class form a group that shares one launch
+// shape of the node-per-lane sweep kernel. Step k of the whole group is one sweep launch over a work
 // list of {run, tile} entries and one epilogue launch with a workgroup per
 // run, so small runs that would leave most compute units idle alone fill the
 // device together, and the per-step launch count no longer grows with the
@@ -123,7 +123,7 @@ int pa_host::device_max_lds()
 
 namespace {
 
-// Tile widths the autotuner tries (threads: the group's count, half and double).
+// Tile widths the autotuner tries, each with 64, 128, 256 and 512 threads.
 constexpr int kTileCand[] = {4, 8, 16};
 
 bool direct_fits(const pa_solver *s, int W)

@@ -424,7 +424,7 @@ def main():
     # the issued VALU rate (rocprofv3 SQ_INSTS_VALU per launch, committed
     # under profiles/ and used only while the kernel source matches, x 64
     # lanes), the measured HBM bytes per launch, and the streaming model of
-    # int8 spins and int16 fields the survey prices the sweep with.
+    # a design that streams int8 spins and int16 local fields from HBM.
     f_up = att_up / attempts
     alg_ops = dbar + 6.0 + 25.0 * f_up
     alg_rate = alg_ops * per_launch_attempts / avg_launch_s

@@ -20,6 +20,7 @@ FLAGS = [
     "-std=c++17",
     "-fPIC",
     "-shared",
+    "-pthread",
     # Packed-FP32 instructions stay off in every HIP object of this library.
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall",

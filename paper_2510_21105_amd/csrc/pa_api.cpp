@@ -13,7 +13,9 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <map>
+#include <thread>
 #include <new>
 #include <vector>
 
@@ -408,6 +410,26 @@ static uint64_t weight_fixed(double dbeta, long long n)
     return (uint64_t)std::floor(std::ldexp(x, 32));
 }
 
+// Calls fn(k0, k1) over [0, K) in contiguous chunks, on up to 8 host threads
+// when the work (entries) is large enough to pay for them.
+static void parallel_rows(int K, long long work, const std::function<void(int, int)> &fn)
+{
+    const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+    const int nt = (int)std::min<long long>({8, (long long)hw, K, work / 20000 + 1});
+    if (nt <= 1) {
+        fn(0, K);
+        return;
+    }
+    std::vector<std::thread> pool;
+    const int per = (K + nt - 1) / nt;
+    for (int t = 1; t < nt; ++t) {
+        const int k0 = t * per, k1 = std::min(K, k0 + per);
+        if (k0 < k1) pool.emplace_back(fn, k0, k1);
+    }
+    fn(0, std::min(K, per));
+    for (auto &th : pool) th.join();
+}
+
 pa_status pa_host::build_plan(pa_solver *s, const pa_schedule *sch, int R, Plan &p, bool tables,
                               const Shape *force)
 {
@@ -599,6 +621,11 @@ pa_status pa_host::build_plan(pa_solver *s, const pa_schedule *sch, int R, Plan 
     p.wtab_off.assign(std::max(p.K, 1), 0);
     p.wtab_len.assign(std::max(p.K, 1), 0);
     std::map<uint64_t, std::pair<int, int>> seen;
+    struct Tab {
+        double db;
+        long long off, len;
+    };
+    std::vector<Tab> distinct;
     long long total = 0;
     for (int k = 0; k < n_tab; ++k) {
         const double db = sch->beta_adapt ? sch->beta[k + 1] - sch->beta[0] : sch->beta[k + 1] - sch->beta[k];
@@ -606,15 +633,34 @@ pa_status pa_host::build_plan(pa_solver *s, const pa_schedule *sch, int R, Plan 
         std::memcpy(&key, &db, sizeof key);
         auto it = seen.find(key);
         if (it == seen.end()) {
-            long long len = 0;
-            while (len <= span && weight_fixed(db, len) != 0) ++len;
-            if (tables)
-                for (long long q = 0; q < len; ++q) p.wtab.push_back(weight_fixed(db, q));
+            // The table runs to its first zero entry (at most span + 1
+            // entries); the weights fall with n, so the first zero is found
+            // by bisection and only the entries kept are evaluated.
+            long long len = span + 1;
+            if (weight_fixed(db, span) == 0) {
+                long long lo = 0, hi = span;          // weight(lo) != 0 or lo = 0; weight(hi) == 0
+                if (weight_fixed(db, 0) == 0) hi = 0;
+                while (hi - lo > 1) {
+                    const long long mid = lo + (hi - lo) / 2;
+                    (weight_fixed(db, mid) != 0 ? lo : hi) = mid;
+                }
+                len = hi;
+            }
+            if (tables) distinct.push_back({db, total, len});
             it = seen.emplace(key, std::make_pair((int)total, (int)len)).first;
             total += len;
         }
         p.wtab_off[k] = it->second.first;
         p.wtab_len[k] = it->second.second;
+    }
+    if (tables && !distinct.empty()) {
+        // The distinct tables' entries, filled by table on host threads.
+        p.wtab.assign((size_t)total, 0);
+        parallel_rows((int)distinct.size(), total, [&](int t0, int t1) {
+            for (int t = t0; t < t1; ++t)
+                for (long long q = 0; q < distinct[t].len; ++q)
+                    p.wtab[(size_t)(distinct[t].off + q)] = weight_fixed(distinct[t].db, q);
+        });
     }
     if (total == 0) {
         total = 1;
@@ -630,34 +676,33 @@ pa_status pa_host::build_plan(pa_solver *s, const pa_schedule *sch, int R, Plan 
             }
         }
     }
-    if (tables && p.kind == 1) {
+    if (tables) {
+        // Threshold rows, one per (step, noise level); rows are independent,
+        // so large tables are filled by several host threads.
         const int D = s->dmax + 1;
-        p.thr32.assign((size_t)p.K * p.lmax1 * D, 0);
-        for (int k = 0; k < p.K; ++k) {
-            double g = 1.0;
-            for (int l = 0; l < p.lmax1; ++l) {
-                const double b = sch->beta[k] * g;
-                uint32_t *row = &p.thr32[((size_t)k * p.lmax1 + l) * D];
-                for (int m = 1; m < D; ++m)
-                    row[m - 1] = (uint32_t)std::min<uint64_t>(threshold_fixed(b, m), 0xFFFFFFFFull);
-                // Every uphill move accepted (exp rounds to 1 up to the max degree).
-                row[D - 1] = s->dmax >= 1 && threshold_fixed(b, s->dmax) == (1ull << 32) ? 1u : 0u;
-                g = g * sch->as_gamma;
+        if (p.kind == 1) p.thr32.assign((size_t)p.K * p.lmax1 * D, 0);
+        else p.thr.assign((size_t)p.K * p.lmax1 * D, 0);
+        auto fill = [&](int k0, int k1) {
+            for (int k = k0; k < k1; ++k) {
+                double g = 1.0;
+                for (int l = 0; l < p.lmax1; ++l) {
+                    const double b = sch->beta[k] * g;
+                    if (p.kind == 1) {
+                        uint32_t *row = &p.thr32[((size_t)k * p.lmax1 + l) * D];
+                        for (int m = 1; m < D; ++m)
+                            row[m - 1] = (uint32_t)std::min<uint64_t>(threshold_fixed(b, m), 0xFFFFFFFFull);
+                        // Every uphill move accepted (exp rounds to 1 up to the max degree).
+                        row[D - 1] = s->dmax >= 1 && threshold_fixed(b, s->dmax) == (1ull << 32) ? 1u : 0u;
+                    } else {
+                        uint64_t *row = &p.thr[((size_t)k * p.lmax1 + l) * D];
+                        row[0] = 0;
+                        for (int m = 1; m < D; ++m) row[m] = threshold_fixed(b, m);
+                    }
+                    g = g * sch->as_gamma;
+                }
             }
-        }
-    } else if (tables) {
-        const int D = s->dmax + 1;
-        p.thr.assign((size_t)p.K * p.lmax1 * D, 0);
-        for (int k = 0; k < p.K; ++k) {
-            double g = 1.0;
-            for (int l = 0; l < p.lmax1; ++l) {
-                const double b = sch->beta[k] * g;
-                uint64_t *row = &p.thr[((size_t)k * p.lmax1 + l) * D];
-                row[0] = 0;
-                for (int m = 1; m < D; ++m) row[m] = threshold_fixed(b, m);
-                g = g * sch->as_gamma;
-            }
-        }
+        };
+        parallel_rows(p.K, (long long)p.K * p.lmax1 * D, fill);
     }
 
     Layout &L = p.L;

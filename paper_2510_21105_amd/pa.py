@@ -9,7 +9,7 @@ from __future__ import annotations
 
 import ctypes
 import os
-from dataclasses import dataclass
+from dataclasses import dataclass, fields
 
 import numpy as np
 
@@ -186,6 +186,19 @@ class RunParams:
     adapt_den: int = 2
 
 
+def _params_key(p: RunParams):
+    """Hashable form of a RunParams (arrays by their bytes)."""
+    out = []
+    for f in fields(p):
+        v = getattr(p, f.name)
+        if isinstance(v, (list, tuple)):
+            v = np.asarray(v)
+        if isinstance(v, np.ndarray):
+            v = (str(v.dtype), v.shape, v.tobytes())
+        out.append(v)
+    return tuple(out)
+
+
 class Solver:
     """One validated graph; runs population annealing on the current HIP device."""
 
@@ -199,6 +212,7 @@ class Solver:
         _check(lib().pa_create(ctypes.byref(h), self.n, _p(self._row_ptr), _p(self._col), _p(self._w)))
         self._h = h
         self._workspace = None
+        self._need = {}
         self._keep = None
         self._R = 0
         self._K = 0
@@ -256,7 +270,13 @@ class Solver:
         """Schedule struct (with the arrays it points to) and an aligned workspace."""
         import torch
         sch, keep = self._schedule(p)
-        need = self.workspace_bytes(p)
+        # The size is a pure function of the graph and the run's arguments:
+        # asked once per distinct arguments (the library plans the run again
+        # when it starts it).
+        key = _params_key(p)
+        need = self._need.get(key)
+        if need is None:
+            need = self._need[key] = self.workspace_bytes(p)
         if workspace is None:
             if self._workspace is None or self._workspace.numel() < need + 256:
                 self._workspace = torch.empty(need + 256, dtype=torch.uint8, device="cuda")
@@ -454,6 +474,7 @@ class FusedBatch:
         _check(lib().pa_fused_create(ctypes.byref(h), entries, len(self.solvers)))
         self._h = h
         self._workspace = None
+        self._need = {}
 
     def close(self):
         if getattr(self, "_h", None):

@@ -1681,14 +1681,23 @@ __global__ __launch_bounds__(kIcmThreads) void icm_kernel(IcmArgs a)
     const int ne = a.g.ne;
     const bool sparse = total * 16 <= n;
     if (sparse) {
-        for (int w = tid; w < nw; w += nt) {
-            uint32_t bits = D[w];
+        // Half a bitmap word per thread (all threads busy on small graphs);
+        // a row's neighbours are read 8 at a time before any of them is
+        // united, so the loads overlap instead of waiting one by one.
+        for (int u = tid; u < 2 * nw; u += nt) {
+            const int w = u >> 1;
+            uint32_t bits = D[w] & ((u & 1) ? 0xFFFF0000u : 0x0000FFFFu);
             while (bits) {
                 const uint32_t i = (uint32_t)(w * 32 + __ffs(bits) - 1);
                 bits &= bits - 1;
-                for (int e = a.g.row_ptr[i]; e < a.g.row_ptr[i + 1]; ++e) {
-                    const uint32_t j = (uint32_t)a.g.col[e];
-                    if (j > i && inD(j)) uf_unite(P, i, j);
+                const int e0 = a.g.row_ptr[i], e1 = a.g.row_ptr[i + 1];
+                for (int e = e0; e < e1; e += 8) {
+                    uint32_t jv[8];
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) jv[q] = e + q < e1 ? (uint32_t)a.g.col[e + q] : 0u;
+#pragma unroll
+                    for (int q = 0; q < 8; ++q)
+                        if (e + q < e1 && jv[q] > i && inD(jv[q])) uf_unite(P, i, jv[q]);
                 }
             }
         }
@@ -1762,16 +1771,23 @@ __global__ __launch_bounds__(kIcmThreads) void icm_kernel(IcmArgs a)
     long long dEa = 0;
     auto bitA = [&](uint32_t i) { return (int)((A[i >> 5] >> (i & 31)) & 1u); };
     if (sparse) {
-        for (int w = tid; w < nw; w += nt) {
-            uint32_t bits = V[w];
+        for (int u = tid; u < 2 * nw; u += nt) {
+            const int w = u >> 1;
+            uint32_t bits = V[w] & ((u & 1) ? 0xFFFF0000u : 0x0000FFFFu);
             while (bits) {
                 const uint32_t i = (uint32_t)(w * 32 + __ffs(bits) - 1);
                 bits &= bits - 1;
                 const int e0 = a.g.row_ptr[i], e1 = a.g.row_ptr[i + 1], em = e0 + a.g.npos[i];
-                for (int e = e0; e < e1; ++e) {
-                    const uint32_t j = (uint32_t)a.g.col[e];
-                    if ((V[j >> 5] >> (j & 31)) & 1u) continue;
-                    dEa += -2 * (1 - 2 * (bitA(i) ^ bitA(j) ^ (e >= em ? 1 : 0)));
+                for (int e = e0; e < e1; e += 8) {
+                    uint32_t jv[8];
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) jv[q] = e + q < e1 ? (uint32_t)a.g.col[e + q] : 0u;
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) {
+                        const uint32_t j = jv[q];
+                        if (e + q >= e1 || ((V[j >> 5] >> (j & 31)) & 1u)) continue;
+                        dEa += -2 * (1 - 2 * (bitA(i) ^ bitA(j) ^ (e + q >= em ? 1 : 0)));
+                    }
                 }
             }
         }

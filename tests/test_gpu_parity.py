@@ -572,6 +572,74 @@ def test_pool_server_continuous_batching_equals_oracle(pa):
         assert np.array_equal(r.best_x, ref.best_x) and r.best_cut == ref.best_cut, rid
 
 
+def _edge_runs():
+    """Degenerate runs: one replica and one step, a 2-node graph, isolated
+    nodes, inverse temperature 0, a ragged population of 65 and a signed
+    torus of 3 x 3."""
+    base = dict(W.workload("small800"), nl_period=0, as_enable=0)
+    out = []
+    g = W.random_graph(200, 600, 5)
+    out.append(dict(base, graph=g, R=1, betas=[1.0], sweeps=3, order=W.natural_order(g.n), inst=0))
+    g = W.from_edges(2, [0], [1], None, "K2")
+    out.append(dict(base, graph=g, R=4, betas=W.linear_betas(0.1, 2.0, 5), sweeps=2, order=None, inst=1))
+    g = W.from_edges(50, [0, 1, 2], [1, 2, 3], None, "sparse50")
+    out.append(dict(base, graph=g, R=70, betas=W.linear_betas(0.1, 2.0, 5), sweeps=2, order=None, inst=2))
+    g = W.random_graph(300, 900, 6)
+    out.append(dict(base, graph=g, R=65, betas=[0.0, 0.0], sweeps=1, order=W.natural_order(g.n), inst=3))
+    g = W.torus(3, 7, True, "torus3")
+    out.append(dict(base, graph=g, R=33, betas=W.linear_betas(0.1, 3.0, 4), sweeps=2,
+                    order=W.checkerboard_order(3), inst=4))
+    return out
+
+
+def _check_stats_best(s, w, p):
+    ref = O.run_workload(dict(w, R=p.R), want_counts=False)
+    assert np.array_equal(s.step_stats(), ref.stats), w["graph"].name
+    x, E = s.population()
+    assert np.array_equal(E, ref.E) and np.array_equal(x, ref.x), w["graph"].name
+    info = s.best_info()
+    assert (info["E"], info["step"], info["sweep"], info["replica"]) == \
+        (ref.best_E, ref.best_step, ref.best_sweep, ref.best_replica), w["graph"].name
+    assert np.array_equal(s.best_config(), ref.best_x), w["graph"].name
+
+
+def test_fused_batch_degenerate_runs_equal_oracle(pa):
+    """A fused batch of degenerate runs (R = 1 with K = 1, a 2-node graph,
+    isolated nodes, beta = 0, a ragged R, a 3 x 3 signed torus) equals the
+    oracle run by run, untuned and tuned."""
+    wls = _edge_runs()
+    params = [pa.params_from_workload(w) for w in wls]
+    solvers = [pa.Solver(w["graph"]) for w in wls]
+    fb = pa.FusedBatch(solvers, params)
+    _say(f"fused degenerate {fb.info()}")
+    fb.run()
+    for w, p, s in zip(wls, params, solvers):
+        _check_stats_best(s, w, p)
+    fb.tune(probe_steps=1)
+    fb.run()
+    for w, p, s in zip(wls, params, solvers):
+        _check_stats_best(s, w, p)
+
+
+def test_pool_degenerate_runs_equal_oracle(pa):
+    """The same degenerate runs served by the resident pool equal the oracle."""
+    from paper_2510_21105_amd import serve as S
+    wls = _edge_runs()
+    items = [(w["graph"], pa.params_from_workload(w)) for w in wls]
+    srv = S.PoolServer(hbm_budget=64 << 20)
+    res = srv.serve([S.Request(j, g, p, 0.0) for j, (g, p) in enumerate(items)], realtime=False)
+    got = {r.rid: r for r in res}
+    assert sorted(got) == list(range(len(items)))
+    for rid, r in got.items():
+        g, p = items[rid]
+        ref = O.run(g, p.betas, p.sweeps, p.R, p.seed, p.inst, p.order, want_population=False,
+                    want_counts=False)
+        assert np.array_equal(r.stats, ref.stats), g.name
+        assert r.best_info == dict(E=ref.best_E, step=ref.best_step, sweep=ref.best_sweep,
+                                   replica=ref.best_replica), g.name
+        assert np.array_equal(r.best_x, ref.best_x) and r.best_cut == ref.best_cut, g.name
+
+
 def test_pool_runs_at_different_steps_share_launches(pa):
     """Two runs of one launch shape (one lane) admitted three iterations apart
     advance in the same launches at different steps, beside a signed torus in

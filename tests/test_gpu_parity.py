@@ -184,6 +184,47 @@ def test_torus_full_population_first_step(pa):
     _compare(pa, wl["graph"], wl, record=0)
 
 
+# ------------------------------------------------- device statistics ----
+
+def test_device_samples_boltzmann_and_estimates_free_energy(pa):
+    """The device's own statistics, independent of the oracle (another seed
+    than the oracle's pins): at fixed beta the population of an 8-node signed
+    graph follows exp(-beta E) / Z (chi-square over all 256 states, the wrong
+    exponent rejected), and the PA free-energy estimator from the device's
+    per-step weight sums reproduces ln Z of a 12-node graph by enumeration."""
+    import math
+    g = W.from_edges(8, [0, 0, 1, 2, 3, 4, 5, 6, 1, 2, 0, 3],
+                     [1, 2, 3, 4, 5, 6, 7, 7, 5, 6, 7, 6],
+                     [1, -1, 1, 1, -1, 1, 1, -1, 1, 1, -1, 1])
+    beta, R = 0.6, 32768
+    wl = dict(W.workload("small800"), graph=g, R=R, betas=[beta], sweeps=64, seed=17, inst=0,
+              order=None, nl_period=0, as_enable=0)
+    s = pa.Solver(g).run(pa.params_from_workload(wl))
+    x, _ = s.population()
+    E = refs.all_energies(g)
+    prob = np.exp(-beta * (E - E.min()))
+    prob /= prob.sum()
+    obs = np.bincount(refs.state_index(x), minlength=prob.shape[0])
+    chi2 = float(((obs - R * prob) ** 2 / (R * prob)).sum())
+    assert chi2 < 400.0                    # 255 degrees of freedom: about 6 sd
+    bad = np.exp(-0.5 * beta * (E - E.min()))
+    bad /= bad.sum()
+    assert float(((obs - R * bad) ** 2 / (R * bad)).sum()) > 2000.0
+    g = W.random_graph(12, 30, 9)
+    betas = W.linear_betas(0.0, 1.5, 31)
+    R = 20000
+    wl = dict(W.workload("small800"), graph=g, R=R, betas=betas, sweeps=5, seed=23, inst=0,
+              order=None, nl_period=0, as_enable=0)
+    st = pa.Solver(g).run(pa.params_from_workload(wl)).step_stats()
+    est = g.n * math.log(2.0)
+    for k in range(len(betas) - 1):
+        est += math.log(float(st[k, 7]) / (R * 2.0 ** 32)) - (betas[k + 1] - betas[k]) * float(st[k, 0])
+    E = refs.all_energies(g)
+    b = betas[-1]
+    exact = float(np.log(np.exp(-b * (E - E.min())).sum()) - b * E.min())
+    assert abs(est - exact) < 0.03
+
+
 # ---------------------------------------------------------------- edges ----
 
 def test_single_replica_and_single_step(pa):

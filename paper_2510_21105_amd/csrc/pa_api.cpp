@@ -611,6 +611,22 @@ pa_status pa_host::build_plan(pa_solver *s, const pa_schedule *sch, int R, Plan 
             }
     }
     build_blocks(s, p, -1);
+    if (p.kind == 1) {
+        // Two workgroups sharing a compute unit: the issue arbiter breaks
+        // ties by age, so the one dispatched first would finish far earlier
+        // and leave the other alone on the unit for the launch's tail.
+        // Measured on MI355X with the G63-shaped run (8-replica tiles, two
+        // per CU, all resident at once): the second one's waves ahead in 6 of
+        // every 10 sweeps even them out (durations 709k / 915k cycles ->
+        // 840k / 850k), the launch 7 % shorter. Launches of several
+        // generations of workgroups (the 100 x 100 torus) were 2 % slower
+        // with the slots alternating, so they keep the plain kernel.
+        const int lds = pa::sweep_bytes_lds(p.W, p.bsg == 1 ? 1 : 0, n, s->dmax);
+        const int waves = (p.threads + 63) / 64;
+        const int per_cu = std::min(max_lds / std::max(lds, 1), 16 / std::max(waves, 1));
+        const long long slots = (long long)cus * per_cu;
+        if (p.W == 8 && per_cu == 2 && p.nblk > slots / 2 && p.nblk <= slots) p.prio_mode = 1;
+    }
     }
 
     // Weight-table sizes (needed for the workspace size even without tables).
@@ -973,6 +989,7 @@ pa_status pa_host::start_run(pa_solver *s, const pa_schedule *sch, int32_t R, ui
     sa.n_rounds = P.n_rounds;
     sa.flush_every = P.flush_every;
     sa.direct = P.direct;
+    sa.prio_mode = P.prio_mode;
     sa.R = R;
     sa.S = P.S;
     sa.lmax1 = P.lmax1;

@@ -58,6 +58,8 @@ struct SweepArgs {
     int n_rounds;
     int flush_every;            // rounds between widenings of the byte energy accumulators
     int direct;                 // kernel 1: block entries are LDS byte offsets
+    int prio_mode;              // kernel 1: 1 = issue-priority turns of the two workgroups
+                                // sharing a compute unit (8-replica tiles), else 0
     const uint64_t *thr;        // kernel 2: [K][lmax1][dmax+1] T[m] (T[0] unused), by grid point
     const uint32_t *thr32;      // kernel 1: [K][lmax1][dmax+1] T[1..dmax], all-accept flag
     const int *as_state;        // [0] level, [3] grid point of this step

@@ -54,6 +54,7 @@ struct Plan {
     int lmax1 = 1, n_levels = 0, record = 0;
     int kind = 2, sgn = 0, block_bytes = 0, qpad = 0, n_rounds = 0, flush_every = 1;
     int direct = 0;   // kernel 1: block entries are LDS byte offsets (else record indices)
+    int prio_mode = 0;  // kernel 1: issue-priority turns (SweepArgs::prio_mode)
     int bsg = 0;      // kernel 1 records: 0 unsigned, 1 complemented copies, 2 sign bits in entries
     std::vector<int> sched, level_off;
     std::vector<uint32_t> blocks;   // [n][block_bytes / 4] + 128 B

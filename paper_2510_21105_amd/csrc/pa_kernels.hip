@@ -634,7 +634,7 @@ __device__ __forceinline__ int wave_sum_dpp(int v)
 template <int W, int SG, bool DIRECT>
 __device__ __forceinline__ void sweep_bytes_tile(const SweepArgs &a, const int4 *__restrict__ rounds,
                                                  const uint4 *__restrict__ blocks, const int blk,
-                                                 const int nblk)
+                                                 const int nblk, const bool prio)
 {
     constexpr bool SIGNED = SG == 1;     // complemented records in LDS
     constexpr bool SBIT = SG == 2;       // sign bits in the block entries
@@ -701,6 +701,14 @@ __device__ __forceinline__ void sweep_bytes_tile(const SweepArgs &a, const int4 
     if (tid < W) {
         Eblk[tid] = (r0 + tid < a.R) ? a.Ein[ident ? r0 + tid : a.parent[r0 + tid]] : 0;
         Ed[tid] = 0;
+    }
+    if (prio && tid == 0) {
+        // Sweeps in which this workgroup's waves take the higher issue
+        // priority, as bits of s mod 10: the second workgroup on a compute
+        // unit (slot 1, TG_ID of the HW_ID register) in sweeps 0, 2, 4, 5, 7
+        // and 9 of every ten.
+        const uint32_t slot = (__builtin_amdgcn_s_getreg((31 << 11) | 4) >> 16) & 15u;
+        misc[14] = slot == 1 ? 0x2B5u : 0u;
     }
     if (tid == 0) {
         misc[0] = a.best_E[0];
@@ -1047,6 +1055,16 @@ __device__ __forceinline__ void sweep_bytes_tile(const SweepArgs &a, const int4 
 
     // End of sweep s: the energy changes are summed over the workgroup, then
     // the block's best candidate is taken.
+    // Issue priority for sweep s (scheduling only; launches with prio_mode 1):
+    // bit s mod 10 of the workgroup's turn mask, set at the start.
+    auto prio_turn = [&](int s) {
+        if (!prio) return;
+        const uint32_t turns = (uint32_t)misc[14];
+        if (turns != 0u) {
+            if ((turns >> (s % 10)) & 1u) __builtin_amdgcn_s_setprio(2);
+            else __builtin_amdgcn_s_setprio(0);
+        }
+    };
     auto sweep_done = [&](int s) {
         flush();
         __syncthreads();
@@ -1078,6 +1096,7 @@ __device__ __forceinline__ void sweep_bytes_tile(const SweepArgs &a, const int4 
                 }
             }
             __syncthreads();
+            prio_turn(s + 1);
             const int sq = (int)misc[2];
             if (sq >= 0) {
                 // Snapshot of the improving replica; the next round may only
@@ -1107,6 +1126,7 @@ __device__ __forceinline__ void sweep_bytes_tile(const SweepArgs &a, const int4 
         rd = nd;
         nd = n2;
     };
+    prio_turn(0);
     for (int s = 0; s < a.S; ++s) {
         for (int rho = 0; rho < nrounds;) {
             const int cnt = min(a.flush_every, nrounds - rho);
@@ -1175,7 +1195,7 @@ __device__ __forceinline__ void sweep_bytes_tile(const SweepArgs &a, const int4 
     }
 }
 
-template <int W, int SG, bool DIRECT>
+template <int W, int SG, bool DIRECT, bool PRIO>
 __global__ __launch_bounds__(1024) void sweep_bytes_kernel(SweepArgs a, const int4 *__restrict__ rounds,
                                                           const uint4 *__restrict__ blocks)
 {
@@ -1191,7 +1211,7 @@ __global__ __launch_bounds__(1024) void sweep_bytes_kernel(SweepArgs a, const in
         const int x = b & 7, q = nb >> 3, rem = nb & 7;
         return x * q + (x < rem ? x : rem) + (b >> 3);
     }();
-    sweep_bytes_tile<W, SG, DIRECT>(a, rounds, blocks, blk, nb);
+    sweep_bytes_tile<W, SG, DIRECT>(a, rounds, blocks, blk, nb, PRIO);
 }
 
 // One step of many runs in one launch: workgroup b takes the tile work[b] =
@@ -1217,7 +1237,7 @@ __global__ __launch_bounds__(1024) void sweep_bytes_multi_kernel(const MultiRun 
     a.Ein = even ? m.E0 : m.E1;
     a.E = even ? m.E1 : m.E0;
     a.parent = k == 0 ? nullptr : m.epi.parent;
-    sweep_bytes_tile<W, SG, DIRECT>(a, a.rounds, a.blocks, wk.y, m.nblk);
+    sweep_bytes_tile<W, SG, DIRECT>(a, a.rounds, a.blocks, wk.y, m.nblk, false);
 }
 
 // ---------------------------------------------------------------------------
@@ -2060,12 +2080,19 @@ template <int W, int SG, bool D>
 static int launch_bytes_t(int threads, int nblk, const SweepArgs &a, void *stream)
 {
     const int lds = sweep_bytes_lds(W, SG == 1 ? 1 : 0, a.n, a.dmax);
-    static int configured[kMaxDevices] = {};
-    if (allow_lds(reinterpret_cast<const void *>(&sweep_bytes_kernel<W, SG, D>), configured, lds,
-                  "hipFuncSetAttribute(sweep_bytes)"))
-        return -1;
-    hipLaunchKernelGGL((sweep_bytes_kernel<W, SG, D>), dim3(nblk), dim3(threads), lds,
-                       (hipStream_t)stream, a, a.rounds, a.blocks);
+    // The issue-priority turns are compiled only into 8-replica tiles.
+    constexpr bool kHasPrio = W == 8;
+    const bool prio = kHasPrio && a.prio_mode == 1;
+    const void *fn = prio ? reinterpret_cast<const void *>(&sweep_bytes_kernel<W, SG, D, kHasPrio>)
+                          : reinterpret_cast<const void *>(&sweep_bytes_kernel<W, SG, D, false>);
+    static int configured[kMaxDevices] = {}, configured_p[kMaxDevices] = {};
+    if (allow_lds(fn, prio ? configured_p : configured, lds, "hipFuncSetAttribute(sweep_bytes)")) return -1;
+    if (prio)
+        hipLaunchKernelGGL((sweep_bytes_kernel<W, SG, D, kHasPrio>), dim3(nblk), dim3(threads), lds,
+                           (hipStream_t)stream, a, a.rounds, a.blocks);
+    else
+        hipLaunchKernelGGL((sweep_bytes_kernel<W, SG, D, false>), dim3(nblk), dim3(threads), lds,
+                           (hipStream_t)stream, a, a.rounds, a.blocks);
     return check("sweep_bytes_kernel");
 }
 

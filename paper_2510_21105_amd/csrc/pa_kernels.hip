@@ -36,7 +36,9 @@ namespace pa {
 // ---------------------------------------------------------------------------
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two
 // 32x32->64 products with multipliers 0xD2511F53 / 0xCD9E8D57 and a Weyl key
-// schedule 0x9E3779B9 / 0xBB67AE85.
+// schedule 0x9E3779B9 / 0xBB67AE85. Each product is one 64-bit multiply (a
+// single v_mad_u64_u32 gives both halves) and the two XORs of an output word
+// are one 3-input bit operation (0x96 = a ^ b ^ c).
 // ---------------------------------------------------------------------------
 struct U4 {
     uint32_t x, y, z, w;
@@ -46,11 +48,12 @@ __device__ __forceinline__ U4 philox10(U4 c, uint32_t k0, uint32_t k1)
 {
 #pragma unroll
     for (int round = 0; round < 10; ++round) {
-        const uint32_t lo0 = 0xD2511F53u * c.x;
-        const uint32_t hi0 = __umulhi(0xD2511F53u, c.x);
-        const uint32_t lo1 = 0xCD9E8D57u * c.z;
-        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c.z);
-        c = U4{hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0};
+        const uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c.x;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c.z;
+        c = U4{(uint32_t)__builtin_amdgcn_bitop3_b32((uint32_t)(p1 >> 32), c.y, k0, 0x96),
+               (uint32_t)p1,
+               (uint32_t)__builtin_amdgcn_bitop3_b32((uint32_t)(p0 >> 32), c.w, k1, 0x96),
+               (uint32_t)p0};
         k0 += 0x9E3779B9u;
         k1 += 0xBB67AE85u;
     }
@@ -242,25 +245,6 @@ __device__ __forceinline__ uint64_t field_of(uint64_t v, int sub)
 
 constexpr int kRegCols = 28;   // neighbour entries held in registers (128-byte block head)
 
-// Philox4x32-10 written with 64-bit products (one v_mad_u64_u32 gives hi and
-// lo at once) and the two XORs of each output word as one 3-input bit
-// operation (0x96 = a ^ b ^ c).
-__device__ __forceinline__ U4 philox10_wide(U4 c, uint32_t k0, uint32_t k1)
-{
-#pragma unroll
-    for (int round = 0; round < 10; ++round) {
-        const uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c.x;
-        const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c.z;
-        c = U4{(uint32_t)__builtin_amdgcn_bitop3_b32((uint32_t)(p1 >> 32), c.y, k0, 0x96),
-               (uint32_t)p1,
-               (uint32_t)__builtin_amdgcn_bitop3_b32((uint32_t)(p0 >> 32), c.w, k1, 0x96),
-               (uint32_t)p0};
-        k0 += 0x9E3779B9u;
-        k1 += 0xBB67AE85u;
-    }
-    return c;
-}
-
 template <int W, bool SIGNED>
 __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs a, const int2 *__restrict__ stream_all,
                                                     const int *__restrict__ level_off,
@@ -371,7 +355,7 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs a, const int2 *__
                     const int2 e = stream[q + fill_pass];
                     const int t2 = e.x + fill_slot;
                     const uint32_t i2 = (e.x >= 0 && t2 < n) ? (uint32_t)sched16[t2] : 0u;
-                    const U4 o = philox10_wide(U4{i2, (uint32_t)s, k, rgrp}, a.seed_lo, a.seed_hi);
+                    const U4 o = philox10(U4{i2, (uint32_t)s, k, rgrp}, a.seed_lo, a.seed_hi);
                     *reinterpret_cast<uint4 *>(dbuf + 4 * lane) = make_uint4(o.x, o.y, o.z, o.w);
                     __builtin_amdgcn_wave_barrier();
                 }
@@ -955,7 +939,7 @@ __device__ __forceinline__ void sweep_bytes_tile(const SweepArgs &a, const int4 
             uint32_t dr[NR][4];
 #pragma unroll
             for (int q = 0; q < NR; ++q) {
-                const U4 o = philox10_wide(U4{node, (uint32_t)s, k, rgrp0 + (uint32_t)q}, a.seed_lo,
+                const U4 o = philox10(U4{node, (uint32_t)s, k, rgrp0 + (uint32_t)q}, a.seed_lo,
                                            a.seed_hi);
                 dr[q][0] = o.x; dr[q][1] = o.y; dr[q][2] = o.z; dr[q][3] = o.w;
                 asm volatile("" ::"v"(dr[q][0]), "v"(dr[q][1]), "v"(dr[q][2]), "v"(dr[q][3]));
@@ -1908,8 +1892,12 @@ __global__ __launch_bounds__(kIcmThreads) void wolff_kernel(IcmArgs a)
 #pragma unroll
             for (int v = 1; v < 8; ++v) e = u == v ? ev[v] : e;
             const uint32_t i = e & 0x7FFFu, j = (e >> 15) & 0x7FFFu;
+            // A bond whose ends are already joined cannot change the
+            // components: its draw is skipped.
+            const uint32_t x = uf_find(P, i), y = uf_find(P, j);
+            if (x == y) continue;
             const uint32_t d = draw(a.seed_lo, a.seed_hi, a.inst, 5, j, (uint32_t)a.k, i, (uint32_t)r);
-            if ((uint64_t)d < q) uf_unite(P, i, j);
+            if ((uint64_t)d < q) uf_unite(P, x, y);
         }
     }
     __syncthreads();

@@ -1442,8 +1442,14 @@ __device__ __forceinline__ void epilogue_body(const EpiArgs &a)
                     wv[c] = nn < len ? a.wtab[off + nn] : 0ull;
                 }
             };
+            // The first chunk's weights stay in registers for the walk below
+            // (with R <= 8 x threads it is the thread's only chunk).
+            uint64_t w0[CH];
+            weights(lo, w0);
             uint64_t ws = 0;
-            for (int r0 = lo; r0 < hi; r0 += CH) {
+#pragma unroll
+            for (int c = 0; c < CH; ++c) ws += w0[c];
+            for (int r0 = lo + CH; r0 < hi; r0 += CH) {
                 uint64_t wv[CH];
                 weights(r0, wv);
 #pragma unroll
@@ -1477,7 +1483,12 @@ __device__ __forceinline__ void epilogue_body(const EpiArgs &a)
             long long parents = 0;
             for (int r0 = lo; r0 < hi; r0 += CH) {
                 uint64_t wv[CH];
-                weights(r0, wv);
+                if (r0 == lo) {
+#pragma unroll
+                    for (int c = 0; c < CH; ++c) wv[c] = w0[c];
+                } else {
+                    weights(r0, wv);
+                }
 #pragma unroll
                 for (int c = 0; c < CH; ++c) {
                     const int r = r0 + c;

@@ -1614,13 +1614,38 @@ __device__ __forceinline__ uint32_t uf_find(lds_vu32 *P, uint32_t x)
     }
 }
 
+// Roots of x and y, both paths walked together (one round trip serves a
+// step of each), with path halving on both.
+__device__ __forceinline__ void uf_find2(lds_vu32 *P, uint32_t &x, uint32_t &y)
+{
+    for (;;) {
+        const uint32_t px = P[x], py = P[y];
+        if (px >= x && py >= y) return;
+        const uint32_t ppx = P[px], ppy = P[py];
+        if (ppx != px) P[x] = ppx;
+        if (ppy != py) P[y] = ppy;
+        x = ppx;
+        y = ppy;
+    }
+}
+
+// Bitmap words of nodes base .. base + blockDim.x - 1 from one flag per
+// thread (lanes 0 and 32 of each wave write its two words).
+__device__ __forceinline__ void label_words(uint32_t *V, int nw, int base, bool in)
+{
+    const int tid = threadIdx.x, lane = tid & 63;
+    const unsigned long long m = __ballot(in);
+    const int w0 = (base + (tid & ~63)) >> 5;
+    if (lane == 0 && w0 < nw) V[w0] = (uint32_t)m;
+    if (lane == 32 && w0 + 1 < nw) V[w0 + 1] = (uint32_t)(m >> 32);
+}
+
 // Merge the sets of x and y (lock-free: a failed hook means another lane
 // hooked that root, which happens at most once per root).
 __device__ __forceinline__ void uf_unite(lds_vu32 *P, uint32_t x, uint32_t y)
 {
     for (;;) {
-        x = uf_find(P, x);
-        y = uf_find(P, y);
+        uf_find2(P, x, y);
         if (x == y) return;
         if (x > y) {
             const uint32_t t = x;
@@ -1771,14 +1796,15 @@ __global__ __launch_bounds__(kIcmThreads) void icm_kernel(IcmArgs a)
     }
     __syncthreads();
     const uint32_t root = root_s;
-    // Cluster = the seed's component.
-    for (int base = 0; base < nw * 32; base += nt) {
-        const int i = base + tid;
-        const bool in = i < n && inD((uint32_t)i) && uf_find(P, (uint32_t)i) == root;
-        const unsigned long long m = __ballot(in);
-        const int w0 = (base + (tid & ~63)) >> 5;
-        if (lane == 0 && w0 < nw) V[w0] = (uint32_t)m;
-        if (lane == 32 && w0 + 1 < nw) V[w0 + 1] = (uint32_t)(m >> 32);
+    // Cluster = the seed's component: two nodes per thread and pass, their
+    // roots walked together (nodes outside D start at the root itself).
+    for (int base = 0; base < nw * 32; base += 2 * nt) {
+        const int i0 = base + tid, i1 = i0 + nt;
+        const bool c0 = i0 < n && inD((uint32_t)i0), c1 = i1 < n && inD((uint32_t)i1);
+        uint32_t x = c0 ? (uint32_t)i0 : root, y = c1 ? (uint32_t)i1 : root;
+        uf_find2(P, x, y);
+        label_words(V, nw, base, c0 && x == root);
+        label_words(V, nw, base + nt, c1 && y == root);
     }
     __syncthreads();
     // Energy change of replica a: the edges with one end in the cluster
@@ -1905,7 +1931,8 @@ __global__ __launch_bounds__(kIcmThreads) void wolff_kernel(IcmArgs a)
             const uint32_t i = e & 0x7FFFu, j = (e >> 15) & 0x7FFFu;
             // A bond whose ends are already joined cannot change the
             // components: its draw is skipped.
-            const uint32_t x = uf_find(P, i), y = uf_find(P, j);
+            uint32_t x = i, y = j;
+            uf_find2(P, x, y);
             if (x == y) continue;
             const uint32_t d = draw(a.seed_lo, a.seed_hi, a.inst, 5, j, (uint32_t)a.k, i, (uint32_t)r);
             if ((uint64_t)d < q) uf_unite(P, x, y);
@@ -1918,13 +1945,12 @@ __global__ __launch_bounds__(kIcmThreads) void wolff_kernel(IcmArgs a)
     }
     __syncthreads();
     const uint32_t root = root_s;
-    for (int base = 0; base < nw * 32; base += nt) {
-        const int i = base + tid;
-        const bool in = i < n && uf_find(P, (uint32_t)i) == root;
-        const unsigned long long m = __ballot(in);
-        const int w0 = (base + (tid & ~63)) >> 5;
-        if (lane == 0 && w0 < nw) V[w0] = (uint32_t)m;
-        if (lane == 32 && w0 + 1 < nw) V[w0 + 1] = (uint32_t)(m >> 32);
+    for (int base = 0; base < nw * 32; base += 2 * nt) {
+        const int i0 = base + tid, i1 = i0 + nt;
+        uint32_t x = i0 < n ? (uint32_t)i0 : root, y = i1 < n ? (uint32_t)i1 : root;
+        uf_find2(P, x, y);
+        label_words(V, nw, base, i0 < n && x == root);
+        label_words(V, nw, base + nt, i1 < n && y == root);
     }
     __syncthreads();
     // Energy change: each edge with one end in the cluster changes sign.

@@ -1592,9 +1592,6 @@ __global__ __launch_bounds__(256) void gather_kernel(GatherArgs a)
 // flips the clusters of all pairs in the population words.
 // ---------------------------------------------------------------------------
 
-// Root of x with path halving. Roots are only ever hooked under smaller
-// roots and halving links x to an ancestor, so P[x] <= x always holds and
-// every step strictly decreases x: the walk ends within n steps.
 typedef volatile __attribute__((address_space(3))) uint32_t lds_vu32;
 
 // LDS compare-and-swap on an LDS-typed pointer (a generic pointer would become a FLAT atomic).
@@ -1603,6 +1600,9 @@ __device__ __forceinline__ bool lds_cas(lds_vu32 *p, uint32_t expected, uint32_t
     return __atomic_compare_exchange_n(p, &expected, desired, false, __ATOMIC_RELAXED, __ATOMIC_RELAXED);
 }
 
+// Root of x with path halving. Roots are only ever hooked under smaller
+// roots and halving links x to an ancestor, so P[x] <= x always holds and
+// every step strictly decreases x: the walk ends within n steps.
 __device__ __forceinline__ uint32_t uf_find(lds_vu32 *P, uint32_t x)
 {
     for (;;) {
@@ -1614,8 +1614,10 @@ __device__ __forceinline__ uint32_t uf_find(lds_vu32 *P, uint32_t x)
     }
 }
 
-// Roots of x and y, both paths walked together (one round trip serves a
-// step of each), with path halving on both.
+// Roots of x and y, both paths walked together (one LDS round trip serves a
+// step of each), with path halving on both; a walk already at its root
+// stays there (its reads return the root itself), and every pass moves the
+// other one strictly down, so this ends as uf_find does.
 __device__ __forceinline__ void uf_find2(lds_vu32 *P, uint32_t &x, uint32_t &y)
 {
     for (;;) {

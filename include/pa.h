@@ -440,9 +440,12 @@ pa_status pa_best_config(pa_solver *s, int8_t *x);
  * zero-padded to a multiple of 4 variables. Needs len >= ceil(n/4) + 1. */
 pa_status pa_best_config_hex(pa_solver *s, char *buf, size_t len);
 
-/* Final population of the last run: x (R*n int8, replica-major, +-1) and
- * E (R int32). Either pointer may be NULL. Synchronises the stream. */
-pa_status pa_get_population(pa_solver *s, int8_t *x, int32_t *E);
+/* Final population of the last run: x (R*n int8, replica-major, +-1), the
+ * local fields h (R*n int16, replica-major: h_i = sum_j w_ij x_j, so that
+ * E = (1/2) sum_i x_i h_i, eq. (1) up to the constant W_tot) and E (R int32).
+ * The device keeps no fields: h is computed on the host from x. Any pointer
+ * may be NULL. Synchronises the stream. */
+pa_status pa_get_population(pa_solver *s, int8_t *x, int16_t *h, int32_t *E);
 
 /* Initial population (R*n int8); needs schedule.record bit 1. */
 pa_status pa_get_initial_population(pa_solver *s, int8_t *x);

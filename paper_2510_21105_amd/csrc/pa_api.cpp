@@ -1413,10 +1413,11 @@ static void unpack_population(const std::vector<uint64_t> &X, int n, int R, int8
     }
 }
 
-extern "C" pa_status pa_get_population(pa_solver *s, int8_t *x, int32_t *E)
+extern "C" pa_status pa_get_population(pa_solver *s, int8_t *x, int16_t *h, int32_t *E)
 {
     if (!s || !s->has_run) return fail(PA_ESTATE, "no completed pa_run on this solver");
     const Plan &P = s->plan;
+    const int n = s->n;
     // After a range that stopped before the last step, kernel 1 still holds
     // the population of the next step as the current buffer read through the
     // resampling parents: apply them here.
@@ -1426,17 +1427,40 @@ extern "C" pa_status pa_get_population(pa_solver *s, int8_t *x, int32_t *E)
         pa_status st = fetch(s, parent.data(), P.L.parent, sizeof(int) * P.R);
         if (st != PA_OK) return st;
     }
-    if (x) {
-        std::vector<uint64_t> X((size_t)P.G * s->n);
+    if (x || h) {
+        std::vector<uint64_t> X((size_t)P.G * n);
         pa_status st = fetch(s, X.data(), s->final_x, sizeof(uint64_t) * X.size());
         if (st != PA_OK) return st;
+        std::vector<int8_t> own;
+        int8_t *xs = x;
+        if (!xs) {
+            own.resize((size_t)P.R * n);
+            xs = own.data();
+        }
         if (parent.empty()) {
-            unpack_population(X, s->n, P.R, x);
+            unpack_population(X, n, P.R, xs);
         } else {
-            std::vector<int8_t> all((size_t)P.R * s->n);
-            unpack_population(X, s->n, P.R, all.data());
+            std::vector<int8_t> all((size_t)P.R * n);
+            unpack_population(X, n, P.R, all.data());
             for (int r = 0; r < P.R; ++r)
-                std::memcpy(x + (size_t)r * s->n, all.data() + (size_t)parent[r] * s->n, (size_t)s->n);
+                std::memcpy(xs + (size_t)r * n, all.data() + (size_t)parent[r] * n, (size_t)n);
+        }
+        if (h) {
+            // The device keeps no fields: h_i = sum_j w_ij x_j from the spins
+            // (the positive neighbours of a row come first).
+            parallel_rows(P.R, (long long)P.R * s->nnz, [&](int r0, int r1) {
+                for (int r = r0; r < r1; ++r) {
+                    const int8_t *xr = xs + (size_t)r * n;
+                    int16_t *hr = h + (size_t)r * n;
+                    for (int i = 0; i < n; ++i) {
+                        const int e0 = s->row_ptr[i], e1 = s->row_ptr[i + 1], em = e0 + s->npos[i];
+                        int acc = 0;
+                        for (int e = e0; e < em; ++e) acc += xr[s->col[e]];
+                        for (int e = em; e < e1; ++e) acc -= xr[s->col[e]];
+                        hr[i] = (int16_t)acc;
+                    }
+                }
+            });
         }
     }
     if (E) {

@@ -130,7 +130,7 @@ def lib():
             "pa_best_info": [P, P],
             "pa_best_config": [P, P],
             "pa_best_config_hex": [P, ctypes.c_char_p, ctypes.c_size_t],
-            "pa_get_population": [P, P, P],
+            "pa_get_population": [P, P, P, P],
             "pa_get_initial_population": [P, P],
             "pa_get_step_stats": [P, P],
             "pa_get_counts": [P, P],
@@ -374,11 +374,14 @@ class Solver:
         _check(lib().pa_best_config_hex(self._h, buf, len(buf)))
         return buf.value.decode()
 
-    def population(self):
+    def population(self, fields: bool = False):
+        """Final population ``(x, E)``, or ``(x, h, E)`` with the local
+        fields h_i = sum_j w_ij x_j when ``fields`` is set."""
         x = np.zeros((self._R, self.n), dtype=np.int8)
         E = np.zeros(self._R, dtype=np.int32)
-        _check(lib().pa_get_population(self._h, _p(x), _p(E)))
-        return x, E
+        h = np.zeros((self._R, self.n), dtype=np.int16) if fields else None
+        _check(lib().pa_get_population(self._h, _p(x), _p(h), _p(E)))
+        return (x, h, E) if fields else (x, E)
 
     def initial_population(self):
         x = np.zeros((self._R, self.n), dtype=np.int8)

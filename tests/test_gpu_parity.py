@@ -776,6 +776,33 @@ def test_repeated_runs_are_identical(pa):
     assert not np.array_equal(s.population()[1], a_E)
 
 
+@pytest.mark.parametrize("graph", ["small800", "torus20"])
+def test_population_fields_are_the_local_fields_of_the_spins(pa, graph):
+    """pa_get_population's h: h_i = sum_j w_ij x_j of the returned spins and
+    E = (1/2) sum_i x_i h_i for every replica (eq. (1) up to W_tot), also
+    for a range of steps that stops while the next population is still read
+    through the resampling parents; x and E equal the two-output call. The
+    torus has weights of both signs."""
+    from scipy import sparse
+    wl = dict(W.workload("small800"), R=192, betas=W.workload("small800")["betas"][:6])
+    if graph == "torus20":
+        wl = dict(wl, graph=W.torus(20, 9, True, "torus20"), order=W.checkerboard_order(20))
+    g = wl["graph"]
+    assert graph != "torus20" or (np.asarray(g.w) < 0).any()
+    A = sparse.csr_matrix((np.asarray(g.w, dtype=np.int32), np.asarray(g.col), np.asarray(g.row_ptr)),
+                          shape=(g.n, g.n))
+    s = pa.Solver(g)
+    p = pa.params_from_workload(wl)
+    for k_end in (3, 6):
+        s.run_steps(p, 0, k_end)
+        x, h, E = s.population(fields=True)
+        x2, E2 = s.population()
+        assert np.array_equal(x, x2) and np.array_equal(E, E2)
+        want = (A @ x.T.astype(np.int32)).T
+        assert np.array_equal(h.astype(np.int32), want), f"fields differ after {k_end} steps"
+        assert np.array_equal((x.astype(np.int64) * h).sum(axis=1), 2 * E.astype(np.int64))
+
+
 def test_gset_file_command_line_solve(pa, tmp_path):
     """A G-set file through the command-line solve: its best cut and hex
     configuration equal the oracle's run of the same schedule, and the hex

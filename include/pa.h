@@ -104,6 +104,13 @@ typedef struct {
                                  it has.                                          */
     int32_t adapt_jump;       /* 1..64, largest jump in grid points (beta_adapt = 1)  */
     int32_t adapt_num, adapt_den; /* target, 0 <= adapt_num <= adapt_den <= 65536, den >= 1 */
+    int32_t field_bits;       /* 0 = no check; 8 or 16: refuse the run with PA_ERANGE
+                                 unless every local field h_i = sum_j w_ij x_j (|h_i| is
+                                 at most the degree of i) fits a signed integer of that
+                                 many bits, for a caller that keeps fields (such as
+                                 those of pa_get_population) in that width; other
+                                 values give PA_EINVAL. The device keeps no fields, so
+                                 this is a check only: results never depend on it. */
 } pa_schedule;
 
 /* Text of the last error on this thread ("" if none). */

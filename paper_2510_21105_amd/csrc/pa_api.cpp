@@ -191,6 +191,10 @@ pa_status pa_host::check_schedule(const pa_solver *s, const pa_schedule *sch, in
         if (!(sch->as_gamma > 0.0 && sch->as_gamma <= 1.0)) return fail(PA_EINVAL, "as_gamma outside (0, 1]");
     }
     if (sch->nl_period < 0) return fail(PA_EINVAL, "nl_period must be >= 0");
+    if (sch->field_bits != 0 && sch->field_bits != 8 && sch->field_bits != 16)
+        return fail(PA_EINVAL, "field_bits=%d is not 0, 8 or 16", sch->field_bits);
+    if (sch->field_bits == 8 && s->dmax > 127)
+        return fail(PA_ERANGE, "a local field reaches the maximum degree %d, beyond 8-bit fields", s->dmax);
     if (R < 1 || R > kMaxR) return fail(PA_ERANGE, "R=%d outside [1, %d]", R, kMaxR);
     if (sch->nl_kind != 0 && sch->nl_kind != 1) return fail(PA_EINVAL, "nl_kind must be 0 or 1");
     if (sch->beta_adapt != 0 && sch->beta_adapt != 1) return fail(PA_EINVAL, "beta_adapt must be 0 or 1");

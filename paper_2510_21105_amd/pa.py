@@ -62,6 +62,7 @@ class Schedule(ctypes.Structure):
         ("adapt_jump", ctypes.c_int32),
         ("adapt_num", ctypes.c_int32),
         ("adapt_den", ctypes.c_int32),
+        ("field_bits", ctypes.c_int32),
     ]
 
 
@@ -184,6 +185,7 @@ class RunParams:
     adapt_jump: int = 8
     adapt_num: int = 1
     adapt_den: int = 2
+    field_bits: int = 0           # 8 or 16: refuse graphs whose local fields do not fit
 
 
 def _params_key(p: RunParams):
@@ -258,6 +260,7 @@ class Solver:
         sch.adapt_jump = p.adapt_jump
         sch.adapt_num = p.adapt_num
         sch.adapt_den = p.adapt_den
+        sch.field_bits = p.field_bits
         return sch, (betas, order)
 
     def workspace_bytes(self, p: RunParams) -> int:
@@ -618,7 +621,8 @@ def params_from_workload(wl: dict, **over) -> RunParams:
                      tile_replicas=d.get("tile_replicas", 0), wg_threads=d.get("wg_threads", 0),
                      record=d.get("record", 0), nl_kind=d.get("nl_kind", 0),
                      beta_adapt=d.get("beta_adapt", 0), adapt_jump=d.get("adapt_jump", 8),
-                     adapt_num=d.get("adapt_num", 1), adapt_den=d.get("adapt_den", 2))
+                     adapt_num=d.get("adapt_num", 1), adapt_den=d.get("adapt_den", 2),
+                     field_bits=d.get("field_bits", 0))
 
 
 def next_step(blob: bytes) -> int:

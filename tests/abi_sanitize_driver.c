@@ -93,6 +93,11 @@ int main(void)
         b.n_steps = 2;
         expect(pa_workspace_bytes(s, &b, 32, &bytes), PA_EINVAL, "decreasing beta");
         b = sch;
+        b.field_bits = 12;
+        expect(pa_workspace_bytes(s, &b, 32, &bytes), PA_EINVAL, "field_bits 12");
+        b.field_bits = 8;
+        expect(pa_workspace_bytes(s, &b, 32, &bytes), PA_OK, "field_bits 8");
+        b = sch;
         b.beta_adapt = 1;
         double geo[20];
         for (int k = 0; k < 20; ++k) geo[k] = 0.1 * (1 << (k / 4));

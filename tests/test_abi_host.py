@@ -178,6 +178,8 @@ def test_workspace_grows_with_population():
     (dict(beta_adapt=1, adapt_num=0, adapt_den=0), pa.PA_EINVAL),
     (dict(beta_adapt=1, adapt_num=1, adapt_den=70000), pa.PA_EINVAL),
     (dict(nl_kind=-1), pa.PA_EINVAL),
+    (dict(field_bits=12), pa.PA_EINVAL),
+    (dict(field_bits=-8), pa.PA_EINVAL),
 ])
 def test_schedule_validation(bad, status):
     wl = W.workload("small800")
@@ -185,6 +187,26 @@ def test_schedule_validation(bad, status):
     with pytest.raises(pa.PAError) as e:
         _bytes(s, pa.params_from_workload(wl, **bad))
     assert e.value.status == status
+
+
+def test_field_bits_checks_that_local_fields_fit():
+    """field_bits 8 refuses a graph whose degree (the largest |h_i|) exceeds
+    127 and accepts one up to 127; 16 accepts both (degree <= 4096); 0 checks
+    nothing."""
+    wl = W.workload("small800")
+    small = pa.Solver(wl["graph"])
+    assert small.info()["dmax"] <= 127
+    for fb in (0, 8, 16):
+        assert _bytes(small, pa.params_from_workload(wl, field_bits=fb)) > 0
+    star = W.from_edges(200, np.zeros(199, dtype=np.int64), np.arange(1, 200), name="star200")
+    big = pa.Solver(star)
+    p = dict(wl, graph=star, order=W.natural_order(200))
+    assert big.info()["dmax"] == 199
+    for fb in (0, 16):
+        assert _bytes(big, pa.params_from_workload(p, field_bits=fb)) > 0
+    with pytest.raises(pa.PAError) as e:
+        _bytes(big, pa.params_from_workload(p, field_bits=8))
+    assert e.value.status == pa.PA_ERANGE
 
 
 def test_adaptive_steps_need_an_evenly_spaced_grid():

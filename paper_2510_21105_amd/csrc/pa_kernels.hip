@@ -939,8 +939,7 @@ __device__ __forceinline__ void sweep_bytes_tile(const SweepArgs &a, const int4 
             uint32_t dr[NR][4];
 #pragma unroll
             for (int q = 0; q < NR; ++q) {
-                const U4 o = philox10(U4{node, (uint32_t)s, k, rgrp0 + (uint32_t)q}, a.seed_lo,
-                                           a.seed_hi);
+                const U4 o = philox10(U4{node, (uint32_t)s, k, rgrp0 + (uint32_t)q}, a.seed_lo, a.seed_hi);
                 dr[q][0] = o.x; dr[q][1] = o.y; dr[q][2] = o.z; dr[q][3] = o.w;
                 asm volatile("" ::"v"(dr[q][0]), "v"(dr[q][1]), "v"(dr[q][2]), "v"(dr[q][3]));
             }

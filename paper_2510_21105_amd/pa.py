@@ -289,16 +289,21 @@ class Solver:
         avail = workspace.numel() - (aligned - base)
         return sch, keep, workspace, aligned, avail
 
-    def _started(self, p: RunParams, sch, keep, workspace):
+    def _started(self, p: RunParams, sch, keep, workspace, stream=None):
+        # The workspace may be dropped (replaced by a larger one) while the run
+        # still executes on its stream: the allocator must not hand the memory
+        # out again before that stream's queued work is done.
+        if workspace is not None and stream is not None:
+            workspace.record_stream(stream)
         self._keep = (keep, workspace, sch)
         self._R = p.R
         self._K = int(sch.n_steps)
 
-    def _enqueued(self, st: int, p: RunParams, sch, keep, workspace):
+    def _enqueued(self, st: int, p: RunParams, sch, keep, workspace, stream=None):
         """Record the run a call started; a run stopped by the fault hook
         (PA_EABORTED) still holds its workspace and can continue."""
         if st in (PA_OK, PA_EABORTED):
-            self._started(p, sch, keep, workspace)
+            self._started(p, sch, keep, workspace, stream)
         _check(st)
         return self
 
@@ -309,7 +314,7 @@ class Solver:
         st = torch.cuda.current_stream() if stream is None else stream
         return self._enqueued(lib().pa_run(self._h, ctypes.byref(sch), p.R, p.seed, p.inst,
                                            ctypes.c_void_p(aligned), avail, ctypes.c_void_p(st.cuda_stream)),
-                              p, sch, keep, workspace)
+                              p, sch, keep, workspace, st)
 
     def run_static(self, p: RunParams, stream=None):
         """Enqueue a run inside the library's static device workspace
@@ -333,7 +338,7 @@ class Solver:
         return self._enqueued(lib().pa_run_steps(self._h, ctypes.byref(sch), p.R, p.seed, p.inst, k_begin,
                                                  k_end, ctypes.c_void_p(aligned), avail,
                                                  ctypes.c_void_p(st.cuda_stream)),
-                              p, sch, keep, workspace)
+                              p, sch, keep, workspace, st)
 
     def checkpoint(self) -> bytes:
         """The run's state between steps as bytes (synchronises its stream)."""
@@ -352,7 +357,7 @@ class Solver:
         _check(lib().pa_checkpoint_load(self._h, ctypes.byref(sch), p.R, p.seed, p.inst, blob,
                                         len(blob), ctypes.c_void_p(aligned), avail,
                                         ctypes.c_void_p(st.cuda_stream)))
-        self._started(p, sch, keep, workspace)
+        self._started(p, sch, keep, workspace, st)
         return self
 
     # ---- results (each synchronises the run's stream) ----
@@ -457,8 +462,8 @@ def run_batch(solvers, params, streams):
     hs = (ctypes.c_void_p * len(streams))(*[st.cuda_stream for st in streams])
     st = lib().pa_run_batch(runs, len(solvers), hs, len(streams))
     # Keep every workspace alive: runs before a failing one stay enqueued.
-    for s, p, sch, keep, workspace in held:
-        s._started(p, sch, keep, workspace)
+    for i, (s, p, sch, keep, workspace) in enumerate(held):
+        s._started(p, sch, keep, workspace, streams[i % len(streams)])
     _check(st)
     return solvers
 
@@ -513,6 +518,7 @@ class FusedBatch:
         st = torch.cuda.current_stream() if stream is None else stream
         _check(lib().pa_fused_tune(self._h, ctypes.c_void_p(ws), n, ctypes.c_void_p(st.cuda_stream),
                                    probe_steps))
+        self._workspace.record_stream(st)
         return self.info()
 
     def set_graph(self, on: bool):
@@ -524,7 +530,7 @@ class FusedBatch:
         st = torch.cuda.current_stream() if stream is None else stream
         _check(lib().pa_fused_run(self._h, ctypes.c_void_p(ws), n, ctypes.c_void_p(st.cuda_stream)))
         for s, p, (sch, keep) in zip(self.solvers, self.params, self._keep):
-            s._started(p, sch, keep, self._workspace)
+            s._started(p, sch, keep, self._workspace, st)
         return self
 
     def info(self):
